@@ -1,0 +1,659 @@
+/* FP64 CPU oracle of the barrel Kalman-filter track builder and fitter.
+ *
+ * TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
+ * benchmark's CPU-baseline leg call it; the GPU library never does, and the
+ * two share no code.  Plain scalar double, generic small-matrix loops, brute
+ * force over every hit of a layer, no blocking or fusion: written to be read
+ * against the method, not to be fast.
+ *
+ * What it follows (Cerati et al., "Kalman filter tracking on parallel
+ * architectures"):
+ *  - Section 2: three stages; building projects each candidate outward layer
+ *    by layer, collects compatible hits with the KF and branches to several
+ *    candidates per seed; fitting repeats the KF over a fixed hit set.
+ *  - Section 2.2: ideal barrel, uniform longitudinal field, hybrid state
+ *    (global Cartesian position, polar momentum), KF update on the plane
+ *    tangent to the hit radius.
+ *  - Section 3.2.1: a variable number of hit candidates per layer, so the
+ *    beam is re-ranked and pruned after every layer.
+ * Where the paper gives no formula, the readings used are: helix in a uniform
+ * field with signed q/pT; Highland multiple scattering added when leaving a
+ * layer; 2-D (r*phi, z) measurement; strict chi2 < cut; hole child only when
+ * no hit was accepted; beam order (n_hits desc, chi2 asc, parent rank asc,
+ * hit index asc, hole last); hits must lie in the forward half-space of the
+ * predicted point.
+ */
+#include "mkf_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdatomic.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KAPPA 0.00299792458   /* GeV / (T cm) */
+#define HOLE_ID 0x7fffffff
+
+static const double PI = 3.14159265358979323846;
+
+/* ---------------------------------------------------------------- helpers */
+
+static double wrap_angle(double a)
+{
+    while (a > PI) a -= 2.0 * PI;
+    while (a <= -PI) a += 2.0 * PI;
+    return a;
+}
+
+static void unpack21(const double *p, double C[36])
+{
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            C[i * 6 + j] = p[k];
+            C[j * 6 + i] = p[k];
+            ++k;
+        }
+}
+
+static void pack21(const double C[36], double *p)
+{
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) p[k++] = C[i * 6 + j];
+}
+
+/* generic dense product: out[m x n] = A[m x k] B[k x n] */
+static void matmul(const double *A, const double *B, double *out, int m, int k, int n)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int t = 0; t < k; ++t) acc += A[i * k + t] * B[t * n + j];
+            out[i * n + j] = acc;
+        }
+}
+
+static void transpose(const double *A, double *out, int m, int n)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) out[j * m + i] = A[i * n + j];
+}
+
+static void symmetrize(double C[36])
+{
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j) {
+            double v = 0.5 * (C[i * 6 + j] + C[j * 6 + i]);
+            C[i * 6 + j] = v;
+            C[j * 6 + i] = v;
+        }
+}
+
+/* ------------------------------------------------------------ propagation */
+
+/* Helix in a uniform field B along z.  With w = -KAPPA*B*q/pT the momentum
+ * azimuth turns as phi(s) = phi + w*s over transverse path s, so
+ *   x(s) = x + s*A(a),  y(s) = y + s*B(a),  a = w*s,
+ *   A = (sin(phi+a) - sin phi)/a,  B = (cos phi - cos(phi+a))/a,
+ * and z(s) = z + s*cot(theta).  The small-|a| limits are taken by series. */
+static void sinc_terms(double a, double *S1, double *C1, double *S2, double *C2)
+{
+    if (fabs(a) < 1e-2) {
+        double a2 = a * a;
+        *S1 = 1.0 - a2 / 6.0 + a2 * a2 / 120.0;                   /* sin a / a        */
+        *C1 = a / 2.0 - a * a2 / 24.0 + a * a2 * a2 / 720.0;       /* (1 - cos a) / a  */
+        *S2 = -a / 3.0 + a * a2 / 30.0 - a * a2 * a2 / 840.0;      /* (a cos a - sin a)/a^2 */
+        *C2 = 0.5 - a2 / 8.0 + a2 * a2 / 144.0;                    /* (a sin a - 1 + cos a)/a^2 */
+    } else {
+        double sa = sin(a), ca = cos(a);
+        *S1 = sa / a;
+        *C1 = (1.0 - ca) / a;
+        *S2 = (a * ca - sa) / (a * a);
+        *C2 = (a * sa - 1.0 + ca) / (a * a);
+    }
+}
+
+int orc_propagate(const double p[6], double r, double bz, double out[6], double F[36],
+                  double *path, double *margin)
+{
+    const double x = p[0], y = p[1], z = p[2], qpt = p[3], phi = p[4], th = p[5];
+    const double w = -KAPPA * bz * qpt;
+    double s = -1.0, mrg;
+
+    /* Closed form for the path.  After turning by a = w s the chord from the
+     * start is (2/w) sin(d) along phi + d, with d = a/2.  Requiring the end
+     * point on the cylinder and writing T = tan(d)/w gives the quadratic
+     *   alpha T^2 + b T - D/4 = 0,
+     *   b = x cos phi + y sin phi,  e = -x sin phi + y cos phi,
+     *   D = r^2 - (x^2 + y^2),      alpha = 1 + w e - w^2 D / 4,
+     * whose w -> 0 limit is the straight line.  Each root gives d = atan(w T)
+     * or d + pi (the far half of the circle); the path is the smallest
+     * positive s = 2 d / w. */
+    const double b = x * cos(phi) + y * sin(phi);
+    const double e = -x * sin(phi) + y * cos(phi);
+    const double D = r * r - (x * x + y * y);
+    const double alpha = 1.0 + w * e - 0.25 * w * w * D;
+    const double disc = b * b + alpha * D;
+    if (fabs(w) * r > 1e-6) {
+        const double R = 1.0 / fabs(w);
+        const double cx = x - sin(phi) / w, cy = y + cos(phi) / w;
+        mrg = R + hypot(cx, cy) - r;        /* distance to outer tangency */
+    } else {
+        mrg = r - fabs(e);                  /* straight line: distance to tangency */
+    }
+    if (disc >= 0.0) {
+        const double q = sqrt(disc);
+        double roots[2];
+        int nr = 0;
+        if (b + q != 0.0) roots[nr++] = 0.5 * D / (b + q);
+        if (alpha != 0.0) roots[nr++] = -(b + q) / (2.0 * alpha);
+        for (int i = 0; i < nr; ++i) {
+            const double u = w * roots[i];
+            /* s = 2 atan(u) / w, evaluated as 2 T atan(u)/u near u = 0 */
+            double atanc = fabs(u) < 1e-4 ? 1.0 - u * u / 3.0 + u * u * u * u / 5.0 : atan(u) / u;
+            double cand[2];
+            int nc = 0;
+            cand[nc++] = 2.0 * roots[i] * atanc;
+            if (w != 0.0) cand[nc++] = 2.0 * (atan(u) + (w > 0.0 ? PI : -PI)) / w;
+            for (int c = 0; c < nc; ++c)
+                if (cand[c] > 1e-12 * r && (s < 0.0 || cand[c] < s)) s = cand[c];
+        }
+    }
+    if (margin) *margin = mrg;
+    if (!(s > 0.0)) return 1;
+
+    double a = w * s, S1, C1, S2, C2;
+    sinc_terms(a, &S1, &C1, &S2, &C2);
+    const double cph = cos(phi), sph = sin(phi);
+    const double A = cph * S1 - sph * C1;        /* (sin(phi+a) - sin phi)/a */
+    const double B = cph * C1 + sph * S1;        /* (cos phi - cos(phi+a))/a */
+    const double gx = cph * S2 - sph * C2;       /* d A / d a */
+    const double gy = sph * S2 + cph * C2;       /* d B / d a */
+    const double cot = cos(th) / sin(th);
+    const double nx = x + s * A, ny = y + s * B;
+    const double nphi = phi + a;
+
+    out[0] = nx;
+    out[1] = ny;
+    out[2] = z + s * cot;
+    out[3] = qpt;
+    out[4] = wrap_angle(nphi);
+    out[5] = th;
+    if (path) *path = s;
+    if (!F) return 0;
+
+    /* d(out)/d(in) at fixed path s */
+    double P[36];
+    memset(P, 0, sizeof(P));
+    for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
+    const double dw = -KAPPA * bz;                /* dw / d(q/pT) */
+    P[0 * 6 + 3] = s * s * gx * dw;
+    P[0 * 6 + 4] = -s * B;
+    P[1 * 6 + 3] = s * s * gy * dw;
+    P[1 * 6 + 4] = s * A;
+    P[2 * 6 + 5] = -s / (sin(th) * sin(th));
+    P[4 * 6 + 3] = s * dw;
+    /* the path depends on the inputs through x(s)^2 + y(s)^2 = r^2 */
+    const double cn = cos(nphi), sn = sin(nphi);
+    const double den = nx * cn + ny * sn;
+    const double t[6] = {cn, sn, cot, 0.0, w, 0.0};
+    double ds[6];
+    for (int j = 0; j < 6; ++j) ds[j] = -(nx * P[0 * 6 + j] + ny * P[1 * 6 + j]) / den;
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) F[i * 6 + j] = P[i * 6 + j] + t[i] * ds[j];
+    return 0;
+}
+
+void orc_transport(const double F[36], double C[36])
+{
+    double FC[36], Ft[36];
+    matmul(F, C, FC, 6, 6, 6);
+    transpose(F, Ft, 6, 6);
+    matmul(FC, Ft, C, 6, 6, 6);
+    symmetrize(C);
+}
+
+/* ------------------------------------------------------------ material */
+
+/* Highland scattering angle for a layer of x0 radiation lengths crossed at
+ * incidence alpha to its normal; the two projected angles add noise to the
+ * momentum direction: Var phi += th0^2/sin^2 theta, Var theta += th0^2, and
+ * q/pT = q/(p sin theta) picks up the theta part at fixed |p|. */
+void orc_add_ms(const double p[6], double x0, double mass, double C[36])
+{
+    if (x0 <= 0.0) return;
+    const double qpt = p[3], phi = p[4], th = p[5];
+    const double phipos = atan2(p[1], p[0]);
+    double cosa = fabs(sin(th) * cos(phi - phipos));
+    if (cosa < 1e-6) cosa = 1e-6;
+    const double t = x0 / cosa;
+    const double k = fabs(qpt) * sin(th);                 /* 1 / |p| */
+    const double inv_beta_p = k * sqrt(1.0 + mass * mass * k * k);
+    const double th0 = 0.0136 * inv_beta_p * sqrt(t) * (1.0 + 0.038 * log(t));
+    const double v = th0 * th0;
+    const double cot = cos(th) / sin(th);
+    /* Q = J diag(v, v) J^T with J the derivative of (q/pT, phi, theta) wrt
+     * the two projected angles at fixed |p| */
+    double J[12];          /* rows: state params 0..5, cols: (angle_1, angle_2) */
+    memset(J, 0, sizeof(J));
+    J[4 * 2 + 0] = 1.0 / sin(th);
+    J[5 * 2 + 1] = 1.0;
+    J[3 * 2 + 1] = -qpt * cot;
+    double Jt[12], JJt[36];
+    transpose(J, Jt, 6, 2);
+    matmul(J, Jt, JJt, 6, 2, 6);
+    for (int i = 0; i < 36; ++i) C[i] += v * JJt[i];
+}
+
+/* ------------------------------------------------------------ measurement */
+
+/* The measurement is the hit position in the plane tangent to the layer at
+ * the hit: u along (-sin phi_h, cos phi_h, 0) and z.  H is the 2x6 matrix of
+ * that projection, V = diag(sigma_rphi^2, sigma_z^2). */
+static void measurement(const double p[6], const double hit[3], double srphi, double sz,
+                        double H[12], double res[2], double V[4])
+{
+    const double phih = atan2(hit[1], hit[0]);
+    const double sh = sin(phih), ch = cos(phih);
+    memset(H, 0, 12 * sizeof(double));
+    H[0 * 6 + 0] = -sh;
+    H[0 * 6 + 1] = ch;
+    H[1 * 6 + 2] = 1.0;
+    res[0] = (hit[0] - p[0]) * (-sh) + (hit[1] - p[1]) * ch;
+    res[1] = hit[2] - p[2];
+    V[0] = srphi * srphi;
+    V[1] = 0.0;
+    V[2] = 0.0;
+    V[3] = sz * sz;
+}
+
+static void innovation(const double C[36], const double H[12], const double V[4], double HC[12],
+                       double S[4], double Sinv[4])
+{
+    double Ht[12];
+    matmul(H, C, HC, 2, 6, 6);
+    transpose(H, Ht, 2, 6);
+    matmul(HC, Ht, S, 2, 6, 2);
+    for (int i = 0; i < 4; ++i) S[i] += V[i];
+    const double det = S[0] * S[3] - S[1] * S[2];
+    Sinv[0] = S[3] / det;
+    Sinv[1] = -S[1] / det;
+    Sinv[2] = -S[2] / det;
+    Sinv[3] = S[0] / det;
+}
+
+double orc_chi2(const double p[6], const double C[36], const double hit[3], double srphi, double sz)
+{
+    double H[12], r[2], V[4], HC[12], S[4], Si[4], Sr[2];
+    measurement(p, hit, srphi, sz, H, r, V);
+    innovation(C, H, V, HC, S, Si);
+    matmul(Si, r, Sr, 2, 2, 1);
+    return r[0] * Sr[0] + r[1] * Sr[1];
+}
+
+double orc_update(const double p[6], const double C[36], const double hit[3], double srphi,
+                  double sz, double out_p[6], double out_C[36])
+{
+    double H[12], r[2], V[4], HC[12], S[4], Si[4], Sr[2];
+    measurement(p, hit, srphi, sz, H, r, V);
+    innovation(C, H, V, HC, S, Si);
+    matmul(Si, r, Sr, 2, 2, 1);
+    const double chi2 = r[0] * Sr[0] + r[1] * Sr[1];
+    /* gain K = C H^T S^-1 = (H C)^T S^-1 */
+    double CHt[12], K[12], Kr[6], KHC[36];
+    transpose(HC, CHt, 2, 6);
+    matmul(CHt, Si, K, 6, 2, 2);
+    matmul(K, r, Kr, 6, 2, 1);
+    matmul(K, HC, KHC, 6, 2, 6);
+    double np[6], nC[36];
+    for (int i = 0; i < 6; ++i) np[i] = p[i] + Kr[i];
+    np[4] = wrap_angle(np[4]);
+    for (int i = 0; i < 36; ++i) nC[i] = C[i] - KHC[i];
+    symmetrize(nC);
+    memcpy(out_p, np, sizeof(np));
+    memcpy(out_C, nC, sizeof(nC));
+    return chi2;
+}
+
+/* ------------------------------------------------------------ threading */
+
+typedef struct {
+    void (*fn)(void *ctx, int64_t i);
+    void *ctx;
+    int64_t n;
+    int64_t chunk;
+    atomic_long next;
+} pool_job;
+
+static void *pool_worker(void *arg)
+{
+    pool_job *job = (pool_job *)arg;
+    for (;;) {
+        int64_t b = atomic_fetch_add(&job->next, job->chunk);
+        if (b >= job->n) break;
+        int64_t e = b + job->chunk < job->n ? b + job->chunk : job->n;
+        for (int64_t i = b; i < e; ++i) job->fn(job->ctx, i);
+    }
+    return NULL;
+}
+
+static void parallel_for(int64_t n, int n_threads, int64_t chunk, void (*fn)(void *, int64_t), void *ctx)
+{
+    pool_job job;
+    job.fn = fn;
+    job.ctx = ctx;
+    job.n = n;
+    job.chunk = chunk;
+    atomic_init(&job.next, 0);
+    if (n_threads <= 1) {
+        pool_worker(&job);
+        return;
+    }
+    pthread_t th[256];
+    if (n_threads > 256) n_threads = 256;
+    for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, pool_worker, &job);
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+}
+
+/* ------------------------------------------------------------ fit */
+
+typedef struct {
+    const orc_config *cfg;
+    const orc_hits *hits;
+    const double *init_par, *init_cov;
+    const int32_t *track_hits;
+    double *out_par, *out_cov, *out_chi2, *hit_chi2;
+    int32_t *out_ndof, *out_status;
+} fit_ctx;
+
+static void fit_one(void *vctx, int64_t i)
+{
+    const fit_ctx *c = (const fit_ctx *)vctx;
+    const orc_config *cfg = c->cfg;
+    const int nl = cfg->n_layers;
+    double p[6], C[36], op[6], oC[36];
+    memcpy(p, c->init_par + 6 * i, sizeof(p));
+    unpack21(c->init_cov + 21 * i, C);
+    memcpy(op, p, sizeof(p));
+    memcpy(oC, C, sizeof(C));
+    double chi2 = 0.0;
+    int nupd = 0, status = 0;
+    for (int L = 0; L < nl; ++L) {
+        if (c->hit_chi2) c->hit_chi2[i * nl + L] = -1.0;
+    }
+    for (int L = 0; L < nl; ++L) {
+        if (L > 0) {
+            double np[6], F[36];
+            orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
+            if (orc_propagate(p, cfg->radius[L], cfg->bz, np, F, NULL, NULL)) {
+                status = 2;
+                break;
+            }
+            memcpy(p, np, sizeof(p));
+            orc_transport(F, C);
+        }
+        const int32_t h = c->track_hits[i * nl + L];
+        if (h >= 0) {
+            const double *hit = c->hits->xyz[L] + 3 * (int64_t)h;
+            double c2 = orc_update(p, C, hit, cfg->sigma_rphi, cfg->sigma_z, p, C);
+            chi2 += c2;
+            ++nupd;
+            memcpy(op, p, sizeof(p));
+            memcpy(oC, C, sizeof(C));
+            if (c->hit_chi2) c->hit_chi2[i * nl + L] = c2;
+        }
+    }
+    memcpy(c->out_par + 6 * i, op, sizeof(op));
+    pack21(oC, c->out_cov + 21 * i);
+    c->out_chi2[i] = chi2;
+    c->out_ndof[i] = 2 * nupd - 5;
+    c->out_status[i] = status;
+}
+
+void orc_fit(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks, const double *init_par,
+             const double *init_cov, const int32_t *track_hits, double *out_par, double *out_cov,
+             double *out_chi2, int32_t *out_ndof, int32_t *out_status, double *hit_chi2,
+             int32_t n_threads)
+{
+    fit_ctx c = {cfg, hits, init_par, init_cov, track_hits, out_par, out_cov, out_chi2, hit_chi2,
+                 out_ndof, out_status};
+    parallel_for(n_tracks, n_threads, 64, fit_one, &c);
+}
+
+/* ------------------------------------------------------------ building */
+
+typedef struct {
+    double par[6];
+    double C[36];
+    double chi2;
+    int32_t hits[ORC_MAX_LAYERS];
+    int32_t n_hits, n_holes, status, stopped;
+} cand_t;
+
+enum { KIND_HIT = 0, KIND_HOLE = 1, KIND_STOPPED = 2 };
+
+typedef struct {
+    int32_t n_hits;
+    double chi2;        /* parent's chi2 plus this hit's chi2 */
+    double hit_chi2;
+    int32_t parent;     /* parent's rank in the current beam */
+    int32_t hit;        /* hit index in the layer, HOLE_ID for holes and stopped */
+    int32_t kind;
+} entry_t;
+
+static int entry_cmp(const void *va, const void *vb)
+{
+    const entry_t *a = (const entry_t *)va, *b = (const entry_t *)vb;
+    if (a->n_hits != b->n_hits) return a->n_hits > b->n_hits ? -1 : 1;
+    if (a->chi2 != b->chi2) return a->chi2 < b->chi2 ? -1 : 1;
+    if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
+    if (a->hit != b->hit) return a->hit < b->hit ? -1 : 1;
+    return 0;
+}
+
+typedef struct {
+    const orc_config *cfg;
+    const orc_hits *hits;
+    const double *seed_par, *seed_cov;
+    const int32_t *seed_hits, *seed_ids;
+    orc_track *out;
+} build_ctx;
+
+static void build_one(void *vctx, int64_t row)
+{
+    const build_ctx *bc = (const build_ctx *)vctx;
+    const orc_config *cfg = bc->cfg;
+    const int nl = cfg->n_layers, nsl = cfg->n_seed_layers;
+    int k = cfg->max_cands;
+    if (k > ORC_MAX_CANDS) k = ORC_MAX_CANDS;
+    const int64_t sid = bc->seed_ids ? bc->seed_ids[row] : row;
+    orc_track *o = &bc->out[row];
+
+    cand_t beam[ORC_MAX_CANDS], next[ORC_MAX_CANDS];
+    double pred_par[ORC_MAX_CANDS][6], pred_C[ORC_MAX_CANDS][36];
+    int nb = 1;
+    memset(&beam[0], 0, sizeof(cand_t));
+    memcpy(beam[0].par, bc->seed_par + 6 * sid, 6 * sizeof(double));
+    unpack21(bc->seed_cov + 21 * sid, beam[0].C);
+    for (int L = 0; L < ORC_MAX_LAYERS; ++L) beam[0].hits[L] = -1;
+    for (int L = 0; L < nsl; ++L) {
+        beam[0].hits[L] = bc->seed_hits[sid * nsl + L];
+        if (beam[0].hits[L] >= 0) beam[0].n_hits++;
+    }
+
+    double m_cut = INFINITY, m_rank = INFINITY, m_prop = INFINITY;
+    int64_t n_prop = 0, n_accept = 0, n_update = 0;
+    int cap = 64, ne = 0;
+    entry_t *ent = (entry_t *)malloc(cap * sizeof(entry_t));
+
+    for (int L = nsl; L < nl; ++L) {
+        ne = 0;
+        const double r = cfg->radius[L];
+        for (int c = 0; c < nb; ++c) {
+            cand_t *cd = &beam[c];
+            if (!cd->stopped) {
+                double p[6], C[36], F[36], mrg;
+                memcpy(p, cd->par, sizeof(p));
+                memcpy(C, cd->C, sizeof(C));
+                orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
+                ++n_prop;
+                int fail = orc_propagate(p, r, cfg->bz, pred_par[c], F, NULL, &mrg);
+                if (fabs(mrg) / r < m_prop) m_prop = fabs(mrg) / r;
+                if (fail) {
+                    cd->stopped = 1;
+                    cd->status = 2;       /* keeps its state on the previous surface */
+                } else {
+                    memcpy(pred_C[c], C, sizeof(C));
+                    orc_transport(F, pred_C[c]);
+                    int nacc = 0;
+                    const double *xyz = bc->hits->xyz[L];
+                    const double *pp = pred_par[c];
+                    for (int32_t j = 0; j < bc->hits->n_hits[L]; ++j) {
+                        const double *h = xyz + 3 * (int64_t)j;
+                        if (h[0] * pp[0] + h[1] * pp[1] <= 0.0) continue;   /* other side */
+                        double c2 = orc_chi2(pp, pred_C[c], h, cfg->sigma_rphi, cfg->sigma_z);
+                        double dm = fabs(c2 - cfg->chi2_cut);
+                        if (dm < m_cut) m_cut = dm;
+                        if (c2 < cfg->chi2_cut) {
+                            if (ne == cap) {
+                                cap *= 2;
+                                ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
+                            }
+                            entry_t *e = &ent[ne++];
+                            e->n_hits = cd->n_hits + 1;
+                            e->chi2 = cd->chi2 + c2;
+                            e->hit_chi2 = c2;
+                            e->parent = c;
+                            e->hit = j;
+                            e->kind = KIND_HIT;
+                            ++nacc;
+                        }
+                    }
+                    n_accept += nacc;
+                    if (nacc == 0 || cfg->hole_always) {
+                        if (cd->n_holes < cfg->max_holes) {
+                            if (ne == cap) {
+                                cap *= 2;
+                                ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
+                            }
+                            entry_t *e = &ent[ne++];
+                            e->n_hits = cd->n_hits;
+                            e->chi2 = cd->chi2;
+                            e->hit_chi2 = 0.0;
+                            e->parent = c;
+                            e->hit = HOLE_ID;
+                            e->kind = KIND_HOLE;
+                        } else if (nacc == 0) {
+                            /* no hit and no hole left: stop on this surface */
+                            cd->stopped = 1;
+                            cd->status = 1;
+                            memcpy(cd->par, pred_par[c], sizeof(cd->par));
+                            memcpy(cd->C, pred_C[c], sizeof(cd->C));
+                        }
+                    }
+                }
+            }
+            if (cd->stopped) {
+                if (ne == cap) {
+                    cap *= 2;
+                    ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
+                }
+                entry_t *e = &ent[ne++];
+                e->n_hits = cd->n_hits;
+                e->chi2 = cd->chi2;
+                e->hit_chi2 = 0.0;
+                e->parent = c;
+                e->hit = HOLE_ID;
+                e->kind = KIND_STOPPED;
+            }
+        }
+        qsort(ent, ne, sizeof(entry_t), entry_cmp);
+        if (ne > k && ent[k - 1].n_hits == ent[k].n_hits) {
+            double gap = (ent[k].chi2 - ent[k - 1].chi2) / (1.0 + ent[k - 1].chi2);
+            if (gap < m_rank) m_rank = gap;
+        }
+        int nn = ne < k ? ne : k;
+        for (int i = 0; i < nn; ++i) {
+            const entry_t *e = &ent[i];
+            const cand_t *par = &beam[e->parent];
+            cand_t *nc = &next[i];
+            *nc = *par;
+            if (e->kind == KIND_HIT) {
+                const double *h = bc->hits->xyz[L] + 3 * (int64_t)e->hit;
+                orc_update(pred_par[e->parent], pred_C[e->parent], h, cfg->sigma_rphi, cfg->sigma_z,
+                           nc->par, nc->C);
+                nc->chi2 = e->chi2;
+                nc->hits[L] = e->hit;
+                nc->n_hits = e->n_hits;
+                ++n_update;
+            } else if (e->kind == KIND_HOLE) {
+                memcpy(nc->par, pred_par[e->parent], sizeof(nc->par));
+                memcpy(nc->C, pred_C[e->parent], sizeof(nc->C));
+                nc->n_holes++;
+            }
+        }
+        memcpy(beam, next, nn * sizeof(cand_t));
+        nb = nn;
+    }
+    free(ent);
+
+    if (nb > 1 && beam[0].n_hits == beam[1].n_hits) {
+        double gap = (beam[1].chi2 - beam[0].chi2) / (1.0 + beam[0].chi2);
+        if (gap < m_rank) m_rank = gap;
+    }
+    const cand_t *best = &beam[0];
+    memcpy(o->par, best->par, sizeof(o->par));
+    pack21(best->C, o->cov);
+    o->chi2 = best->chi2;
+    for (int L = 0; L < ORC_MAX_LAYERS; ++L) o->hits[L] = L < nl ? best->hits[L] : -1;
+    o->n_hits = best->n_hits;
+    o->n_holes = best->n_holes;
+    o->status = best->status;
+    o->n_final = nb;
+    o->m_cut = m_cut;
+    o->m_rank = m_rank;
+    o->m_prop = m_prop;
+    o->n_prop = n_prop;
+    o->n_accept = n_accept;
+    o->n_update = n_update;
+}
+
+void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total,
+               const double *seed_par, const double *seed_cov, const int32_t *seed_hits,
+               const int32_t *seed_ids, int32_t n_sel, orc_track *out, int32_t n_threads)
+{
+    (void)n_seeds_total;
+    build_ctx bc = {cfg, hits, seed_par, seed_cov, seed_hits, seed_ids, out};
+    parallel_for(n_sel, n_threads, 4, build_one, &bc);
+}
+
+double orc_replay(const orc_config *cfg, const orc_hits *hits, const double seed_par[6],
+                  const double seed_cov[21], const int32_t *layer_hits, double *layer_chi2,
+                  int32_t *ok)
+{
+    double p[6], C[36], total = 0.0;
+    memcpy(p, seed_par, sizeof(p));
+    unpack21(seed_cov, C);
+    *ok = 1;
+    for (int L = 0; L < cfg->n_layers; ++L) layer_chi2[L] = -1.0;
+    for (int L = cfg->n_seed_layers; L < cfg->n_layers; ++L) {
+        double np[6], F[36];
+        orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
+        if (orc_propagate(p, cfg->radius[L], cfg->bz, np, F, NULL, NULL)) {
+            *ok = 0;
+            break;
+        }
+        memcpy(p, np, sizeof(p));
+        orc_transport(F, C);
+        const int32_t h = layer_hits[L];
+        if (h >= 0) {
+            const double *hit = hits->xyz[L] + 3 * (int64_t)h;
+            double c2 = orc_update(p, C, hit, cfg->sigma_rphi, cfg->sigma_z, p, C);
+            layer_chi2[L] = c2;
+            total += c2;
+            if (!(c2 < cfg->chi2_cut)) *ok = 0;
+        }
+    }
+    return total;
+}

@@ -1,0 +1,116 @@
+/* FP64 CPU oracle of the barrel Kalman-filter track builder and fitter.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the package's smoke check and
+ * the benchmark's CPU-baseline leg may call it.  It shares no source, header,
+ * table or helper with the GPU library, and the GPU library never calls it.
+ *
+ * Units: cm, GeV, tesla, radians; field along +z.  A state is
+ * (x, y, z, q/pT, phi, theta): global Cartesian position and polar momentum
+ * (the paper's hybrid coordinate system, Section 2.2).  Covariances cross this
+ * interface packed as the 21-entry upper triangle, row-major.
+ */
+#ifndef MKF_ORACLE_H
+#define MKF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_LAYERS 16
+#define ORC_MAX_CANDS 16
+
+typedef struct {
+    int32_t n_layers;
+    int32_t n_seed_layers;      /* seeds sit on layer n_seed_layers-1 */
+    int32_t max_cands;          /* beam width k */
+    int32_t max_holes;
+    int32_t hole_always;        /* 1: a hole child even when hits were accepted */
+    int32_t pad_;
+    double radius[ORC_MAX_LAYERS];
+    double x0[ORC_MAX_LAYERS];  /* material per layer, radiation lengths at normal incidence */
+    double bz;
+    double sigma_rphi;
+    double sigma_z;
+    double chi2_cut;
+    double mass;                /* mass hypothesis for the scattering angle */
+} orc_config;
+
+typedef struct {
+    int32_t n_layers;
+    int32_t pad_;
+    const int32_t *n_hits;      /* [n_layers] */
+    const double *const *xyz;   /* [n_layers] -> [n_hits[L]][3] */
+} orc_hits;
+
+/* Result of one seed's build (rank-0 candidate after the last layer). */
+typedef struct {
+    double par[6];
+    double cov[21];
+    double chi2;
+    int32_t hits[ORC_MAX_LAYERS];
+    int32_t n_hits;
+    int32_t n_holes;
+    int32_t status;             /* 0 reached last layer, 1 hole limit, 2 propagation failed */
+    int32_t n_final;            /* candidates alive in the final beam */
+    /* decision margins, for the tie protocol of the parity tests */
+    double m_cut;               /* min |chi2 - cut| over all (candidate, hit) chi2 evaluated */
+    double m_rank;              /* min relative key gap at beam boundaries and final choice */
+    double m_prop;              /* min |distance to tangency| / r over propagations */
+    /* counters */
+    int64_t n_prop;             /* candidate-layers propagated */
+    int64_t n_accept;           /* (candidate, hit) pairs passing the cut */
+    int64_t n_update;           /* KF updates of surviving hit children */
+} orc_track;
+
+/* Propagate a state to the cylinder of radius r (closed-form circle
+ * intersection).  F (6x6 row-major, may be NULL) receives d(out)/d(in) on the
+ * cylinder.  Returns 0 on success, 1 if the helix never reaches r.
+ * *margin (may be NULL) receives the signed distance to tangency. */
+int orc_propagate(const double par[6], double r, double bz, double out[6],
+                  double F[36], double *path, double *margin);
+
+/* Add multiple-scattering noise for crossing a layer of thickness x0 at the
+ * state's position (full 6x6 row-major covariance, in place). */
+void orc_add_ms(const double par[6], double x0, double mass, double C[36]);
+
+/* chi2 of a hit against a predicted state (full 6x6 covariance). */
+double orc_chi2(const double par[6], const double C[36], const double hit[3],
+                double sigma_rphi, double sigma_z);
+
+/* KF update with one hit; writes the filtered state and covariance and
+ * returns the hit's chi2. */
+double orc_update(const double par[6], const double C[36], const double hit[3],
+                  double sigma_rphi, double sigma_z, double out_par[6], double out_C[36]);
+
+/* Transport C <- F C F^T (full 6x6). */
+void orc_transport(const double F[36], double C[36]);
+
+/* Forward fit with known hits (-1 = no hit on that layer).  init_* are the
+ * prior at layer 0, packed covariance.  Output: state after the last update,
+ * chi2 summed over all updates, ndof = 2*n_updates - 5, status as above.
+ * hit_chi2 (may be NULL): [n][n_layers] per-hit chi2 (-1 where no update). */
+void orc_fit(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
+             const double *init_par, const double *init_cov, const int32_t *track_hits,
+             double *out_par, double *out_cov, double *out_chi2, int32_t *out_ndof,
+             int32_t *out_status, double *hit_chi2, int32_t n_threads);
+
+/* Combinatorial KF building of the listed seeds (all if seed_ids == NULL).
+ * Output row i belongs to seed_ids[i]. */
+void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total,
+               const double *seed_par, const double *seed_cov, const int32_t *seed_hits,
+               const int32_t *seed_ids, int32_t n_sel, orc_track *out, int32_t n_threads);
+
+/* Replay a given hit list for one seed through the building rules: propagate
+ * layer by layer, update with the listed hit (or take a hole for -1).  Writes
+ * per-layer chi2 (-1 for holes) and returns the summed chi2; *ok is 0 when a
+ * listed hit fails the cut or propagation fails. */
+double orc_replay(const orc_config *cfg, const orc_hits *hits, const double seed_par[6],
+                  const double seed_cov[21], const int32_t *layer_hits, double *layer_chi2,
+                  int32_t *ok);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
