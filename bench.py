@@ -1,0 +1,226 @@
+"""Benchmark of the MI355X Kalman-filter track builder.
+
+Default (the headline): combinatorial KF building of 10 events x 20,000
+tracks (10 % noise hits, up to 6 candidates per seed, chi2 cut 30, one hole),
+all events in one batched launch per step, inputs resident on the device.
+A step = hit-index build for every event + the batched build.  Prints one
+JSON line with throughput, the roofline of the build kernel, the CPU oracle
+baseline and serving latencies.
+
+Other workloads (--workload): fit (1,000,000 tracks in 64 uneven batches),
+batched (256 uneven events, batched vs plain builder), serve (Poisson
+arrivals, p50/p99 latency).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operation counts per unit of work, counted from the kernel
+# source (fma = 2, add/mul/div/sqrt/transcendental = 1).
+FLOP_PER_CAND_LAYER = 480     # scattering 40 + propagation and Jacobian 138 + transport 272 + window 30
+FLOP_PER_CHI2 = 36            # tangent-plane residual, 2x2 innovation, chi2
+FLOP_PER_UPDATE = 186         # gain, state and covariance update
+FLOP_PER_FIT_LAYER = 40 + 138 + 272 + 186   # scattering, propagation, transport, update
+PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_SEED_IO = 228 + 280     # seed in (par, cov, hits) + track out (par, cov, hits, counts, chi2)
+BYTES_PER_HIT = 16                # binned hit read once
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_count_guard(n):
+    if n != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "detail": "events shard across GPUs with no exchange (see DESIGN.md); "
+                                    "multi-GPU runs are not part of this build"}))
+        sys.exit(2)
+
+
+def make_ctx(k, tuning=None):
+    from paper_1702_06359_amd import abi, synth
+    ctx = abi.Context(abi.config_from_geometry(synth.Geometry(), max_cands=k))
+    if tuning:
+        ctx.set_tuning(**tuning)
+    return ctx
+
+
+def time_steps(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_build(ev, k, target_cpu_s=15.0):
+    """The FP64 oracle on a bounded sample of seeds of one event."""
+    import oracle
+    cfg = oracle.config(ev.geometry, max_cands=k)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    hs = oracle.HitSet(ev.hits)
+    probe = np.arange(min(8, ev.n_seeds), dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.build_tracks(cfg, hs, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=probe, n_threads=1)
+    per_seed = (time.perf_counter() - t0) / len(probe)
+    n = int(min(ev.n_seeds, max(threads, target_cpu_s / max(per_seed, 1e-6))))
+    rows = np.arange(n, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.build_tracks(cfg, hs, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=rows, n_threads=threads)
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "tracks/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} seeds of one 20,000-track event (FP64 oracle, brute-force hit search), "
+                      f"{wall:.1f} s wall on {threads} threads"}
+
+
+def serve_latency(ctx, pool, n_submit, rate_hz, seed=0):
+    """Poisson arrivals at rate_hz from a pool of events; returns latencies (s)."""
+    from paper_1702_06359_amd import abi
+    rng = np.random.default_rng(seed)
+    arrays = [abi.EventArrays.from_synth(e) for e in pool]
+    gaps = rng.exponential(1.0 / rate_hz, n_submit)
+    order = rng.integers(0, len(pool), n_submit)
+    pending, lat = [], []
+    t_next = time.perf_counter()
+    i = 0
+    while i < n_submit or pending:
+        now = time.perf_counter()
+        if i < n_submit and now >= t_next:
+            t, _ = ctx.serve_submit(None, ea=arrays[order[i]])
+            if t is not None:
+                pending.append(t)
+                i += 1
+                t_next += gaps[i - 1]
+        still = []
+        for t in pending:
+            r = ctx.serve_poll(t)
+            if r is None:
+                still.append(t)
+            else:
+                assert r[0] == abi.OK, r[0]
+                lat.append(r[1])
+        pending = still
+    return np.array(lat)
+
+
+def workload_ckf(args):
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    n_events, n_tracks, noise, k = 10, 20000, 0.10, 6
+    log(f"generating {n_events} events x {n_tracks} tracks")
+    evs = synth.ckf_events(n_events, n_tracks, noise)
+    ctx = make_ctx(k, args.tuning)
+    handles = [ctx.load_event(e) for e in evs]
+    if args.tune:
+        t = ctx.autotune(handles)
+        log("autotuned:", t.as_dict())
+    tuning = ctx.get_tuning().as_dict()
+
+    def step():
+        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX)
+
+    sync = torch.cuda.synchronize
+    log("warmup + timed steps")
+    for _ in range(args.warmup):
+        step()
+    sync()
+    ctx.timer_reset()
+    elapsed = time_steps(step, args.steps, 0, sync)
+    build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
+    index_ms, index_n = ctx.timer_read(abi.TIMER_INDEX)
+    tracks = n_events * n_tracks
+    value = tracks * args.steps / elapsed
+    # work counters of one launch (separate, untimed)
+    ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_STATS)
+    st = {k2: 0 for k2 in ("cand_layers", "chi2_evals", "accepted", "updates", "hits_scanned")}
+    for h in handles:
+        for k2, v in ctx.get_stats(h).items():
+            st[k2] += v
+    flops = (st["cand_layers"] * FLOP_PER_CAND_LAYER + st["chi2_evals"] * FLOP_PER_CHI2 +
+             st["updates"] * FLOP_PER_UPDATE)
+    avg_ms = build_ms / max(build_n, 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
+                "traffic": None, "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
+                "flop_per_launch": int(flops), "counters": st}
+    plain_rate = None
+    if not args.quick:
+        # the plain per-event builder (one launch per layer) on the same events
+        n_plain = max(1, args.steps // 5)
+        plain_s = time_steps(lambda: [lib_build_plain(ctx, h) for h in handles], n_plain, 1, sync)
+        plain_rate = tracks * n_plain / plain_s
+    result = {
+        "metric": "tracks built/sec (20k-track events, combinatorial KF) and p50/p99 event latency",
+        "value": round(value, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "combinatorial KF building, 10 events x 20,000 tracks, 10% noise hits, "
+                               "k=6 candidates/seed, chi2<30, 1 hole, 10-layer barrel, 3.8 T",
+                   "events": n_events, "tracks_per_event": n_tracks, "noise": noise, "max_cands": k,
+                   "step": "hit index + batched build of all events", "tuning": tuning},
+        "roofline": roofline,
+        "index_kernels_avg_ms": round(index_ms / max(index_n, 1), 4),
+        "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
+    }
+    if not args.quick:
+        log("serving latency run")
+        pool_sizes = synth.loguniform_sizes(16, 500, 50000, cfg=4)
+        pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(pool_sizes)]
+        ctx.serve_config(16 << 30, max_in_flight=64)
+        # saturated rate: everything submitted at once
+        t0 = time.perf_counter()
+        lat = serve_latency(ctx, pool, 96, 1e9)
+        sat = 96 / (time.perf_counter() - t0)
+        lat = serve_latency(ctx, pool, 200, 0.5 * sat, seed=1)
+        result["serving"] = {"events": 200, "rate_events_per_s": round(0.5 * sat, 1),
+                             "saturated_events_per_s": round(sat, 1),
+                             "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                             "tracks_per_event_mean": float(np.mean(pool_sizes))}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline_build(evs[0], k, args.cpu_seconds)
+    ctx.close()
+    return result
+
+
+def lib_build_plain(ctx, h):
+    from paper_1702_06359_amd import abi
+    abi.check(abi.lib().mkf_build(ctx.h, int(h), None))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ckf", choices=["ckf"])
+    ap.add_argument("--tune", action="store_true", help="autotune launch shapes first")
+    ap.add_argument("--quick", action="store_true", help="headline number only (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    gpu_count_guard(args.gpus)
+    args.tuning = None
+    res = {"ckf": workload_ckf}[args.workload](args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

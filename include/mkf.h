@@ -1,0 +1,282 @@
+/* mkf.h - C ABI of the MI355X (gfx950) Kalman-filter track builder.
+ *
+ * The method is Kalman-filter track reconstruction in a barrel detector
+ * (Cerati et al., "Kalman filter tracking on parallel architectures"):
+ * seeding gives a first estimate from a few inner hits; building projects
+ * each candidate outward layer by layer, collects compatible hits with the
+ * KF and branches to several candidates per seed; fitting re-runs the KF
+ * over the final hit set (Section 2).  This library implements building and
+ * fitting on the GPU; seeds are an input.
+ *
+ * Conventions for every call:
+ *  - Units cm, GeV, tesla, radians; magnetic field along +z.
+ *  - A state is (x, y, z, q/pT, phi, theta): global Cartesian position and
+ *    polar momentum, the paper's hybrid coordinates (Section 2.2).  q/pT is
+ *    signed; phi in (-pi, pi] is the momentum azimuth; theta in (0, pi).
+ *  - A covariance is the symmetric 6x6 matrix packed as its 21-entry upper
+ *    triangle, row-major: (0,0) (0,1) .. (0,5) (1,1) .. (5,5).
+ *  - A hit is identified by its layer and its index in the caller's array
+ *    for that layer.
+ *  - All host pointers are plain C arrays in the caller's memory, read or
+ *    written only during the call unless stated; nothing is retained.
+ *  - Every call returns an mkf_status; on error the outputs are untouched and
+ *    mkf_last_error() describes the failure.  Argument checks run on the host
+ *    before any device work.  No C++ exception crosses this interface.
+ *  - One context is used by one host thread at a time, except
+ *    mkf_serve_submit / mkf_serve_poll / mkf_serve_cancel, which are
+ *    thread-safe.
+ */
+#ifndef MKF_H
+#define MKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MKF_MAX_LAYERS 16
+#define MKF_MAX_CANDS 8
+
+typedef enum {
+    MKF_OK = 0,
+    MKF_E_INVALID = -1,   /* bad argument, NaN, count or index out of range */
+    MKF_E_NOMEM = -2,     /* device allocation failed or budget too small */
+    MKF_E_DEVICE = -3,    /* HIP runtime error */
+    MKF_E_AGAIN = -4,     /* serving queue full: retry later */
+    MKF_E_NOTFOUND = -5,  /* unknown event handle or ticket */
+    MKF_E_STATE = -6      /* call not valid in the current state */
+} mkf_status;
+
+/* config.flags */
+#define MKF_HOLE_ALWAYS 0x1u   /* offer a hole child even when hits were accepted */
+
+/* Detector, field and building parameters (Section 2.2: ideal barrel of
+ * cylinders in a uniform longitudinal field, Gaussian hit resolution).
+ * layer_half_z bounds the hit index grid only (hits beyond it go to the edge
+ * bins); layer_x0 is the material of each layer in radiation lengths at
+ * normal incidence (0 = none). */
+typedef struct {
+    int32_t n_layers;        /* 4 .. MKF_MAX_LAYERS */
+    int32_t n_seed_layers;   /* seeds carry one hit on each of layers 0 .. n_seed_layers-1 */
+    int32_t max_cands;       /* candidates kept per seed, 1 .. MKF_MAX_CANDS (1 = best hit) */
+    int32_t max_holes;       /* layers a candidate may cross without a hit, 0 .. 7 */
+    uint32_t flags;          /* MKF_HOLE_ALWAYS */
+    int32_t reserved;
+    double layer_r[MKF_MAX_LAYERS];       /* increasing radii */
+    double layer_half_z[MKF_MAX_LAYERS];
+    double layer_x0[MKF_MAX_LAYERS];
+    double bz;               /* tesla */
+    double sigma_rphi;       /* hit resolution along the layer, cm */
+    double sigma_z;          /* hit resolution along z, cm */
+    double chi2_cut;         /* a hit is compatible when its chi2 < chi2_cut */
+    double mass;             /* mass hypothesis for the scattering angle, GeV */
+} mkf_config;
+
+/* Device memory hooks.  alloc returns device memory usable on `stream`
+ * (the context's HIP stream), or NULL; free releases it.  With no allocator
+ * the library uses hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} mkf_allocator;
+
+/* One event (input).  hit_xyz[L] points at n_hits[L] rows of (x, y, z).
+ * Seeds (for building) and tracks (for fitting) are both optional.
+ *  seed_par  [n_seeds][6]  state on layer n_seed_layers-1 (through its hit)
+ *  seed_cov  [n_seeds][21]
+ *  seed_hits [n_seeds][n_seed_layers]   hit index per seed layer (-1 = none)
+ *  track_par [n_tracks][6]  prior state on layer 0
+ *  track_cov [n_tracks][21]
+ *  track_hits[n_tracks][n_layers]  hit index per layer, -1 = no hit */
+typedef struct {
+    int32_t n_layers;
+    int32_t n_seeds;
+    int32_t n_tracks;
+    int32_t reserved;
+    const int32_t *n_hits;
+    const double *const *hit_xyz;
+    const double *seed_par;
+    const double *seed_cov;
+    const int32_t *seed_hits;
+    const double *track_par;
+    const double *track_cov;
+    const int32_t *track_hits;
+} mkf_event;
+
+/* Track output, caller-allocated, one row per seed (building) or per track
+ * (fitting).  Any pointer may be NULL to skip that field.
+ *  par  [n][6], cov [n][21]: state and covariance on the last surface the
+ *        candidate reached (building) or after the last update (fitting);
+ *        scattering of that last surface is not included.
+ *  hits [n][n_layers]: hit index per layer, -1 = hole or not reached; the
+ *        seed layers carry the seed's hits.
+ *  n_hits: hits on the track (seed hits included) / updates in the fit.
+ *  n_holes: holes taken (building) / layers without a hit (fitting).
+ *  chi2: sum of the accepted hits' chi2 on the building layers / over all
+ *        updates of the fit.
+ *  ndof: 2 * updates - 5 (fitting); 2 * building hits (building).
+ *  status: 0 reached the last layer, 1 stopped when no hit and no hole was
+ *        left, 2 the helix does not reach the next layer. */
+typedef struct {
+    int32_t n;
+    int32_t reserved;
+    double *par;
+    double *cov;
+    int32_t *hits;
+    int32_t *n_hits;
+    int32_t *n_holes;
+    double *chi2;
+    int32_t *ndof;
+    int32_t *status;
+} mkf_tracks;
+
+/* Launch shapes.  None of them changes any result. */
+typedef struct {
+    int32_t lanes_per_seed;   /* 1, 2, 4 or 8, >= max_cands; 0 = smallest valid */
+    int32_t waves_per_block;  /* 1 .. 16; 0 = 4 */
+    int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 256 */
+    int32_t bins_z;           /* hit-index bins in z per layer, 1 .. 1024; 0 = 16 */
+    int32_t persistent;       /* batched build: 1 = persistent waves on a work queue */
+    int32_t blocks_per_cu;    /* persistent grid size per compute unit, 1 .. 32; 0 = 8 */
+} mkf_tuning;
+
+/* Counters of the last build of an event (zero unless MKF_BATCH_STATS). */
+typedef struct {
+    int64_t cand_layers;      /* candidate propagations to a layer */
+    int64_t chi2_evals;       /* (candidate, hit) pairs inside the search window */
+    int64_t accepted;         /* pairs with chi2 < cut */
+    int64_t updates;          /* Kalman updates of surviving hit children */
+    int64_t hits_scanned;     /* hits read from the window's bins */
+} mkf_build_stats;
+
+typedef struct mkf_ctx mkf_ctx;
+
+/* Library version string, static storage. */
+const char *mkf_version(void);
+
+/* Create a context on the current HIP device.
+ * cfg: building parameters (copied).  alloc: may be NULL.  hip_stream: a
+ * hipStream_t to run on (NULL = a stream the library creates).  *out
+ * receives the context.  Errors: MKF_E_INVALID for an inconsistent config,
+ * MKF_E_DEVICE when no gfx950 device is current. */
+mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *hip_stream,
+                      mkf_ctx **out);
+
+/* Destroy a context and everything it owns (events, serving state).  Waits
+ * for outstanding device work.  NULL is ignored. */
+void mkf_destroy(mkf_ctx *ctx);
+
+/* Message of the last failed call on this thread (static storage). */
+const char *mkf_last_error(void);
+
+/* Change launch shapes (copied).  Loaded events are re-indexed on their next
+ * build when the bin grid changes.  MKF_E_INVALID for values out of range. */
+mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t);
+mkf_status mkf_get_tuning(const mkf_ctx *ctx, mkf_tuning *t);
+
+/* Load an event: validate on the host, copy hits, seeds and tracks to the
+ * device and build its (eta, phi)-binned hit index there (Section 3.2.1: the
+ * data structures used to select hit candidates).  Synchronous: the host
+ * arrays may be freed on return.  *handle identifies the event until
+ * mkf_unload_event.  Errors: MKF_E_INVALID (counts, NaN or hit index out of
+ * range), MKF_E_NOMEM, MKF_E_DEVICE. */
+mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle);
+mkf_status mkf_unload_event(mkf_ctx *ctx, int32_t handle);
+
+/* Plain builder: one event, one kernel launch per layer with the candidate
+ * state in device memory between layers (Section 2: building layer by layer
+ * with branching; Section 3.2.1: the beam is re-ranked and pruned after each
+ * layer).  Blocks until the tracks are in `out` (out->n must equal the
+ * event's n_seeds; out may be NULL to keep the results on the device). */
+mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
+
+/* mkf_build_batch flags */
+#define MKF_BATCH_REINDEX 0x1u   /* rebuild every event's hit index first (same stream) */
+#define MKF_BATCH_STATS 0x2u     /* count work (mkf_get_stats); slower */
+#define MKF_BATCH_GRAPH 0x4u     /* run the pipeline as a captured hipGraph, cached per handle list */
+
+/* Batched builder: all listed events in one launch of persistent waves that
+ * take (event, seed group) work items from a device queue, with every layer
+ * of a candidate kept in registers (Section 2.3: small units of work with
+ * dynamic assignment against uneven events; Section 4: seeds of several
+ * events processed together).  Results equal mkf_build's.  outs: n entries
+ * or NULL (results stay on the device; see mkf_fetch_tracks). */
+mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags,
+                           mkf_tracks *outs);
+
+/* Copy the last build results of an event to the host. */
+mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
+
+/* Work counters of the last build of an event. */
+mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out);
+
+/* KF fit with known hits (Section 2: once the hit set is fixed the filter
+ * runs without branching).  For each track: update with its layer-0 hit,
+ * then for every further layer add the previous layer's scattering noise,
+ * propagate, transport the covariance and update with the assigned hit (or
+ * skip).  Inputs are host arrays as in mkf_event (track_*), hits refer to the
+ * loaded event `handle`.  Blocks until `out` (n rows) is written. */
+mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double *init_par,
+                   const double *init_cov, const int32_t *track_hits, mkf_tracks *out);
+
+/* Fit the tracks loaded with each event (mkf_event.track_*), all events in
+ * one launch.  outs: n entries (outs[i].n = that event's n_tracks) or NULL. */
+mkf_status mkf_fit_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tracks *outs);
+
+/* Device time of the library's kernels, from HIP events recorded on the
+ * context stream around each launch of non-graph calls.  which: 0 = build
+ * (batched build kernel, or the plain per-layer kernels), 1 = hit index,
+ * 2 = fit.  Returns the summed milliseconds and launch count since the last
+ * reset. */
+mkf_status mkf_timer_read(mkf_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
+mkf_status mkf_timer_reset(mkf_ctx *ctx);
+
+/* Autotune: time the batched build of the given events over a grid of
+ * launch shapes, keep the fastest (applied to ctx and written to *best).
+ * Results do not depend on the choice. */
+mkf_status mkf_autotune(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tuning *best);
+
+/* ---- serving (continuous batching) -------------------------------------
+ * Events are submitted as they arrive; a scheduler thread admits them while
+ * the device-memory budget and the in-flight limit allow, copies and indexes
+ * them, and launches batched builds of whatever has been admitted, so new
+ * events start while earlier ones are still on the device.  Each event's
+ * result does not depend on what it was batched with.  Latency runs from
+ * submit until the scheduler observes the event's completion. */
+
+/* Configure serving: device-memory budget in bytes (reserved at once),
+ * events in flight, events per launch (0 = unlimited). */
+mkf_status mkf_serve_config(mkf_ctx *ctx, uint64_t hbm_budget_bytes, int32_t max_in_flight,
+                            int32_t max_batch_events);
+
+/* Submit an event: validated and copied into host staging before return
+ * (the event arrays may be freed); `out` must stay valid until the ticket is
+ * done.  MKF_E_AGAIN when the submission queue is full, MKF_E_NOMEM when the
+ * event can never fit the budget, MKF_E_STATE before mkf_serve_config. */
+mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, uint64_t *ticket);
+
+/* Poll a ticket: *done = 1 once finished; *ticket_status is its mkf_status;
+ * *latency_s the submit-to-completion time.  A finished ticket is forgotten
+ * after the poll that reports it.  MKF_E_NOTFOUND for an unknown ticket. */
+mkf_status mkf_serve_poll(mkf_ctx *ctx, uint64_t ticket, int32_t *done, int32_t *ticket_status,
+                          double *latency_s);
+
+/* Cancel a ticket not yet admitted (MKF_E_STATE once running). */
+mkf_status mkf_serve_cancel(mkf_ctx *ctx, uint64_t ticket);
+
+/* Block until every submitted ticket has finished. */
+mkf_status mkf_serve_drain(mkf_ctx *ctx);
+
+/* ---- measurement helper --------------------------------------------------
+ * Plain device-to-device copy of `bytes` (multiple of 16) on the context
+ * stream with a simple streaming kernel; used to calibrate hardware memory
+ * counters against a known traffic.  Blocks until done. */
+mkf_status mkf_calib_copy(mkf_ctx *ctx, const void *src_dev, void *dst_dev, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

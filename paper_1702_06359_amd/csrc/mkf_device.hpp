@@ -1,0 +1,352 @@
+// FP32 device arithmetic of the Kalman filter: helix propagation with its
+// Jacobian, covariance transport, multiple-scattering noise, hit chi2 and the
+// measurement update.  One lane holds one track candidate; a state lives in
+// registers as p[6] = (x, y, z, q/pT, phi, theta) and the symmetric
+// covariance as its 21-entry packed upper triangle.
+#pragma once
+
+#include "mkf_internal.hpp"
+
+namespace mkf {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kInf = __builtin_huge_valf();
+
+// index of element (i, j) of a symmetric 6x6 matrix in packed upper-triangle storage
+__host__ __device__ constexpr int sym(int i, int j)
+{
+    return i <= j ? i * 6 - (i * (i - 1)) / 2 + (j - i) : j * 6 - (j * (j - 1)) / 2 + (i - j);
+}
+
+__device__ __forceinline__ float wrap_pi(float a)
+{
+    if (a > kPi) a -= kTwoPi;
+    else if (a <= -kPi) a += kTwoPi;
+    return a;
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Structure of the propagation Jacobian in (x, y, z, q/pT, phi, theta):
+// 0 = known zero, 2 = known one, 1 = computed.  The transport below is
+// unrolled against this pattern so known zeros and ones cost nothing (the
+// paper's Matriplex generator does the same for its CPU kernels, Section 2.1).
+constexpr signed char kFpat[6][6] = {
+    {1, 1, 0, 1, 1, 0},
+    {1, 1, 0, 1, 1, 0},
+    {1, 1, 2, 1, 1, 1},
+    {0, 0, 0, 2, 0, 0},
+    {1, 1, 0, 1, 1, 0},
+    {0, 0, 0, 0, 0, 2},
+};
+
+// C <- F C F^T on the packed covariance.
+__device__ __forceinline__ void transport(const float (&F)[6][6], float (&c)[21])
+{
+    float M[6][6];   // F C
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            float acc = 0.f;
+            bool first = true;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                if (kFpat[i][t] == 0) continue;
+                const float v = c[sym(t, j)];
+                if (first) acc = (kFpat[i][t] == 2) ? v : F[i][t] * v;
+                else acc = (kFpat[i][t] == 2) ? acc + v : fmaf(F[i][t], v, acc);
+                first = false;
+            }
+            M[i][j] = acc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int k = i; k < 6; ++k) {
+            float acc = 0.f;
+            bool first = true;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                if (kFpat[k][t] == 0) continue;
+                const float v = M[i][t];
+                if (first) acc = (kFpat[k][t] == 2) ? v : v * F[k][t];
+                else acc = (kFpat[k][t] == 2) ? acc + v : fmaf(v, F[k][t], acc);
+                first = false;
+            }
+            c[sym(i, k)] = acc;
+        }
+    }
+}
+
+// sin(a)/a, (1-cos a)/a and their derivatives (a cos a - sin a)/a^2,
+// (a sin a - 1 + cos a)/a^2: series below |a| = 0.5, where the direct forms
+// lose FP32 digits to cancellation.
+__device__ __forceinline__ void turn_terms(float a, float &S1, float &C1, float &S2, float &C2)
+{
+    if (fabsf(a) < 0.5f) {
+        const float a2 = a * a;
+        S1 = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f), 1.f);
+        C1 = a * fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 3628800.f, -1.f / 40320.f), 1.f / 720.f), -1.f / 24.f), 0.5f);
+        S2 = a * fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 45360.f, -1.f / 840.f), 1.f / 30.f), -1.f / 3.f);
+        C2 = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 403200.f, -1.f / 5760.f), 1.f / 144.f), -0.125f), 0.5f);
+    } else {
+        float sa, ca;
+        sincosf(a, &sa, &ca);
+        const float ia = 1.f / a;
+        S1 = sa * ia;
+        C1 = (1.f - ca) * ia;
+        S2 = (a * ca - sa) * ia * ia;
+        C2 = (a * sa - 1.f + ca) * ia * ia;
+    }
+}
+
+// atan(u)/u
+__device__ __forceinline__ float atanc(float u)
+{
+    if (fabsf(u) < 1e-2f) {
+        const float u2 = u * u;
+        return fmaf(u2, fmaf(u2, 0.2f, -1.f / 3.f), 1.f);
+    }
+    return atanf(u) / u;
+}
+
+// Propagate state p to the cylinder of radius r along the helix of the
+// uniform field (curvature w = w_per_qpt * q/pT, w > 0 turning
+// counter-clockwise).  The transverse path s is the smallest positive root of
+// the half-turn-angle quadratic  alpha T^2 + b T - D/4 = 0  (T = tan(a/2)/w,
+// a = w s) of the chord condition |(x,y) + chord| = r; its w -> 0 limit is the
+// straight line.  Writes the new state o and the Jacobian F = d o / d p on
+// the cylinder (the derivative at fixed s plus the change of s that keeps the
+// end point on the cylinder).  Returns false when r is never reached.
+__device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_per_qpt, float (&o)[6],
+                                          float (&F)[6][6])
+{
+    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4], th = p[5];
+    const float w = w_per_qpt * q;
+    float sph, cph;
+    sincosf(phi, &sph, &cph);
+    const float b = fmaf(x, cph, y * sph);
+    const float e = fmaf(y, cph, -x * sph);
+    const float D = fmaf(r, r, -fmaf(x, x, y * y));
+    const float alpha = fmaf(w, e, 1.f) - 0.25f * w * w * D;
+    const float disc = fmaf(b, b, alpha * D);
+    if (!(disc >= 0.f)) return false;
+    const float qd = sqrtf(disc);
+    const float roots[2] = {(b + qd != 0.f) ? 0.5f * D / (b + qd) : kInf,
+                            (alpha != 0.f) ? -(b + qd) / (2.f * alpha) : kInf};
+    const float smin = 1e-6f * r;
+    float s = kInf;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float T = roots[i];
+        if (!(fabsf(T) < kInf)) continue;
+        const float u = w * T;
+        const float s1 = 2.f * T * atanc(u);
+        if (s1 > smin && s1 < s) s = s1;
+        if (w != 0.f) {
+            const float s2 = 2.f * (atanf(u) + copysignf(kPi, w)) / w;
+            if (s2 > smin && s2 < s) s = s2;
+        }
+    }
+    if (!(s < kInf)) return false;
+
+    const float a = w * s;
+    float S1, C1, S2, C2;
+    turn_terms(a, S1, C1, S2, C2);
+    const float A = fmaf(cph, S1, -sph * C1);     // (sin(phi+a) - sin phi)/a
+    const float B = fmaf(cph, C1, sph * S1);      // (cos phi - cos(phi+a))/a
+    const float gx = fmaf(cph, S2, -sph * C2);    // dA/da
+    const float gy = fmaf(sph, S2, cph * C2);     // dB/da
+    float sth, cth;
+    sincosf(th, &sth, &cth);
+    const float ist = 1.f / sth;
+    const float cot = cth * ist;
+    const float nx = fmaf(s, A, x), ny = fmaf(s, B, y);
+    const float ca = fmaf(-a, C1, 1.f), sa = a * S1;       // cos a, sin a
+    const float cn = fmaf(cph, ca, -sph * sa), sn = fmaf(sph, ca, cph * sa);
+    o[0] = nx;
+    o[1] = ny;
+    o[2] = fmaf(s, cot, z);
+    o[3] = q;
+    o[4] = wrap_pi(phi + a);
+    o[5] = th;
+
+    // derivatives at fixed path
+    const float Pxq = s * s * gx * w_per_qpt, Pxp = -s * B;
+    const float Pyq = s * s * gy * w_per_qpt, Pyp = s * A;
+    const float Pzt = -s * ist * ist;
+    const float Ppq = s * w_per_qpt;
+    // d s / d p from x'^2 + y'^2 = r^2
+    const float iden = -1.f / fmaf(nx, cn, ny * sn);
+    const float dsx = nx * iden, dsy = ny * iden;
+    const float dsq = fmaf(nx, Pxq, ny * Pyq) * iden;
+    const float dsp = fmaf(nx, Pxp, ny * Pyp) * iden;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) F[i][j] = 0.f;
+    F[0][0] = fmaf(cn, dsx, 1.f);
+    F[0][1] = cn * dsy;
+    F[0][3] = fmaf(cn, dsq, Pxq);
+    F[0][4] = fmaf(cn, dsp, Pxp);
+    F[1][0] = sn * dsx;
+    F[1][1] = fmaf(sn, dsy, 1.f);
+    F[1][3] = fmaf(sn, dsq, Pyq);
+    F[1][4] = fmaf(sn, dsp, Pyp);
+    F[2][0] = cot * dsx;
+    F[2][1] = cot * dsy;
+    F[2][3] = cot * dsq;
+    F[2][4] = cot * dsp;
+    F[2][5] = Pzt;
+    F[4][0] = w * dsx;
+    F[4][1] = w * dsy;
+    F[4][3] = fmaf(w, dsq, Ppq);
+    F[4][4] = fmaf(w, dsp, 1.f);
+    return true;
+}
+
+// Multiple scattering in a layer of x0 radiation lengths, crossed at the
+// state's position: Highland angle th0 with the path factor 1/|cos alpha|,
+// added to (q/pT, phi, theta) at fixed |p|.
+__device__ __forceinline__ void add_scattering(const float (&p)[6], float x0, float mass2, float (&c)[21])
+{
+    if (!(x0 > 0.f)) return;
+    const float x = p[0], y = p[1], q = p[3];
+    float sph, cph, sth, cth;
+    sincosf(p[4], &sph, &cph);
+    sincosf(p[5], &sth, &cth);
+    const float ir0 = rsqrtf(fmaf(x, x, y * y));
+    const float cosa = fmaxf(fabsf(sth * fmaf(cph, x * ir0, sph * y * ir0)), 1e-6f);
+    const float t = x0 / cosa;
+    const float k = fabsf(q) * sth;                           // 1/|p|
+    const float inv_bp = k * sqrtf(fmaf(mass2 * k, k, 1.f));  // 1/(beta p)
+    const float th0 = 0.0136f * inv_bp * sqrtf(t) * fmaf(0.038f, logf(t), 1.f);
+    const float v = th0 * th0;
+    const float ist = 1.f / sth;
+    const float cot = cth * ist;
+    c[sym(4, 4)] += v * ist * ist;
+    c[sym(5, 5)] += v;
+    c[sym(3, 3)] += q * q * cot * cot * v;
+    c[sym(3, 5)] -= q * cot * v;
+}
+
+// chi2 of a hit (cos phi_h, sin phi_h, z_h) against a predicted state: the
+// residual on the plane tangent to the layer at the hit, u along
+// (-sin phi_h, cos phi_h, 0) and z, with S = H C H^T + V.
+__device__ __forceinline__ float hit_chi2(const float (&p)[6], const float (&c)[21], float ch, float sh,
+                                          float zh, float var_u, float var_z)
+{
+    const float ru = fmaf(p[0], sh, -p[1] * ch);
+    const float rz = zh - p[2];
+    const float suu = fmaf(sh * sh, c[sym(0, 0)], fmaf(-2.f * sh * ch, c[sym(0, 1)], fmaf(ch * ch, c[sym(1, 1)], var_u)));
+    const float suz = fmaf(-sh, c[sym(0, 2)], ch * c[sym(1, 2)]);
+    const float szz = c[sym(2, 2)] + var_z;
+    const float idet = fast_rcp(fmaf(suu, szz, -suz * suz));
+    return fmaf(szz * ru, ru, fmaf(-2.f * suz * ru, rz, suu * rz * rz)) * idet;
+}
+
+// Kalman update with one hit.  K = C H^T S^-1, p += K r, C -= K (H C) on the
+// upper triangle (so C stays exactly symmetric).  Returns the hit's chi2.
+__device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], float ch, float sh, float zh,
+                                           float var_u, float var_z)
+{
+    const float ru = fmaf(p[0], sh, -p[1] * ch);
+    const float rz = zh - p[2];
+    float Mu[6], Mz[6];   // rows of H C
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        Mu[j] = fmaf(-sh, c[sym(0, j)], ch * c[sym(1, j)]);
+        Mz[j] = c[sym(2, j)];
+    }
+    const float suu = fmaf(-sh, Mu[0], fmaf(ch, Mu[1], var_u));
+    const float suz = Mu[2];
+    const float szz = Mz[2] + var_z;
+    const float idet = 1.f / fmaf(suu, szz, -suz * suz);
+    const float i00 = szz * idet, i01 = -suz * idet, i11 = suu * idet;
+    const float chi2 = fmaf(ru, fmaf(i00, ru, i01 * rz), rz * fmaf(i01, ru, i11 * rz));
+    float K0[6], K1[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        K0[j] = fmaf(Mu[j], i00, Mz[j] * i01);
+        K1[j] = fmaf(Mu[j], i01, Mz[j] * i11);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) p[j] = fmaf(K0[j], ru, fmaf(K1[j], rz, p[j]));
+    p[4] = wrap_pi(p[4]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) c[sym(i, j)] -= fmaf(K0[i], Mu[j], K1[i] * Mz[j]);
+    return chi2;
+}
+
+// Kalman update in Joseph form, C' = (I - K H) C (I - K H)^T + K V K^T.
+// Used where the prediction is much looser than the hit (a fit starting
+// from a wide prior): there C - K H C subtracts two nearly equal numbers and
+// loses FP32 digits, while the Joseph form only scales them by (I - K H).
+__device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21], float ch, float sh, float zh,
+                                                  float var_u, float var_z)
+{
+    const float ru = fmaf(p[0], sh, -p[1] * ch);
+    const float rz = zh - p[2];
+    float Mu[6], Mz[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        Mu[j] = fmaf(-sh, c[sym(0, j)], ch * c[sym(1, j)]);
+        Mz[j] = c[sym(2, j)];
+    }
+    const float suu = fmaf(-sh, Mu[0], fmaf(ch, Mu[1], var_u));
+    const float suz = Mu[2];
+    const float szz = Mz[2] + var_z;
+    const float idet = 1.f / fmaf(suu, szz, -suz * suz);
+    const float i00 = szz * idet, i01 = -suz * idet, i11 = suu * idet;
+    const float chi2 = fmaf(ru, fmaf(i00, ru, i01 * rz), rz * fmaf(i01, ru, i11 * rz));
+    float K0[6], K1[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        K0[j] = fmaf(Mu[j], i00, Mz[j] * i01);
+        K1[j] = fmaf(Mu[j], i01, Mz[j] * i11);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) p[j] = fmaf(K0[j], ru, fmaf(K1[j], rz, p[j]));
+    p[4] = wrap_pi(p[4]);
+    // one row of D = (I - K H) C at a time; the result goes to a fresh array
+    // because every row of D reads the old C
+    float nc[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        float D[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) D[j] = c[sym(i, j)] - fmaf(K0[i], Mu[j], K1[i] * Mz[j]);
+        const float du = fmaf(-sh, D[0], ch * D[1]);   // (D H^T)_iu
+        const float dz = D[2];                         // (D H^T)_iz
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            const float kvk = fmaf(var_u * K0[i], K0[j], var_z * K1[i] * K1[j]);
+            nc[sym(i, j)] = D[j] - fmaf(du, K0[j], dz * K1[j]) + kvk;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = nc[i];
+    return chi2;
+}
+
+// ---- beam ordering ---------------------------------------------------------
+// A child's rank key packs, most significant first: (31 - n_hits), the
+// candidate's summed chi2 (non-negative float bits order like the floats),
+// the parent's rank and the hit index (kHoleId for hole and stopped entries).
+// Smaller key = better; every key of a seed is distinct.
+__device__ __forceinline__ unsigned long long beam_key(int n_hits, float chi2, int parent, unsigned hit)
+{
+    return ((unsigned long long)(31 - n_hits) << 59) | ((unsigned long long)__float_as_uint(chi2) << 27) |
+           ((unsigned long long)parent << 24) | (unsigned long long)(hit & kHoleId);
+}
+__device__ __forceinline__ int key_nhits(unsigned long long k) { return 31 - (int)(k >> 59); }
+__device__ __forceinline__ float key_chi2(unsigned long long k) { return __uint_as_float((unsigned)(k >> 27)); }
+__device__ __forceinline__ int key_parent(unsigned long long k) { return (int)((k >> 24) & 7); }
+__device__ __forceinline__ unsigned key_hit(unsigned long long k) { return (unsigned)(k & kHoleId); }
+
+}  // namespace mkf

@@ -1,0 +1,118 @@
+// Internal structures shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mkf.h"
+
+namespace mkf {
+
+constexpr int kMaxLayers = MKF_MAX_LAYERS;
+constexpr int kMaxCands = MKF_MAX_CANDS;
+constexpr int kWave = 64;
+constexpr uint32_t kHoleId = 0xFFFFFFu;   // hit-id field of a hole or stopped entry
+constexpr int kMaxHitsPerLayer = 0xFFFFFE;
+
+// Per-layer geometry and the hit-index grid, in FP32 as the kernels use it.
+struct LayerParam {
+    float r;
+    float half_z;
+    float x0;
+    float inv_dphi;    // bins_phi / (2 pi)
+    float inv_dz;      // bins_z / (2 half_z)
+    float pad0, pad1, pad2;
+};
+
+// Building and fitting parameters for one launch.
+struct Params {
+    LayerParam layer[kMaxLayers];
+    int n_layers;
+    int n_seed_layers;
+    int max_cands;
+    int max_holes;
+    int hole_always;
+    int bins_phi;
+    int bins_z;
+    int pad;
+    float w_per_qpt;     // -kappa * B: curvature w = w_per_qpt * q/pT
+    float var_u;         // sigma_rphi^2
+    float var_z;         // sigma_z^2
+    float chi2_cut;
+    float mass2;         // scattering mass hypothesis squared
+    float win_scale;     // (1 + window margin)
+    float pad1, pad2;
+};
+
+// Device view of one loaded event.  All pointers are device pointers.
+struct DevEvent {
+    int n_layers;
+    int n_seeds;
+    int n_tracks;
+    int n_hits;                          // all layers
+    int layer_off[kMaxLayers + 1];       // first hit of each layer in the flat hit arrays
+    const double *raw_xyz;               // [n_hits][3] caller order
+    float4 *hits;                        // [n_hits] caller order: (cos phi_h, sin phi_h, z, 0)
+    float4 *binned;                      // [n_hits] grouped by layer then bin: (c, s, z, id bits)
+    int *bin_of;                         // [n_hits] bin of each caller-order hit
+    int *bin_count;                      // [n_layers][n_bins] counts, then scatter cursors
+    int *bin_off;                        // [n_layers][n_bins + 1] absolute index into `binned`
+    const double *seed_par;              // [n_seeds][6]
+    const double *seed_cov;              // [n_seeds][21]
+    const int *seed_hits;                // [n_seeds][n_seed_layers]
+    const double *track_par;             // [n_tracks][6]
+    const double *track_cov;             // [n_tracks][21]
+    const int *track_hits;               // [n_tracks][n_layers]
+    // build outputs
+    double *out_par;                     // [n_seeds][6]
+    double *out_cov;                     // [n_seeds][21]
+    int *out_hits;                       // [n_seeds][n_layers]
+    int *out_nhits;
+    int *out_nholes;
+    double *out_chi2;
+    int *out_status;
+    // fit outputs
+    double *fit_par;                     // [n_tracks][6]
+    double *fit_cov;                     // [n_tracks][21]
+    double *fit_chi2;
+    int *fit_nupd;
+    int *fit_status;
+    unsigned long long *stats;           // [5] mkf_build_stats counters
+    // plain per-layer builder state (slots = n_seeds * lanes_per_seed)
+    float *st_par;                       // [6][slots]
+    float *st_cov;                       // [21][slots]
+    float *st_chi2;                      // [slots]
+    int *st_meta;                        // [slots]
+    int *st_hist_hit;                    // [n_layers][slots]
+    unsigned char *st_hist_par;          // [n_layers][slots]
+    int st_slots;
+    int pad;
+};
+
+// A batch: events plus the flattened work decomposition over them.
+struct BatchArgs {
+    const DevEvent *events;
+    const int *item_prefix;      // [n_events + 1] work items (seed groups) before each event
+    const int *hit_prefix;       // [n_events + 1] hits before each event
+    const int *track_prefix;     // [n_events + 1] tracks before each event
+    unsigned int *queue;         // work-queue counter (persistent kernels)
+    int n_events;
+    int total_items;
+    int total_hits;
+    int total_tracks;
+    int seeds_per_item;
+    int pad;
+};
+
+// Launch helpers implemented in mkf_kernels.hip.
+hipError_t launch_fill_i32(int *ptr, int value, int n, hipStream_t s);
+hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s);
+hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s);
+hipError_t launch_build_batch(const Params &p, const BatchArgs &b, int lanes_per_seed, int waves_per_block,
+                              int persistent, int n_blocks, bool stats, hipStream_t s);
+hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const DevEvent &ev_host, int layer,
+                              int lanes_per_seed, int waves_per_block, bool stats, hipStream_t s);
+hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace mkf

@@ -1,0 +1,684 @@
+// HIP kernels of the barrel Kalman-filter track builder (gfx950).
+//
+// Layout: one lane = one track candidate.  A seed owns G consecutive lanes
+// (G = lanes_per_seed >= max_cands), so a wavefront carries 64/G seeds and a
+// seed's beam never leaves its wavefront: ranking and pruning use lane
+// shuffles only.  Candidate state (27 floats) lives in registers; the
+// per-layer choice of every kept candidate (parent rank, hit) is recorded in
+// LDS (batched builder) or device memory (per-layer builder) and unwound at
+// the end to produce the hit list.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mkf_device.hpp"
+
+namespace mkf {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ int upper_bound_i32(const int *a, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
+{
+    const unsigned lo = __shfl_xor((unsigned)v, m);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), m);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__global__ void k_fill_i32(int *__restrict__ p, int v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Plain streaming copy used to calibrate memory-traffic counters.
+__global__ void k_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Clears the per-event work counters and/or hit-index bin counts of a batch
+// (a kernel rather than a memset so that it can sit in a captured graph).
+__global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_stats, int do_bins)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (do_stats && g < B.n_events * 5) B.events[g / 5].stats[g % 5] = 0ull;
+    if (do_bins && g < B.n_events * n_bins_per_event) {
+        const int e = g / n_bins_per_event;
+        B.events[e].bin_count[g - e * n_bins_per_event] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hit index: per layer, hits are grouped by an (eta, phi) grid.  On a cylinder
+// eta is a function of z, so the grid is (z, phi): bin = iz * bins_phi + iphi.
+// A counting sort over all events of a batch at once.
+
+// Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it, count.
+__global__ void k_index_prep(const Params P, const BatchArgs B)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B.total_hits) return;
+    const int e = upper_bound_i32(B.hit_prefix, B.n_events + 1, g) - 1;
+    const DevEvent &E = B.events[e];
+    const int h = g - B.hit_prefix[e];
+    const int L = upper_bound_i32(E.layer_off, P.n_layers + 1, h) - 1;
+    const LayerParam lp = P.layer[L];
+    const double x = E.raw_xyz[3 * (size_t)h], y = E.raw_xyz[3 * (size_t)h + 1];
+    const double ir = 1.0 / sqrt(x * x + y * y);
+    const float c = (float)(x * ir), s = (float)(y * ir);
+    const float z = (float)E.raw_xyz[3 * (size_t)h + 2];
+    const float phi = atan2f(s, c);
+    int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
+    int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
+    ip = min(max(ip, 0), P.bins_phi - 1);
+    iz = min(max(iz, 0), P.bins_z - 1);
+    const int bin = iz * P.bins_phi + ip;
+    E.hits[h] = make_float4(c, s, z, 0.f);
+    E.bin_of[h] = bin;
+    atomicAdd(&E.bin_count[L * P.bins_phi * P.bins_z + bin], 1);
+}
+
+// Pass 2: one block per (event, layer): exclusive scan of the bin counts into
+// absolute offsets; counts are reset to serve as scatter cursors.
+__global__ void __launch_bounds__(1024) k_index_scan(const Params P, const BatchArgs B)
+{
+    __shared__ int s_sum[1024];
+    const int e = blockIdx.x / P.n_layers;
+    const int L = blockIdx.x - e * P.n_layers;
+    const DevEvent &E = B.events[e];
+    const int nb = P.bins_phi * P.bins_z;
+    int *cnt = E.bin_count + L * nb;
+    int *off = E.bin_off + L * (nb + 1);
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * per;
+    const int b1 = min(b0 + per, nb);
+    int local = 0;
+    for (int b = b0; b < b1; ++b) local += cnt[b];
+    s_sum[threadIdx.x] = local;
+    __syncthreads();
+    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        const int v = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = E.layer_off[L] + s_sum[threadIdx.x] - local;
+    for (int b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        off[b] = run;
+        cnt[b] = 0;
+        run += v;
+    }
+    if (threadIdx.x == blockDim.x - 1) off[nb] = E.layer_off[L + 1];
+}
+
+// Pass 3: scatter each hit into its bin (order inside a bin is irrelevant:
+// every hit of a window is tested and ties are broken by hit index).
+__global__ void k_index_scatter(const Params P, const BatchArgs B)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B.total_hits) return;
+    const int e = upper_bound_i32(B.hit_prefix, B.n_events + 1, g) - 1;
+    const DevEvent &E = B.events[e];
+    const int h = g - B.hit_prefix[e];
+    const int L = upper_bound_i32(E.layer_off, P.n_layers + 1, h) - 1;
+    const int nb = P.bins_phi * P.bins_z;
+    const int bin = E.bin_of[h];
+    const int pos = E.bin_off[L * (nb + 1) + bin] + atomicAdd(&E.bin_count[L * nb + bin], 1);
+    float4 v = E.hits[h];
+    v.w = __int_as_float(h - E.layer_off[L]);
+    E.binned[pos] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Track building
+
+struct Lane {
+    float p[6];
+    float c[21];
+    float chi2;
+    int n_hits;
+    int n_holes;
+    int status;
+    int live;
+    int stopped;
+};
+
+struct Hist {          // per-layer record of every kept candidate: (hit, parent rank)
+    int *hit;
+    unsigned char *par;
+    int stride;        // elements between layers
+    __device__ void put(int L, int lane, int h, int parent) const
+    {
+        hit[L * stride + lane] = h;
+        par[L * stride + lane] = (unsigned char)parent;
+    }
+};
+
+constexpr int kHitUnroll = 4;
+
+struct Count {
+    unsigned long long prop = 0, chi2 = 0, acc = 0, upd = 0, scan = 0;
+};
+
+template <int K>
+__device__ __forceinline__ void list_insert(float (&lc)[K], unsigned (&lid)[K], float c, unsigned id)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const bool less = (c < lc[i]) || (c == lc[i] && id < lid[i]);
+        const float tc = lc[i];
+        const unsigned ti = lid[i];
+        lc[i] = less ? c : tc;
+        lid[i] = less ? id : ti;
+        c = less ? tc : c;
+        id = less ? ti : id;
+    }
+}
+
+__device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Params &P, int seed, bool first_slot)
+{
+    S.live = first_slot ? 1 : 0;
+    S.stopped = 0;
+    S.status = 0;
+    S.n_holes = 0;
+    S.chi2 = 0.f;
+    S.n_hits = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.p[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 21; ++i) S.c[i] = 0.f;
+    if (!first_slot) return;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.p[i] = (float)E.seed_par[6 * (size_t)seed + i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) S.c[i] = (float)E.seed_cov[21 * (size_t)seed + i];
+    for (int L = 0; L < P.n_seed_layers; ++L) S.n_hits += E.seed_hits[(size_t)seed * P.n_seed_layers + L] >= 0;
+}
+
+// One building layer for every lane of a wavefront (Section 2: propagate the
+// candidate to the next layer, collect compatible hits, branch; Section
+// 3.2.1: re-rank and prune to max_cands per seed).
+template <int G, bool kStats>
+__device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
+                                           const int lane, const Hist &H, Count &cnt)
+{
+    constexpr int K = kMaxCands;
+    const int slot = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const LayerParam lp = P.layer[L];
+    const bool active = S.live && !S.stopped;
+
+    float pp[6], pc[21];    // state offered to this lane's children
+#pragma unroll
+    for (int i = 0; i < 6; ++i) pp[i] = S.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) pc[i] = S.c[i];
+
+    // 1. scattering of the layer being left, propagation, transport
+    bool predicted = false;
+    if (active) {
+        float np[6], F[6][6];
+        const bool ok = propagate(S.p, lp.r, P.w_per_qpt, np, F);
+        if (kStats) cnt.prop++;
+        if (ok) {
+            add_scattering(S.p, P.layer[L - 1].x0, P.mass2, pc);
+            transport(F, pc);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) pp[i] = np[i];
+            predicted = true;
+        } else {
+            S.stopped = 1;
+            S.status = 2;
+        }
+    }
+
+    // 2. windowed hit search: keep this lane's best K hit children
+    float lc[K];
+    unsigned lid[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        lc[i] = kInf;
+        lid[i] = 0xFFFFFFFFu;
+    }
+    int nacc = 0;
+    if (predicted) {
+        // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
+        // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
+        const float cxx = pc[sym(0, 0)], cxy = pc[sym(0, 1)], cyy = pc[sym(1, 1)];
+        const float hd = 0.5f * (cxx - cyy);
+        const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
+        const float du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
+        const float dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
+        const float phipos = atan2f(pp[1], pp[0]);
+        const float dphi = (du >= lp.r ? 0.5f * kPi : asinf(du / lp.r)) + 1e-5f;
+        const int nphi = P.bins_phi;
+        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
+            const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
+            const int ihi = (int)floorf((phipos + dphi + kPi) * lp.inv_dphi);
+            const int izlo = min(max((int)floorf((pp[2] - dz - 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
+            const int izhi = min(max((int)floorf((pp[2] + dz + 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
+            int s0lo, s0hi, s1lo = 1, s1hi = 0;
+            if (ihi - ilo + 1 >= nphi) {
+                s0lo = 0;
+                s0hi = nphi - 1;
+            } else if (ilo < 0) {
+                s0lo = ilo + nphi;
+                s0hi = nphi - 1;
+                s1lo = 0;
+                s1hi = ihi;
+            } else if (ihi >= nphi) {
+                s0lo = ilo;
+                s0hi = nphi - 1;
+                s1lo = 0;
+                s1hi = ihi - nphi;
+            } else {
+                s0lo = ilo;
+                s0hi = ihi;
+            }
+            const int *off = E.bin_off + L * (nphi * P.bins_z + 1);
+            const float4 *bh = E.binned;
+            for (int iz = izlo; iz <= izhi; ++iz) {
+                const int row = iz * nphi;
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int lo = sg ? s1lo : s0lo, hi = sg ? s1hi : s0hi;
+                    if (lo > hi) continue;
+                    const int beg = off[row + lo], end = off[row + hi + 1];
+                    for (int h0 = beg; h0 < end; h0 += kHitUnroll) {
+                        // issue the loads of several hits before using any (latency hiding)
+                        float4 hv[kHitUnroll];
+#pragma unroll
+                        for (int u = 0; u < kHitUnroll; ++u) hv[u] = bh[min(h0 + u, end - 1)];
+#pragma unroll
+                        for (int u = 0; u < kHitUnroll; ++u) {
+                            if (h0 + u >= end) break;
+                            if (kStats) cnt.scan++;
+                            if (fabsf(hv[u].z - pp[2]) > dz) continue;
+                            if (fabsf(fmaf(pp[0], hv[u].y, -pp[1] * hv[u].x)) > du) continue;
+                            if (fmaf(pp[0], hv[u].x, pp[1] * hv[u].y) <= 0.f) continue;
+                            if (kStats) cnt.chi2++;
+                            const float c2 = hit_chi2(pp, pc, hv[u].x, hv[u].y, hv[u].z, P.var_u, P.var_z);
+                            if (c2 < P.chi2_cut) {
+                                ++nacc;
+                                list_insert<K>(lc, lid, S.chi2 + c2, (unsigned)__float_as_int(hv[u].w));
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (kStats) cnt.acc += nacc;
+    }
+
+    // 3. hole child, or stop on this surface when neither a hit nor a hole is left
+    const bool hole = predicted && (nacc == 0 || P.hole_always) && S.n_holes < P.max_holes;
+    if (predicted && nacc == 0 && S.n_holes >= P.max_holes) {
+        S.stopped = 1;
+        S.status = 1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) S.p[i] = pp[i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) S.c[i] = pc[i];
+    }
+    bool tail = S.live && (S.stopped || hole);
+    const unsigned long long tail_key = beam_key(S.n_hits, S.chi2, slot, kHoleId);
+    const int child_hits = S.n_hits + 1;
+
+    // 4. keep the max_cands best entries of the seed: repeated group minimum
+    unsigned long long mine = ~0ull;
+    for (int r = 0; r < P.max_cands; ++r) {
+        unsigned long long hk = ~0ull;
+        if (S.live) {
+            if (lc[0] < kInf) hk = beam_key(child_hits, lc[0], slot, lid[0]);
+            else if (tail) hk = tail_key;
+        }
+        unsigned long long m = hk;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const unsigned long long t = shfl_xor_u64(m, o);
+            m = t < m ? t : m;
+        }
+        if (hk == m && m != ~0ull) {
+            if (lc[0] < kInf) {
+#pragma unroll
+                for (int i = 0; i < K - 1; ++i) {
+                    lc[i] = lc[i + 1];
+                    lid[i] = lid[i + 1];
+                }
+                lc[K - 1] = kInf;
+            } else {
+                tail = false;
+            }
+        }
+        if (slot == r) mine = m;
+    }
+
+    // 5. each kept entry moves to the lane of its rank: fetch the parent's
+    //    state and apply the Kalman update with the entry's hit
+    const bool alive = mine != ~0ull;
+    const int parent = alive ? key_parent(mine) : slot;
+    const int src = gbase + parent;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.p[i] = __shfl(pp[i], src);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) S.c[i] = __shfl(pc[i], src);
+    const int p_holes = __shfl(S.n_holes, src);
+    const int p_stopped = __shfl(S.stopped, src);
+    const int p_status = __shfl(S.status, src);
+    S.live = alive;
+    if (!alive) return;
+    const unsigned hid = key_hit(mine);
+    S.n_hits = key_nhits(mine);
+    S.chi2 = key_chi2(mine);
+    S.n_holes = p_holes;
+    S.stopped = p_stopped;
+    S.status = p_status;
+    if (hid != kHoleId) {
+        const float4 hv = E.hits[E.layer_off[L] + (int)hid];
+        kf_update(S.p, S.c, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+        if (kStats) cnt.upd++;
+        H.put(L, lane, (int)hid, parent);
+    } else {
+        if (!p_stopped) S.n_holes += 1;
+        H.put(L, lane, -1, parent);
+    }
+}
+
+// Rank-0 candidate of each seed to the output arrays, hit list unwound
+// through the per-layer records.
+template <int G>
+__device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, const DevEvent &E, int lane,
+                                              int seed, const Hist &H)
+{
+    const int gbase = lane & ~(G - 1);
+    if ((lane & (G - 1)) != 0 || seed >= E.n_seeds) return;
+    const size_t s = (size_t)seed;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) E.out_par[6 * s + i] = (double)S.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) E.out_cov[21 * s + i] = (double)S.c[i];
+    E.out_chi2[s] = (double)S.chi2;
+    E.out_nhits[s] = S.n_hits;
+    E.out_nholes[s] = S.n_holes;
+    E.out_status[s] = S.status;
+    int *oh = E.out_hits + s * P.n_layers;
+    for (int L = 0; L < P.n_seed_layers; ++L) oh[L] = E.seed_hits[s * P.n_seed_layers + L];
+    int cur = 0;
+    for (int L = P.n_layers - 1; L >= P.n_seed_layers; --L) {
+        oh[L] = H.hit[L * H.stride + gbase + cur];
+        cur = H.par[L * H.stride + gbase + cur];
+    }
+}
+
+template <bool kStats>
+__device__ __forceinline__ void flush_counts(const Count &cnt, const DevEvent &E, int lane)
+{
+    if (!kStats) return;
+    unsigned long long v[5] = {cnt.prop, cnt.chi2, cnt.acc, cnt.upd, cnt.scan};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[j] += shfl_xor_u64(v[j], o);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) atomicAdd(&E.stats[j], v[j]);
+    }
+}
+
+// Batched builder.  Each wavefront takes work items (event, group of 64/G
+// seeds) - from a device counter when persistent, else from its block index -
+// and runs every building layer of its seeds with the state in registers.
+template <int G, bool kStats>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_batch(const Params P, const BatchArgs B, int persistent)
+{
+    extern __shared__ int s_dyn[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const int per_wave = P.n_layers * kWave;
+    Hist H{s_dyn + wave * per_wave, reinterpret_cast<unsigned char *>(s_dyn + W * per_wave) + wave * per_wave,
+           kWave};
+    int item = blockIdx.x * W + wave;
+    for (;;) {
+        if (persistent) {
+            unsigned v = 0;
+            if (lane == 0) v = atomicAdd(B.queue, 1u);
+            item = (int)__shfl(v, 0);
+        }
+        item = uniform(item);
+        if (item >= B.total_items) break;
+        const int e = uniform(upper_bound_i32(B.item_prefix, B.n_events + 1, item) - 1);
+        const DevEvent &E = B.events[e];
+        const int seed = (item - B.item_prefix[e]) * B.seeds_per_item + lane / G;
+        const bool valid = seed < E.n_seeds;
+        Lane S;
+        init_lane(S, E, P, valid ? seed : 0, valid && (lane & (G - 1)) == 0);
+        Count cnt;
+        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats>(S, L, P, E, lane, H, cnt);
+        finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
+        flush_counts<kStats>(cnt, E, lane);
+        if (!persistent) break;
+    }
+}
+
+// Per-layer builder: one event, one layer per launch, candidate state in
+// device memory (structure of arrays, slot = seed * G + rank) between layers.
+template <int G, bool kStats>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
+{
+    const DevEvent &E = *Ep;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    constexpr int kSeedsPerWave = kWave / G;
+    const int first = item * kSeedsPerWave;
+    if (first >= E.n_seeds) return;
+    const int seed = first + lane / G;
+    const bool valid = seed < E.n_seeds;
+    const int ns = E.st_slots;
+    const int slot = item * kWave + lane;
+    Hist H{E.st_hist_hit + item * kWave, E.st_hist_par + item * kWave, ns};
+    Lane S;
+    if (L == P.n_seed_layers) {
+        init_lane(S, E, P, valid ? seed : 0, valid && (lane & (G - 1)) == 0);
+    } else {
+        const int meta = E.st_meta[slot];
+        S.live = meta & 1;
+        S.stopped = (meta >> 1) & 1;
+        S.status = (meta >> 2) & 3;
+        S.n_hits = (meta >> 4) & 31;
+        S.n_holes = (meta >> 9) & 15;
+        S.chi2 = E.st_chi2[slot];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) S.p[i] = S.live ? E.st_par[i * ns + slot] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 21; ++i) S.c[i] = S.live ? E.st_cov[i * ns + slot] : 0.f;
+    }
+    Count cnt;
+    layer_step<G, kStats>(S, L, P, E, lane, H, cnt);
+    if (L == P.n_layers - 1) {
+        finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
+    } else {
+        E.st_meta[slot] = S.live | (S.stopped << 1) | (S.status << 2) | (S.n_hits << 4) | (S.n_holes << 9);
+        E.st_chi2[slot] = S.chi2;
+        if (S.live) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) E.st_par[i * ns + slot] = S.p[i];
+#pragma unroll
+            for (int i = 0; i < 21; ++i) E.st_cov[i * ns + slot] = S.c[i];
+        }
+    }
+    flush_counts<kStats>(cnt, E, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Fit with known hits: one lane per track, no branching beyond skipped layers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B.total_tracks) return;
+    const int e = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
+    const DevEvent &E = B.events[e];
+    const size_t t = (size_t)(g - B.track_prefix[e]);
+    float p[6], c[21], op[6], oc[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) op[i] = p[i] = (float)E.track_par[6 * t + i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) oc[i] = c[i] = (float)E.track_cov[21 * t + i];
+    float chi2 = 0.f;
+    int nupd = 0, status = 0;
+    for (int L = 0; L < P.n_layers; ++L) {
+        if (L > 0) {
+            float np[6], F[6][6];
+            if (!propagate(p, P.layer[L].r, P.w_per_qpt, np, F)) {
+                status = 2;
+                break;
+            }
+            add_scattering(p, P.layer[L - 1].x0, P.mass2, c);
+            transport(F, c);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) p[i] = np[i];
+        }
+        const int h = E.track_hits[t * P.n_layers + L];
+        if (h >= 0) {
+            const float4 hv = E.hits[E.layer_off[L] + h];
+            // Joseph form: a fit starts from a wide prior, where the plain
+            // form C - K H C would lose FP32 digits
+            chi2 += kf_update_joseph(p, c, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+            ++nupd;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) op[i] = p[i];
+#pragma unroll
+            for (int i = 0; i < 21; ++i) oc[i] = c[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) E.fit_par[6 * t + i] = (double)op[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) E.fit_cov[21 * t + i] = (double)oc[i];
+    E.fit_chi2[t] = (double)chi2;
+    E.fit_nupd[t] = nupd;
+    E.fit_status[t] = status;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_fill_i32(int *ptr, int value, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<blocks_for(n, 256), 256, 0, s>>>(ptr, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 64);
+    k_copy16<<<grid, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s)
+{
+    const int nb = p.n_layers * p.bins_phi * p.bins_z;
+    const long long n = std::max<long long>(stats ? 5LL * b.n_events : 0, bins ? (long long)nb * b.n_events : 0);
+    if (n <= 0) return hipSuccess;
+    k_batch_zero<<<blocks_for(n, 256), 256, 0, s>>>(b, nb, stats ? 1 : 0, bins ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
+{
+    if (b.total_hits <= 0) return hipSuccess;
+    k_index_prep<<<blocks_for(b.total_hits, 256), 256, 0, s>>>(p, b);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_index_scan<<<(unsigned)(b.n_events * p.n_layers), 1024, 0, s>>>(p, b);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_index_scatter<<<blocks_for(b.total_hits, 256), 256, 0, s>>>(p, b);
+    return hipGetLastError();
+}
+
+template <int G, bool kStats>
+static hipError_t launch_batch_t(const Params &p, const BatchArgs &b, int wpb, int persistent, int n_blocks,
+                                 hipStream_t s)
+{
+    const size_t lds = (size_t)wpb * p.n_layers * kWave * (sizeof(int) + 1);
+    const unsigned grid = persistent ? (unsigned)n_blocks : blocks_for(b.total_items, wpb);
+    if (grid == 0) return hipSuccess;
+    k_build_batch<G, kStats><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_batch(const Params &p, const BatchArgs &b, int G, int wpb, int persistent, int n_blocks,
+                              bool stats, hipStream_t s)
+{
+    switch (G * 2 + (stats ? 1 : 0)) {
+    case 2: return launch_batch_t<1, false>(p, b, wpb, persistent, n_blocks, s);
+    case 3: return launch_batch_t<1, true>(p, b, wpb, persistent, n_blocks, s);
+    case 4: return launch_batch_t<2, false>(p, b, wpb, persistent, n_blocks, s);
+    case 5: return launch_batch_t<2, true>(p, b, wpb, persistent, n_blocks, s);
+    case 8: return launch_batch_t<4, false>(p, b, wpb, persistent, n_blocks, s);
+    case 9: return launch_batch_t<4, true>(p, b, wpb, persistent, n_blocks, s);
+    case 16: return launch_batch_t<8, false>(p, b, wpb, persistent, n_blocks, s);
+    case 17: return launch_batch_t<8, true>(p, b, wpb, persistent, n_blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int G, bool kStats>
+static hipError_t launch_layer_t(const Params &p, const DevEvent *ev_dev, int n_seeds, int L, int wpb,
+                                 hipStream_t s)
+{
+    const int items = (n_seeds + kWave / G - 1) / (kWave / G);
+    const unsigned grid = blocks_for(items, wpb);
+    if (grid == 0) return hipSuccess;
+    k_build_layer<G, kStats><<<grid, wpb * kWave, 0, s>>>(p, ev_dev, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const DevEvent &ev_host, int L, int G,
+                              int wpb, bool stats, hipStream_t s)
+{
+    const int n = ev_host.n_seeds;
+    switch (G * 2 + (stats ? 1 : 0)) {
+    case 2: return launch_layer_t<1, false>(p, ev_dev, n, L, wpb, s);
+    case 3: return launch_layer_t<1, true>(p, ev_dev, n, L, wpb, s);
+    case 4: return launch_layer_t<2, false>(p, ev_dev, n, L, wpb, s);
+    case 5: return launch_layer_t<2, true>(p, ev_dev, n, L, wpb, s);
+    case 8: return launch_layer_t<4, false>(p, ev_dev, n, L, wpb, s);
+    case 9: return launch_layer_t<4, true>(p, ev_dev, n, L, wpb, s);
+    case 16: return launch_layer_t<8, false>(p, ev_dev, n, L, wpb, s);
+    case 17: return launch_layer_t<8, true>(p, ev_dev, n, L, wpb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)
+{
+    if (b.total_tracks <= 0) return hipSuccess;
+    k_fit<<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
+    return hipGetLastError();
+}
+
+}  // namespace mkf

@@ -1,0 +1,1174 @@
+// Host runtime and C ABI of the track builder (everything except serving).
+#include "mkf_runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace mkf {
+
+static thread_local char g_err[512] = "";
+
+mkf_status fail(mkf_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+// ---------------------------------------------------------------- memory
+
+void *CtxHeap::alloc(size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (ctx->has_alloc) return ctx->alloc.alloc(bytes, (void *)ctx->stream, ctx->alloc.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void CtxHeap::release(void *p)
+{
+    if (!p) return;
+    if (ctx->has_alloc) ctx->alloc.free(p, (void *)ctx->stream, ctx->alloc.user);
+    else (void)hipFree(p);
+}
+
+SlabHeap::SlabHeap(char *base, size_t bytes) : base_(base), cap_(bytes) { free_[0] = bytes; }
+
+void *SlabHeap::alloc(size_t bytes)
+{
+    bytes = (bytes + 255) & ~size_t(255);
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        taken_[off] = bytes;
+        used_ += bytes;
+        return base_ + off;
+    }
+    return nullptr;
+}
+
+void SlabHeap::release(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    const size_t off = static_cast<char *>(p) - base_;
+    auto t = taken_.find(off);
+    if (t == taken_.end()) return;
+    size_t sz = t->second;
+    taken_.erase(t);
+    used_ -= sz;
+    size_t start = off;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + sz) {
+        sz += nx->second;
+        free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            start = pv->first;
+            sz += pv->second;
+            free_.erase(pv);
+        }
+    }
+    free_[start] = sz;
+}
+
+// ---------------------------------------------------------------- layout
+
+namespace {
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_view)
+{
+    Carver c(base);
+    const size_t n = (size_t)s.n_hits(), ns = (size_t)s.n_seeds, nt = (size_t)s.n_tracks, nl = (size_t)s.n_layers;
+    v->raw_xyz = c.take<double>(3 * n);
+    v->hits = c.take<float4>(n);
+    v->binned = c.take<float4>(n);
+    v->bin_of = c.take<int>(n);
+    v->seed_par = c.take<double>(6 * ns);
+    v->seed_cov = c.take<double>(21 * ns);
+    v->seed_hits = c.take<int>((size_t)s.n_seed_layers * ns);
+    v->track_par = c.take<double>(6 * nt);
+    v->track_cov = c.take<double>(21 * nt);
+    v->track_hits = c.take<int>(nl * nt);
+    v->out_par = c.take<double>(6 * ns);
+    v->out_cov = c.take<double>(21 * ns);
+    v->out_hits = c.take<int>(nl * ns);
+    v->out_nhits = c.take<int>(ns);
+    v->out_nholes = c.take<int>(ns);
+    v->out_chi2 = c.take<double>(ns);
+    v->out_status = c.take<int>(ns);
+    v->fit_par = c.take<double>(6 * nt);
+    v->fit_cov = c.take<double>(21 * nt);
+    v->fit_chi2 = c.take<double>(nt);
+    v->fit_nupd = c.take<int>(nt);
+    v->fit_status = c.take<int>(nt);
+    v->stats = c.take<unsigned long long>(5);
+    DevEvent *dv = c.take<DevEvent>(1);
+    if (dev_view) *dev_view = dv;
+    return c.off;
+}
+
+size_t carve_index(const EventShape &s, int nb, void *base, DevEvent *v)
+{
+    Carver c(base);
+    v->bin_count = c.take<int>((size_t)s.n_layers * nb);
+    v->bin_off = c.take<int>((size_t)s.n_layers * (nb + 1));
+    return c.off;
+}
+
+int plain_slots(int n_seeds, int G)
+{
+    const int spw = kWave / G;
+    return ((n_seeds + spw - 1) / spw) * kWave;
+}
+
+size_t carve_plain(const EventShape &s, int slots, void *base, DevEvent *v)
+{
+    Carver c(base);
+    const size_t S = (size_t)slots;
+    v->st_par = c.take<float>(6 * S);
+    v->st_cov = c.take<float>(21 * S);
+    v->st_chi2 = c.take<float>(S);
+    v->st_meta = c.take<int>(S);
+    v->st_hist_hit = c.take<int>((size_t)s.n_layers * S);
+    v->st_hist_par = c.take<unsigned char>((size_t)s.n_layers * S);
+    v->st_slots = slots;
+    return c.off;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+void derive_params(mkf_ctx *ctx)
+{
+    Params &P = ctx->params;
+    const mkf_config &c = ctx->cfg;
+    const mkf_tuning &t = ctx->tuning;
+    std::memset(&P, 0, sizeof(P));
+    for (int L = 0; L < c.n_layers; ++L) {
+        P.layer[L].r = (float)c.layer_r[L];
+        P.layer[L].half_z = (float)c.layer_half_z[L];
+        P.layer[L].x0 = (float)c.layer_x0[L];
+        P.layer[L].inv_dphi = (float)(t.bins_phi / (2.0 * M_PI));
+        P.layer[L].inv_dz = (float)(t.bins_z / (2.0 * c.layer_half_z[L]));
+    }
+    P.n_layers = c.n_layers;
+    P.n_seed_layers = c.n_seed_layers;
+    P.max_cands = c.max_cands;
+    P.max_holes = c.max_holes;
+    P.hole_always = (c.flags & MKF_HOLE_ALWAYS) ? 1 : 0;
+    P.bins_phi = t.bins_phi;
+    P.bins_z = t.bins_z;
+    P.w_per_qpt = (float)(-0.00299792458 * c.bz);
+    P.var_u = (float)(c.sigma_rphi * c.sigma_rphi);
+    P.var_z = (float)(c.sigma_z * c.sigma_z);
+    P.chi2_cut = (float)c.chi2_cut;
+    P.mass2 = (float)(c.mass * c.mass);
+    P.win_scale = 1.05f;
+}
+
+mkf_status check_config(const mkf_config *c)
+{
+    if (!c) return fail(MKF_E_INVALID, "config is NULL");
+    if (c->n_seed_layers < 1 || c->n_layers <= c->n_seed_layers || c->n_layers > kMaxLayers)
+        return fail(MKF_E_INVALID, "need 1 <= n_seed_layers < n_layers <= %d", kMaxLayers);
+    if (c->max_cands < 1 || c->max_cands > kMaxCands) return fail(MKF_E_INVALID, "max_cands must be 1..%d", kMaxCands);
+    if (c->max_holes < 0 || c->max_holes > 7) return fail(MKF_E_INVALID, "max_holes must be 0..7");
+    if (c->flags & ~MKF_HOLE_ALWAYS) return fail(MKF_E_INVALID, "unknown config flags");
+    for (int L = 0; L < c->n_layers; ++L) {
+        if (!(c->layer_r[L] > 0) || !std::isfinite(c->layer_r[L]) || (L > 0 && !(c->layer_r[L] > c->layer_r[L - 1])))
+            return fail(MKF_E_INVALID, "layer radii must be positive and increasing");
+        if (!(c->layer_half_z[L] > 0) || !std::isfinite(c->layer_half_z[L]))
+            return fail(MKF_E_INVALID, "layer_half_z must be positive");
+        if (!(c->layer_x0[L] >= 0) || !std::isfinite(c->layer_x0[L])) return fail(MKF_E_INVALID, "layer_x0 must be >= 0");
+    }
+    if (!std::isfinite(c->bz)) return fail(MKF_E_INVALID, "bz must be finite");
+    if (!(c->sigma_rphi > 0) || !(c->sigma_z > 0) || !std::isfinite(c->sigma_rphi) || !std::isfinite(c->sigma_z))
+        return fail(MKF_E_INVALID, "hit resolutions must be positive");
+    if (!(c->chi2_cut > 0) || !std::isfinite(c->chi2_cut)) return fail(MKF_E_INVALID, "chi2_cut must be positive");
+    if (!(c->mass >= 0) || !std::isfinite(c->mass)) return fail(MKF_E_INVALID, "mass must be >= 0");
+    return MKF_OK;
+}
+
+mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
+{
+    if (t->lanes_per_seed == 0) {
+        int G = 1;
+        while (G < c.max_cands) G <<= 1;
+        t->lanes_per_seed = G;
+    }
+    const int G = t->lanes_per_seed;
+    if (G != 1 && G != 2 && G != 4 && G != 8) return fail(MKF_E_INVALID, "lanes_per_seed must be 1, 2, 4 or 8");
+    if (G < c.max_cands) return fail(MKF_E_INVALID, "lanes_per_seed must be >= max_cands");
+    if (t->waves_per_block == 0) t->waves_per_block = 4;
+    if (t->waves_per_block < 1 || t->waves_per_block > 4) return fail(MKF_E_INVALID, "waves_per_block must be 1..4");
+    if (t->bins_phi == 0) t->bins_phi = 256;
+    if (t->bins_z == 0) t->bins_z = 16;
+    if (t->bins_phi < 1 || t->bins_phi > 4096 || t->bins_z < 1 || t->bins_z > 1024 ||
+        (long long)t->bins_phi * t->bins_z > (1 << 20))
+        return fail(MKF_E_INVALID, "bins out of range (phi 1..4096, z 1..1024, product <= 2^20)");
+    if (t->persistent != 0 && t->persistent != 1) return fail(MKF_E_INVALID, "persistent must be 0 or 1");
+    if (t->blocks_per_cu == 0) t->blocks_per_cu = 8;
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 32) return fail(MKF_E_INVALID, "blocks_per_cu must be 1..32");
+    return MKF_OK;
+}
+
+void timer_begin(mkf_ctx *ctx, int which, hipStream_t s)
+{
+    Timer &t = ctx->timers[which];
+    if (s != ctx->stream || t.pending) return;
+    (void)hipEventRecord(t.start, s);
+}
+
+void timer_end(mkf_ctx *ctx, int which, hipStream_t s, long long launches)
+{
+    Timer &t = ctx->timers[which];
+    if (s != ctx->stream || t.pending) return;
+    (void)hipEventRecord(t.stop, s);
+    t.pending = true;
+    t.pending_launches = launches;
+}
+
+void timers_collect(mkf_ctx *ctx)
+{
+    for (auto &t : ctx->timers) {
+        if (!t.pending) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            t.total_ms += ms;
+            t.launches += t.pending_launches;
+        }
+        t.pending = false;
+    }
+}
+
+EventRec *find_event(mkf_ctx *ctx, int32_t h)
+{
+    auto it = ctx->events.find(h);
+    return it == ctx->events.end() ? nullptr : it->second.get();
+}
+
+void drop_graphs_with(mkf_ctx *ctx, int32_t handle)
+{
+    auto &g = ctx->graphs;
+    for (size_t i = 0; i < g.size();) {
+        const bool hit = handle < 0 || std::find(g[i]->handles.begin(), g[i]->handles.end(), handle) != g[i]->handles.end();
+        if (hit) {
+            (void)hipGraphExecDestroy(g[i]->exec);
+            ctx->heap.release(g[i]->scratch);
+            g.erase(g.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+void drop_plain_graph(EventRec *rec)
+{
+    if (rec->plain_graph) (void)hipGraphExecDestroy(rec->plain_graph);
+    rec->plain_graph = nullptr;
+}
+
+mkf_status upload_view(EventRec *rec, hipStream_t s)
+{
+    MKF_HIP(hipMemcpyAsync(rec->dev_view, &rec->view, sizeof(DevEvent), hipMemcpyHostToDevice, s));
+    MKF_HIP(hipStreamSynchronize(s));
+    return MKF_OK;
+}
+
+mkf_status ensure_batch_scratch(mkf_ctx *ctx, int n)
+{
+    const size_t need = batch_scratch_bytes(n);
+    if (ctx->batch_dev_bytes < need) {
+        ctx->heap.release(ctx->batch_dev);
+        ctx->batch_dev = ctx->heap.alloc(need);
+        ctx->batch_dev_bytes = ctx->batch_dev ? need : 0;
+        if (!ctx->batch_dev) return fail(MKF_E_NOMEM, "batch scratch of %zu bytes", need);
+    }
+    if (ctx->batch_host_bytes < need) {
+        if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+        ctx->batch_host = nullptr;
+        ctx->batch_host_bytes = 0;
+        MKF_HIP(hipHostMalloc(&ctx->batch_host, need, hipHostMallocDefault));
+        ctx->batch_host_bytes = need;
+    }
+    return MKF_OK;
+}
+
+mkf_status gather_events(mkf_ctx *ctx, const int32_t *handles, int32_t n, std::vector<EventRec *> *recs)
+{
+    if (n < 0 || (n > 0 && !handles)) return fail(MKF_E_INVALID, "bad handle list");
+    std::vector<int32_t> seen(handles, handles + n);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return fail(MKF_E_INVALID, "an event appears twice in the batch");
+    recs->clear();
+    for (int i = 0; i < n; ++i) {
+        EventRec *r = find_event(ctx, handles[i]);
+        if (!r) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handles[i]);
+        recs->push_back(r);
+    }
+    return MKF_OK;
+}
+
+}  // namespace
+
+size_t event_data_bytes(const EventShape &s)
+{
+    DevEvent v{};
+    return carve_data(s, nullptr, &v, nullptr);
+}
+
+size_t event_index_bytes(const EventShape &s, int nb)
+{
+    DevEvent v{};
+    return carve_index(s, nb, nullptr, &v);
+}
+
+size_t batch_scratch_bytes(int n)
+{
+    size_t b = ((size_t)n * sizeof(DevEvent) + 255) & ~size_t(255);
+    b += 3 * (((size_t)(n + 1) * sizeof(int) + 255) & ~size_t(255));
+    return b + 256;
+}
+
+int resolve_lanes(const mkf_ctx *ctx) { return ctx->tuning.lanes_per_seed; }
+int seeds_per_item(int G) { return kWave / G; }
+
+// ---------------------------------------------------------------- events
+
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape)
+{
+    const mkf_config &c = ctx->cfg;
+    if (!ev) return fail(MKF_E_INVALID, "event is NULL");
+    if (ev->n_layers != c.n_layers) return fail(MKF_E_INVALID, "event has %d layers, config %d", ev->n_layers, c.n_layers);
+    if (ev->n_seeds < 0 || ev->n_tracks < 0) return fail(MKF_E_INVALID, "negative seed or track count");
+    if (!ev->n_hits || !ev->hit_xyz) return fail(MKF_E_INVALID, "n_hits / hit_xyz is NULL");
+    EventShape s;
+    s.n_layers = c.n_layers;
+    s.n_seed_layers = c.n_seed_layers;
+    s.n_seeds = ev->n_seeds;
+    s.n_tracks = ev->n_tracks;
+    long long tot = 0;
+    for (int L = 0; L < c.n_layers; ++L) {
+        const int n = ev->n_hits[L];
+        if (n < 0 || n > kMaxHitsPerLayer) return fail(MKF_E_INVALID, "layer %d: %d hits out of range", L, n);
+        if (n > 0 && !ev->hit_xyz[L]) return fail(MKF_E_INVALID, "layer %d: hit_xyz is NULL", L);
+        const double *h = ev->hit_xyz[L];
+        for (int i = 0; i < n; ++i) {
+            const double x = h[3 * i], y = h[3 * i + 1], z = h[3 * i + 2];
+            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z) || !(x * x + y * y > 0))
+                return fail(MKF_E_INVALID, "layer %d hit %d: not finite or on the axis", L, i);
+        }
+        s.layer_off[L] = (int)tot;
+        tot += n;
+        if (tot > (1LL << 30)) return fail(MKF_E_INVALID, "too many hits in one event");
+    }
+    s.layer_off[c.n_layers] = (int)tot;
+    const int nsl = c.n_seed_layers;
+    if (ev->n_seeds > 0) {
+        if (!ev->seed_par || !ev->seed_cov || !ev->seed_hits) return fail(MKF_E_INVALID, "seed arrays are NULL");
+        if (!finite_all(ev->seed_par, 6 * (size_t)ev->n_seeds) || !finite_all(ev->seed_cov, 21 * (size_t)ev->n_seeds))
+            return fail(MKF_E_INVALID, "seed state or covariance not finite");
+        for (int i = 0; i < ev->n_seeds; ++i) {
+            const double *p = ev->seed_par + 6 * (size_t)i;
+            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
+                return fail(MKF_E_INVALID, "seed %d: theta outside (0, pi) or position on the axis", i);
+            for (int L = 0; L < nsl; ++L) {
+                const int h = ev->seed_hits[(size_t)i * nsl + L];
+                if (h < -1 || h >= ev->n_hits[L]) return fail(MKF_E_INVALID, "seed %d: hit index out of range", i);
+            }
+        }
+    }
+    if (ev->n_tracks > 0) {
+        if (!ev->track_par || !ev->track_cov || !ev->track_hits) return fail(MKF_E_INVALID, "track arrays are NULL");
+        if (!finite_all(ev->track_par, 6 * (size_t)ev->n_tracks) ||
+            !finite_all(ev->track_cov, 21 * (size_t)ev->n_tracks))
+            return fail(MKF_E_INVALID, "track state or covariance not finite");
+        for (int i = 0; i < ev->n_tracks; ++i) {
+            const double *p = ev->track_par + 6 * (size_t)i;
+            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
+                return fail(MKF_E_INVALID, "track %d: theta outside (0, pi) or position on the axis", i);
+            for (int L = 0; L < c.n_layers; ++L) {
+                const int h = ev->track_hits[(size_t)i * c.n_layers + L];
+                if (h < -1 || h >= ev->n_hits[L]) return fail(MKF_E_INVALID, "track %d: hit index out of range", i);
+            }
+        }
+    }
+    *shape = s;
+    return MKF_OK;
+}
+
+mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap, std::unique_ptr<EventRec> *out)
+{
+    auto rec = std::make_unique<EventRec>();
+    rec->shape = shape;
+    rec->heap = heap;
+    const size_t bytes = event_data_bytes(shape);
+    rec->data = heap->alloc(bytes);
+    if (!rec->data) return fail(MKF_E_NOMEM, "event data: %zu bytes", bytes);
+    DevEvent &v = rec->view;
+    std::memset(&v, 0, sizeof(v));
+    carve_data(shape, rec->data, &v, &rec->dev_view);
+    v.n_layers = shape.n_layers;
+    v.n_seeds = shape.n_seeds;
+    v.n_tracks = shape.n_tracks;
+    v.n_hits = shape.n_hits();
+    for (int L = 0; L <= shape.n_layers; ++L) v.layer_off[L] = shape.layer_off[L];
+    (void)ctx;
+    *out = std::move(rec);
+    return MKF_OK;
+}
+
+mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s)
+{
+    (void)ctx;
+    const EventShape &sh = rec->shape;
+    DevEvent &v = rec->view;
+    for (int L = 0; L < sh.n_layers; ++L) {
+        const size_t n = (size_t)ev->n_hits[L];
+        if (n)
+            MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.raw_xyz) + 3 * (size_t)sh.layer_off[L], ev->hit_xyz[L],
+                                   3 * n * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    const size_t ns = (size_t)sh.n_seeds, nt = (size_t)sh.n_tracks;
+    if (ns) {
+        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_par), ev->seed_par, 6 * ns * 8, hipMemcpyHostToDevice, s));
+        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_cov), ev->seed_cov, 21 * ns * 8, hipMemcpyHostToDevice, s));
+        MKF_HIP(hipMemcpyAsync(const_cast<int *>(v.seed_hits), ev->seed_hits, (size_t)sh.n_seed_layers * ns * 4,
+                               hipMemcpyHostToDevice, s));
+    }
+    if (nt) {
+        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.track_par), ev->track_par, 6 * nt * 8, hipMemcpyHostToDevice, s));
+        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.track_cov), ev->track_cov, 21 * nt * 8, hipMemcpyHostToDevice, s));
+        MKF_HIP(hipMemcpyAsync(const_cast<int *>(v.track_hits), ev->track_hits, (size_t)sh.n_layers * nt * 4,
+                               hipMemcpyHostToDevice, s));
+    }
+    return MKF_OK;
+}
+
+void destroy_event(mkf_ctx *ctx, EventRec *rec)
+{
+    (void)ctx;
+    drop_plain_graph(rec);
+    rec->heap->release(rec->plain);
+    rec->heap->release(rec->index);
+    rec->heap->release(rec->data);
+    rec->plain = rec->index = rec->data = nullptr;
+}
+
+// Make sure the event's index tables match the current bin grid.  *rebuilt is
+// set when the tables were (re)allocated and the index must be built.
+mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt)
+{
+    const int bp = ctx->tuning.bins_phi, bz = ctx->tuning.bins_z;
+    *rebuilt = false;
+    if (rec->index && rec->index_bins_phi == bp && rec->index_bins_z == bz) return MKF_OK;
+    rec->heap->release(rec->index);
+    const size_t bytes = event_index_bytes(rec->shape, bp * bz);
+    rec->index = rec->heap->alloc(bytes);
+    if (!rec->index) {
+        rec->index_bins_phi = rec->index_bins_z = 0;
+        return fail(MKF_E_NOMEM, "hit index: %zu bytes", bytes);
+    }
+    carve_index(rec->shape, bp * bz, rec->index, &rec->view);
+    rec->index_bins_phi = bp;
+    rec->index_bins_z = bz;
+    drop_plain_graph(rec);
+    *rebuilt = true;
+    return MKF_OK;
+}
+
+mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
+                       BatchArgs *args, hipStream_t s)
+{
+    (void)ctx;
+    const int n = (int)recs.size();
+    char *h = static_cast<char *>(host);
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_ev = place((size_t)n * sizeof(DevEvent));
+    const size_t o_item = place((size_t)(n + 1) * sizeof(int));
+    const size_t o_hit = place((size_t)(n + 1) * sizeof(int));
+    const size_t o_trk = place((size_t)(n + 1) * sizeof(int));
+    const size_t o_q = place(sizeof(unsigned));
+    DevEvent *ev = reinterpret_cast<DevEvent *>(h + o_ev);
+    int *ip = reinterpret_cast<int *>(h + o_item);
+    int *hp = reinterpret_cast<int *>(h + o_hit);
+    int *tp = reinterpret_cast<int *>(h + o_trk);
+    long long items = 0, hits = 0, trks = 0;
+    for (int i = 0; i < n; ++i) {
+        ev[i] = recs[i]->view;
+        ip[i] = (int)items;
+        hp[i] = (int)hits;
+        tp[i] = (int)trks;
+        items += (recs[i]->shape.n_seeds + spi - 1) / spi;
+        hits += recs[i]->shape.n_hits();
+        trks += recs[i]->shape.n_tracks;
+    }
+    if (items > INT32_MAX || hits > INT32_MAX || trks > INT32_MAX) return fail(MKF_E_INVALID, "batch too large");
+    ip[n] = (int)items;
+    hp[n] = (int)hits;
+    tp[n] = (int)trks;
+    *reinterpret_cast<unsigned *>(h + o_q) = 0;
+    MKF_HIP(hipMemcpyAsync(dev, host, off, hipMemcpyHostToDevice, s));
+    char *d = static_cast<char *>(dev);
+    args->events = reinterpret_cast<const DevEvent *>(d + o_ev);
+    args->item_prefix = reinterpret_cast<const int *>(d + o_item);
+    args->hit_prefix = reinterpret_cast<const int *>(d + o_hit);
+    args->track_prefix = reinterpret_cast<const int *>(d + o_trk);
+    args->queue = reinterpret_cast<unsigned *>(d + o_q);
+    args->n_events = n;
+    args->total_items = (int)items;
+    args->total_hits = (int)hits;
+    args->total_tracks = (int)trks;
+    args->seeds_per_item = spi;
+    return MKF_OK;
+}
+
+// The batched pipeline on stream s: optional counter reset and re-index,
+// then the build kernel.
+mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<EventRec *> &recs, uint32_t flags,
+                        bool timed, hipStream_t s)
+{
+    (void)recs;
+    const Params &P = ctx->params;
+    const bool stats = flags & MKF_BATCH_STATS, reindex = flags & MKF_BATCH_REINDEX;
+    if (stats || reindex) MKF_HIP(launch_batch_zero(P, args, stats, reindex, s));
+    if (reindex) {
+        if (timed) timer_begin(ctx, 1, s);
+        MKF_HIP(launch_index(P, args, s));
+        if (timed) timer_end(ctx, 1, s, 3);
+    }
+    const mkf_tuning &t = ctx->tuning;
+    if (t.persistent) MKF_HIP(launch_fill_i32(reinterpret_cast<int *>(args.queue), 0, 1, s));
+    if (timed) timer_begin(ctx, 0, s);
+    MKF_HIP(launch_build_batch(P, args, t.lanes_per_seed, t.waves_per_block, t.persistent,
+                               ctx->n_cu * t.blocks_per_cu, stats, s));
+    if (timed) timer_end(ctx, 0, s, 1);
+    return MKF_OK;
+}
+
+static mkf_status copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (!dst || bytes == 0) return MKF_OK;
+    MKF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    return MKF_OK;
+}
+
+mkf_status copy_tracks_out(mkf_ctx *ctx, const EventRec *rec, const mkf_tracks *out, hipStream_t s)
+{
+    (void)ctx;
+    const DevEvent &v = rec->view;
+    const size_t n = (size_t)rec->shape.n_seeds, nl = (size_t)rec->shape.n_layers;
+    mkf_status st;
+    if ((st = copy_d2h(out->par, v.out_par, 48 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->cov, v.out_cov, 168 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->hits, v.out_hits, 4 * nl * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->n_hits, v.out_nhits, 4 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->n_holes, v.out_nholes, 4 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->chi2, v.out_chi2, 8 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->status, v.out_status, 4 * n, s)) != MKF_OK) return st;
+    if (out->ndof) {
+        // 2 measured coordinates per hit, minus the 5 track parameters
+        if ((st = copy_d2h(out->ndof, v.out_nhits, 4 * n, s)) != MKF_OK) return st;
+    }
+    return MKF_OK;
+}
+
+static void finish_ndof(const mkf_tracks *out)
+{
+    if (!out || !out->ndof) return;
+    for (int i = 0; i < out->n; ++i) out->ndof[i] = 2 * out->ndof[i] - 5;
+}
+
+static mkf_status check_tracks(const mkf_tracks *out, int n, const char *what)
+{
+    if (!out) return MKF_OK;
+    if (out->n != n) return fail(MKF_E_INVALID, "%s: output has %d rows, need %d", what, out->n, n);
+    return MKF_OK;
+}
+
+}  // namespace mkf
+
+using namespace mkf;
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char *mkf_version(void) { return "mkf 0.1 (gfx950, FP32 Kalman filter)"; }
+
+const char *mkf_last_error(void) { return g_err; }
+
+mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *hip_stream, mkf_ctx **out)
+{
+    if (!out) return fail(MKF_E_INVALID, "out is NULL");
+    mkf_status st = check_config(cfg);
+    if (st != MKF_OK) return st;
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MKF_E_INVALID, "allocator needs alloc and free");
+    int dev = 0;
+    MKF_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    MKF_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MKF_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    auto ctx = std::make_unique<mkf_ctx>();
+    ctx->cfg = *cfg;
+    ctx->device = dev;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->heap.ctx = ctx.get();
+    if (alloc) {
+        ctx->alloc = *alloc;
+        ctx->has_alloc = true;
+    }
+    if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        MKF_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    std::memset(&ctx->tuning, 0, sizeof(ctx->tuning));
+    ctx->tuning.persistent = 1;
+    if ((st = check_tuning(ctx->cfg, &ctx->tuning)) != MKF_OK) return st;
+    derive_params(ctx.get());
+    for (auto &t : ctx->timers) {
+        MKF_HIP(hipEventCreate(&t.start));
+        MKF_HIP(hipEventCreate(&t.stop));
+    }
+    *out = ctx.release();
+    return MKF_OK;
+}
+
+void mkf_destroy(mkf_ctx *ctx)
+{
+    if (!ctx) return;
+    shutdown_server(ctx);
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs_with(ctx, -1);
+    for (auto &kv : ctx->events) destroy_event(ctx, kv.second.get());
+    ctx->events.clear();
+    ctx->heap.release(ctx->batch_dev);
+    if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+    for (auto &t : ctx->timers) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t)
+{
+    if (!ctx || !t) return fail(MKF_E_INVALID, "NULL argument");
+    mkf_tuning nt = *t;
+    mkf_status st = check_tuning(ctx->cfg, &nt);
+    if (st != MKF_OK) return st;
+    const size_t lds = (size_t)nt.waves_per_block * ctx->cfg.n_layers * kWave * 5;
+    if (lds > 65536) return fail(MKF_E_INVALID, "waves_per_block too large for %d layers", ctx->cfg.n_layers);
+    ctx->tuning = nt;
+    derive_params(ctx);
+    drop_graphs_with(ctx, -1);
+    for (auto &kv : ctx->events) drop_plain_graph(kv.second.get());
+    return MKF_OK;
+}
+
+mkf_status mkf_get_tuning(const mkf_ctx *ctx, mkf_tuning *t)
+{
+    if (!ctx || !t) return fail(MKF_E_INVALID, "NULL argument");
+    *t = ctx->tuning;
+    return MKF_OK;
+}
+
+mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle)
+{
+    if (!ctx || !handle) return fail(MKF_E_INVALID, "NULL argument");
+    EventShape shape;
+    mkf_status st = validate_event(ctx, ev, &shape);
+    if (st != MKF_OK) return st;
+    std::unique_ptr<EventRec> rec;
+    if ((st = create_event(ctx, shape, &ctx->heap, &rec)) != MKF_OK) return st;
+    bool rebuilt = false;
+    if ((st = upload_event(ctx, rec.get(), ev, ctx->stream)) != MKF_OK ||
+        (st = ensure_index(ctx, rec.get(), &rebuilt)) != MKF_OK ||
+        (st = upload_view(rec.get(), ctx->stream)) != MKF_OK ||
+        (st = ensure_batch_scratch(ctx, 1)) != MKF_OK) {
+        destroy_event(ctx, rec.get());
+        return st;
+    }
+    BatchArgs args{};
+    std::vector<EventRec *> one{rec.get()};
+    if ((st = stage_batch(ctx, one, ctx->batch_dev, ctx->batch_host, seeds_per_item(ctx->tuning.lanes_per_seed),
+                          &args, ctx->stream)) != MKF_OK) {
+        destroy_event(ctx, rec.get());
+        return st;
+    }
+    hipError_t e = launch_batch_zero(ctx->params, args, true, true, ctx->stream);
+    if (e == hipSuccess) e = launch_index(ctx->params, args, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        destroy_event(ctx, rec.get());
+        return fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(e));
+    }
+    const int32_t h = ctx->next_handle++;
+    ctx->events[h] = std::move(rec);
+    *handle = h;
+    return MKF_OK;
+}
+
+mkf_status mkf_unload_event(mkf_ctx *ctx, int32_t handle)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    auto it = ctx->events.find(handle);
+    if (it == ctx->events.end()) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    drop_graphs_with(ctx, handle);
+    destroy_event(ctx, it->second.get());
+    ctx->events.erase(it);
+    return MKF_OK;
+}
+
+static mkf_status reindex_if_needed(mkf_ctx *ctx, const std::vector<EventRec *> &recs, bool *any)
+{
+    *any = false;
+    for (EventRec *r : recs) {
+        bool rebuilt = false;
+        mkf_status st = ensure_index(ctx, r, &rebuilt);
+        if (st != MKF_OK) return st;
+        if (rebuilt) {
+            if ((st = upload_view(r, ctx->stream)) != MKF_OK) return st;
+            drop_graphs_with(ctx, -1);
+            *any = true;
+        }
+    }
+    return MKF_OK;
+}
+
+mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    mkf_status st = check_tracks(out, rec->shape.n_seeds, "build");
+    if (st != MKF_OK) return st;
+    std::vector<EventRec *> one{rec};
+    bool need_index = false;
+    if ((st = reindex_if_needed(ctx, one, &need_index)) != MKF_OK) return st;
+    const int G = ctx->tuning.lanes_per_seed, wpb = ctx->tuning.waves_per_block;
+    if (need_index) {
+        if ((st = ensure_batch_scratch(ctx, 1)) != MKF_OK) return st;
+        BatchArgs args{};
+        if ((st = stage_batch(ctx, one, ctx->batch_dev, ctx->batch_host, seeds_per_item(G), &args, ctx->stream)) !=
+            MKF_OK)
+            return st;
+        MKF_HIP(launch_batch_zero(ctx->params, args, false, true, ctx->stream));
+        MKF_HIP(launch_index(ctx->params, args, ctx->stream));
+    }
+    if (rec->plain_G != G || !rec->plain) {
+        drop_plain_graph(rec);
+        rec->heap->release(rec->plain);
+        const int slots = plain_slots(rec->shape.n_seeds, G);
+        const size_t bytes = carve_plain(rec->shape, slots, nullptr, &rec->view);
+        rec->plain = rec->heap->alloc(bytes);
+        if (!rec->plain) {
+            rec->plain_G = 0;
+            return fail(MKF_E_NOMEM, "builder state: %zu bytes", bytes);
+        }
+        carve_plain(rec->shape, slots, rec->plain, &rec->view);
+        rec->plain_G = G;
+        if ((st = upload_view(rec, ctx->stream)) != MKF_OK) return st;
+    }
+    const int n_launch = rec->shape.n_layers - rec->shape.n_seed_layers;
+    if (rec->shape.n_seeds > 0) {
+        if (!rec->plain_graph || rec->plain_graph_G != G || rec->plain_graph_wpb != wpb) {
+            drop_plain_graph(rec);
+            hipGraph_t graph = nullptr;
+            MKF_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t cap = hipSuccess;
+            for (int L = rec->shape.n_seed_layers; L < rec->shape.n_layers && cap == hipSuccess; ++L)
+                cap = launch_build_layer(ctx->params, rec->dev_view, rec->view, L, G, wpb, false, ctx->stream);
+            hipError_t end = hipStreamEndCapture(ctx->stream, &graph);
+            if (cap != hipSuccess || end != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(MKF_E_DEVICE, "capturing the layer loop: %s",
+                            hipGetErrorString(cap != hipSuccess ? cap : end));
+            }
+            hipError_t ins = hipGraphInstantiate(&rec->plain_graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ins != hipSuccess) return fail(MKF_E_DEVICE, "instantiating the layer loop: %s", hipGetErrorString(ins));
+            rec->plain_graph_G = G;
+            rec->plain_graph_wpb = wpb;
+        }
+        timer_begin(ctx, 0, ctx->stream);
+        MKF_HIP(hipGraphLaunch(rec->plain_graph, ctx->stream));
+        timer_end(ctx, 0, ctx->stream, n_launch);
+    }
+    if (out && (st = copy_tracks_out(ctx, rec, out, ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx);
+    finish_ndof(out);
+    return MKF_OK;
+}
+
+mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags, mkf_tracks *outs)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH)) return fail(MKF_E_INVALID, "unknown flags");
+    std::vector<EventRec *> recs;
+    mkf_status st = gather_events(ctx, handles, n, &recs);
+    if (st != MKF_OK) return st;
+    if (outs)
+        for (int i = 0; i < n; ++i)
+            if ((st = check_tracks(&outs[i], recs[i]->shape.n_seeds, "build_batch")) != MKF_OK) return st;
+    if (n == 0) return MKF_OK;
+    bool need_index = false;
+    if ((st = reindex_if_needed(ctx, recs, &need_index)) != MKF_OK) return st;
+    if (need_index) flags |= MKF_BATCH_REINDEX;
+    const int spi = seeds_per_item(ctx->tuning.lanes_per_seed);
+    if (flags & MKF_BATCH_GRAPH) {
+        BatchGraph *bg = nullptr;
+        std::vector<int32_t> key(handles, handles + n);
+        for (auto &g : ctx->graphs)
+            if (g->handles == key && g->flags == flags && std::memcmp(&g->tuning, &ctx->tuning, sizeof(mkf_tuning)) == 0)
+                bg = g.get();
+        if (!bg) {
+            auto g = std::make_unique<BatchGraph>();
+            g->handles = key;
+            g->flags = flags;
+            g->tuning = ctx->tuning;
+            g->scratch = ctx->heap.alloc(batch_scratch_bytes(n));
+            if (!g->scratch) return fail(MKF_E_NOMEM, "graph scratch");
+            if ((st = ensure_batch_scratch(ctx, n)) != MKF_OK) {
+                ctx->heap.release(g->scratch);
+                return st;
+            }
+            BatchArgs args{};
+            if ((st = stage_batch(ctx, recs, g->scratch, ctx->batch_host, spi, &args, ctx->stream)) != MKF_OK) {
+                ctx->heap.release(g->scratch);
+                return st;
+            }
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) {
+                ctx->heap.release(g->scratch);
+                return fail(MKF_E_DEVICE, "staging: %s", hipGetErrorString(e));
+            }
+            hipGraph_t graph = nullptr;
+            MKF_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            mkf_status cst = run_pipeline(ctx, args, recs, flags, false, ctx->stream);
+            hipError_t end = hipStreamEndCapture(ctx->stream, &graph);
+            if (cst != MKF_OK || end != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                ctx->heap.release(g->scratch);
+                return cst != MKF_OK ? cst : fail(MKF_E_DEVICE, "capture: %s", hipGetErrorString(end));
+            }
+            hipError_t ins = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ins != hipSuccess) {
+                ctx->heap.release(g->scratch);
+                return fail(MKF_E_DEVICE, "instantiate: %s", hipGetErrorString(ins));
+            }
+            bg = g.get();
+            ctx->graphs.push_back(std::move(g));
+        }
+        timer_begin(ctx, 0, ctx->stream);
+        MKF_HIP(hipGraphLaunch(bg->exec, ctx->stream));
+        timer_end(ctx, 0, ctx->stream, 1);
+    } else {
+        if ((st = ensure_batch_scratch(ctx, n)) != MKF_OK) return st;
+        BatchArgs args{};
+        if ((st = stage_batch(ctx, recs, ctx->batch_dev, ctx->batch_host, spi, &args, ctx->stream)) != MKF_OK) return st;
+        if ((st = run_pipeline(ctx, args, recs, flags, true, ctx->stream)) != MKF_OK) return st;
+    }
+    if (outs)
+        for (int i = 0; i < n; ++i)
+            if ((st = copy_tracks_out(ctx, recs[i], &outs[i], ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx);
+    if (outs)
+        for (int i = 0; i < n; ++i) finish_ndof(&outs[i]);
+    return MKF_OK;
+}
+
+mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
+{
+    if (!ctx || !out) return fail(MKF_E_INVALID, "NULL argument");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    mkf_status st = check_tracks(out, rec->shape.n_seeds, "fetch");
+    if (st != MKF_OK) return st;
+    if ((st = copy_tracks_out(ctx, rec, out, ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    finish_ndof(out);
+    return MKF_OK;
+}
+
+mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out)
+{
+    if (!ctx || !out) return fail(MKF_E_INVALID, "NULL argument");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    unsigned long long v[5];
+    MKF_HIP(hipMemcpyAsync(v, rec->view.stats, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    out->cand_layers = (int64_t)v[0];
+    out->chi2_evals = (int64_t)v[1];
+    out->accepted = (int64_t)v[2];
+    out->updates = (int64_t)v[3];
+    out->hits_scanned = (int64_t)v[4];
+    return MKF_OK;
+}
+
+static mkf_status copy_fit_out(const EventRec *rec, const DevEvent &v, const mkf_tracks *out, hipStream_t s)
+{
+    const size_t n = (size_t)rec->shape.n_tracks, nl = (size_t)rec->shape.n_layers;
+    mkf_status st;
+    if ((st = copy_d2h(out->par, v.fit_par, 48 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->cov, v.fit_cov, 168 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->hits, v.track_hits, 4 * nl * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->n_hits, v.fit_nupd, 4 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->n_holes, v.fit_nupd, 4 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->chi2, v.fit_chi2, 8 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->status, v.fit_status, 4 * n, s)) != MKF_OK) return st;
+    if ((st = copy_d2h(out->ndof, v.fit_nupd, 4 * n, s)) != MKF_OK) return st;
+    return MKF_OK;
+}
+
+static void finish_fit_out(const mkf_tracks *out, int n_layers)
+{
+    if (!out) return;
+    for (int i = 0; i < out->n; ++i) {
+        if (out->n_holes) out->n_holes[i] = n_layers - out->n_holes[i];
+        if (out->ndof) out->ndof[i] = 2 * out->ndof[i] - 5;
+    }
+}
+
+mkf_status mkf_fit_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tracks *outs)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    std::vector<EventRec *> recs;
+    mkf_status st = gather_events(ctx, handles, n, &recs);
+    if (st != MKF_OK) return st;
+    if (outs)
+        for (int i = 0; i < n; ++i)
+            if ((st = check_tracks(&outs[i], recs[i]->shape.n_tracks, "fit_batch")) != MKF_OK) return st;
+    if (n == 0) return MKF_OK;
+    if ((st = ensure_batch_scratch(ctx, n)) != MKF_OK) return st;
+    BatchArgs args{};
+    if ((st = stage_batch(ctx, recs, ctx->batch_dev, ctx->batch_host, seeds_per_item(ctx->tuning.lanes_per_seed),
+                          &args, ctx->stream)) != MKF_OK)
+        return st;
+    timer_begin(ctx, 2, ctx->stream);
+    MKF_HIP(launch_fit(ctx->params, args, ctx->stream));
+    timer_end(ctx, 2, ctx->stream, 1);
+    if (outs)
+        for (int i = 0; i < n; ++i)
+            if ((st = copy_fit_out(recs[i], recs[i]->view, &outs[i], ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx);
+    if (outs)
+        for (int i = 0; i < n; ++i) finish_fit_out(&outs[i], recs[i]->shape.n_layers);
+    return MKF_OK;
+}
+
+mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double *init_par, const double *init_cov,
+                   const int32_t *track_hits, mkf_tracks *out)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    mkf_status st = check_tracks(out, n_tracks, "fit");
+    if (st != MKF_OK) return st;
+    // validate the tracks against the event's hits
+    std::vector<int32_t> nh(rec->shape.n_layers);
+    for (int L = 0; L < rec->shape.n_layers; ++L) nh[L] = rec->shape.layer_off[L + 1] - rec->shape.layer_off[L];
+    if (n_tracks < 0) return fail(MKF_E_INVALID, "negative track count");
+    if (n_tracks > 0) {
+        if (!init_par || !init_cov || !track_hits) return fail(MKF_E_INVALID, "track arrays are NULL");
+        if (!finite_all(init_par, 6 * (size_t)n_tracks) || !finite_all(init_cov, 21 * (size_t)n_tracks))
+            return fail(MKF_E_INVALID, "track state or covariance not finite");
+        for (int i = 0; i < n_tracks; ++i) {
+            const double *p = init_par + 6 * (size_t)i;
+            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
+                return fail(MKF_E_INVALID, "track %d: theta outside (0, pi) or position on the axis", i);
+            for (int L = 0; L < rec->shape.n_layers; ++L) {
+                const int h = track_hits[(size_t)i * rec->shape.n_layers + L];
+                if (h < -1 || h >= nh[L]) return fail(MKF_E_INVALID, "track %d: hit index out of range", i);
+            }
+        }
+    }
+    if (n_tracks == 0) return MKF_OK;
+    // a temporary event view: the loaded event's hits with these tracks
+    EventShape ts = rec->shape;
+    ts.n_seeds = 0;
+    ts.n_tracks = n_tracks;
+    const size_t nt = (size_t)n_tracks, nl = (size_t)ts.n_layers;
+    const size_t bytes = nt * (48 + 168 + 4 * nl + 48 + 168 + 8 + 4 + 4) + 8 * 256 + sizeof(DevEvent);
+    char *buf = static_cast<char *>(ctx->heap.alloc(bytes));
+    if (!buf) return fail(MKF_E_NOMEM, "fit buffers: %zu bytes", bytes);
+    DevEvent v = rec->view;
+    v.n_seeds = 0;
+    v.n_tracks = n_tracks;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *p = buf + off;
+        off = (off + b + 255) & ~size_t(255);
+        return p;
+    };
+    v.track_par = reinterpret_cast<double *>(take(48 * nt));
+    v.track_cov = reinterpret_cast<double *>(take(168 * nt));
+    v.track_hits = reinterpret_cast<int *>(take(4 * nl * nt));
+    v.fit_par = reinterpret_cast<double *>(take(48 * nt));
+    v.fit_cov = reinterpret_cast<double *>(take(168 * nt));
+    v.fit_chi2 = reinterpret_cast<double *>(take(8 * nt));
+    v.fit_nupd = reinterpret_cast<int *>(take(4 * nt));
+    v.fit_status = reinterpret_cast<int *>(take(4 * nt));
+    auto cleanup = [&](mkf_status s) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->heap.release(buf);
+        return s;
+    };
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(const_cast<double *>(v.track_par), init_par, 48 * nt, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<double *>(v.track_cov), init_cov, 168 * nt, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int *>(v.track_hits), track_hits, 4 * nl * nt, hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(fail(MKF_E_DEVICE, "fit upload failed"));
+    if ((st = ensure_batch_scratch(ctx, 1)) != MKF_OK) return cleanup(st);
+    EventRec tmp;
+    tmp.shape = ts;
+    tmp.view = v;
+    std::vector<EventRec *> one{&tmp};
+    BatchArgs args{};
+    if ((st = stage_batch(ctx, one, ctx->batch_dev, ctx->batch_host, 64, &args, s)) != MKF_OK) return cleanup(st);
+    timer_begin(ctx, 2, s);
+    hipError_t e = launch_fit(ctx->params, args, s);
+    timer_end(ctx, 2, s, 1);
+    if (e != hipSuccess) return cleanup(fail(MKF_E_DEVICE, "fit launch: %s", hipGetErrorString(e)));
+    if (out && (st = copy_fit_out(&tmp, v, out, s)) != MKF_OK) return cleanup(st);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup(fail(MKF_E_DEVICE, "fit: %s", hipGetErrorString(e)));
+    timers_collect(ctx);
+    finish_fit_out(out, ts.n_layers);
+    return cleanup(MKF_OK);
+}
+
+mkf_status mkf_timer_read(mkf_ctx *ctx, int32_t which, double *total_ms, int64_t *launches)
+{
+    if (!ctx || which < 0 || which > 2) return fail(MKF_E_INVALID, "bad timer");
+    if (total_ms) *total_ms = ctx->timers[which].total_ms;
+    if (launches) *launches = ctx->timers[which].launches;
+    return MKF_OK;
+}
+
+mkf_status mkf_timer_reset(mkf_ctx *ctx)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    for (auto &t : ctx->timers) {
+        t.total_ms = 0;
+        t.launches = 0;
+    }
+    return MKF_OK;
+}
+
+mkf_status mkf_autotune(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tuning *best)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    std::vector<EventRec *> recs;
+    mkf_status st = gather_events(ctx, handles, n, &recs);
+    if (st != MKF_OK) return st;
+    if (n == 0) return fail(MKF_E_INVALID, "no events to tune on");
+    const mkf_tuning start = ctx->tuning;
+    auto measure = [&](const mkf_tuning &t, double *ms) -> mkf_status {
+        mkf_status s2 = mkf_set_tuning(ctx, &t);
+        if (s2 != MKF_OK) return s2;
+        s2 = mkf_build_batch(ctx, handles, n, MKF_BATCH_REINDEX, nullptr);
+        if (s2 != MKF_OK) return s2;
+        double best_ms = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            MKF_HIP(hipStreamSynchronize(ctx->stream));
+            const auto t0 = std::chrono::steady_clock::now();
+            s2 = mkf_build_batch(ctx, handles, n, MKF_BATCH_REINDEX, nullptr);
+            if (s2 != MKF_OK) return s2;
+            const auto t1 = std::chrono::steady_clock::now();
+            best_ms = std::min(best_ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        *ms = best_ms;
+        return MKF_OK;
+    };
+    mkf_tuning cur = start;
+    double cur_ms = 0;
+    if ((st = measure(cur, &cur_ms)) != MKF_OK) return st;
+    std::vector<int> lanes;
+    for (int G = 1; G <= kMaxCands; G <<= 1)
+        if (G >= ctx->cfg.max_cands) lanes.push_back(G);
+    const std::vector<int> waves = {1, 2, 4};
+    const std::vector<int> bphi = {64, 128, 256, 512, 1024};
+    const std::vector<int> bz = {4, 8, 16, 32, 64};
+    const std::vector<int> pers = {0, 1};
+    const std::vector<int> bpc = {2, 4, 8, 16};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int dim = 0; dim < 6; ++dim) {
+            const std::vector<int> &vals = dim == 0 ? lanes : dim == 1 ? waves : dim == 2 ? bphi : dim == 3 ? bz
+                                                                                        : dim == 4 ? pers : bpc;
+            for (int v : vals) {
+                mkf_tuning t = cur;
+                int *field = dim == 0 ? &t.lanes_per_seed : dim == 1 ? &t.waves_per_block : dim == 2 ? &t.bins_phi
+                             : dim == 3 ? &t.bins_z : dim == 4 ? &t.persistent : &t.blocks_per_cu;
+                if (*field == v) continue;
+                *field = v;
+                double ms = 0;
+                if (measure(t, &ms) != MKF_OK) continue;
+                if (ms < cur_ms * 0.98) {
+                    cur = t;
+                    cur_ms = ms;
+                }
+            }
+        }
+    }
+    if ((st = mkf_set_tuning(ctx, &cur)) != MKF_OK) return st;
+    if (best) *best = ctx->tuning;
+    return MKF_OK;
+}
+
+mkf_status mkf_calib_copy(mkf_ctx *ctx, const void *src_dev, void *dst_dev, size_t bytes)
+{
+    if (!ctx || !src_dev || !dst_dev || bytes % 16) return fail(MKF_E_INVALID, "bad copy arguments");
+    MKF_HIP(launch_copy(src_dev, dst_dev, bytes, ctx->stream));
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    return MKF_OK;
+}
+
+}  // extern "C"

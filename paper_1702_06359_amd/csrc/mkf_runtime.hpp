@@ -1,0 +1,156 @@
+// Host runtime of the track builder: context, device memory, loaded events.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mkf_internal.hpp"
+
+namespace mkf {
+
+// thread-local message of the last failure
+mkf_status fail(mkf_status st, const char *fmt, ...);
+
+#define MKF_HIP(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return ::mkf::fail(MKF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Source of device memory for events: the caller's hooks / hipMalloc, or
+// the serving slab.
+struct DeviceHeap {
+    virtual ~DeviceHeap() = default;
+    virtual void *alloc(size_t bytes) = 0;
+    virtual void release(void *p) = 0;
+};
+
+// First-fit sub-allocator over one reserved device slab (serving budget).
+class SlabHeap : public DeviceHeap {
+  public:
+    SlabHeap(char *base, size_t bytes);
+    void *alloc(size_t bytes) override;
+    void release(void *p) override;
+    size_t used() const { return used_; }
+    size_t capacity() const { return cap_; }
+
+  private:
+    char *base_;
+    size_t cap_;
+    size_t used_ = 0;
+    std::map<size_t, size_t> free_;     // offset -> size
+    std::map<size_t, size_t> taken_;    // offset -> size
+    std::mutex mu_;
+};
+
+// Sizes of one event, from which its device layout follows.
+struct EventShape {
+    int n_layers = 0;
+    int n_seed_layers = 0;
+    int n_seeds = 0;
+    int n_tracks = 0;
+    int layer_off[kMaxLayers + 1] = {0};
+    int n_hits() const { return layer_off[n_layers]; }
+};
+
+size_t event_data_bytes(const EventShape &s);
+size_t event_index_bytes(const EventShape &s, int n_bins);
+
+// One loaded event.
+struct EventRec {
+    EventShape shape;
+    DeviceHeap *heap = nullptr;
+    void *data = nullptr;          // hits, seeds, tracks, outputs, stats, descriptor
+    void *index = nullptr;         // bin counts and offsets
+    void *plain = nullptr;         // per-layer builder state
+    int index_bins_phi = 0, index_bins_z = 0;   // grid the index was built for (0 = none)
+    int plain_G = 0;
+    DevEvent view{};               // host copy of the device descriptor
+    DevEvent *dev_view = nullptr;  // device copy (inside `data`)
+    hipGraphExec_t plain_graph = nullptr;
+    int plain_graph_G = 0;
+    int plain_graph_wpb = 0;
+};
+
+struct BatchGraph {
+    std::vector<int32_t> handles;
+    uint32_t flags = 0;
+    mkf_tuning tuning{};
+    void *scratch = nullptr;       // descriptors + prefixes + queue, owned
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Timer {
+    hipEvent_t start = nullptr, stop = nullptr;
+    double total_ms = 0.0;
+    long long launches = 0;
+    bool pending = false;
+    long long pending_launches = 0;
+};
+
+struct Server;   // serving state (mkf_serve.cpp)
+struct ServerDeleter {
+    void operator()(Server *s) const;
+};
+
+struct CtxHeap : public DeviceHeap {
+    mkf_ctx *ctx = nullptr;
+    void *alloc(size_t bytes) override;
+    void release(void *p) override;
+};
+
+}  // namespace mkf
+
+struct mkf_ctx {
+    mkf_config cfg{};
+    mkf_tuning tuning{};
+    mkf::Params params{};          // derived from cfg + tuning
+    int device = 0;
+    int n_cu = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool has_alloc = false;
+    mkf_allocator alloc{};
+    mkf::CtxHeap heap;
+    std::unordered_map<int32_t, std::unique_ptr<mkf::EventRec>> events;
+    int32_t next_handle = 1;
+    // batch scratch (descriptor array + prefixes + queue), device and pinned host
+    void *batch_dev = nullptr;
+    size_t batch_dev_bytes = 0;
+    void *batch_host = nullptr;
+    size_t batch_host_bytes = 0;
+    std::vector<std::unique_ptr<mkf::BatchGraph>> graphs;
+    mkf::Timer timers[3];
+    std::unique_ptr<mkf::Server, mkf::ServerDeleter> server;
+};
+
+namespace mkf {
+
+// context-level helpers used by the ABI and the scheduler
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape);
+mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap, std::unique_ptr<EventRec> *out);
+mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s);
+void destroy_event(mkf_ctx *ctx, EventRec *rec);
+mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt);
+mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
+                       BatchArgs *args, hipStream_t s);
+size_t batch_scratch_bytes(int n_events);
+int resolve_lanes(const mkf_ctx *ctx);
+int seeds_per_item(int G);
+mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<EventRec *> &recs, uint32_t flags,
+                        bool timed, hipStream_t s);
+mkf_status copy_tracks_out(mkf_ctx *ctx, const EventRec *rec, const mkf_tracks *out, hipStream_t s);
+void shutdown_server(mkf_ctx *ctx);
+
+}  // namespace mkf

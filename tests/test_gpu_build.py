@@ -1,0 +1,261 @@
+"""GPU track building against the FP64 oracle, and invariances of the GPU path.
+
+Parity follows the tie protocol of parity_util: identical hit lists for every
+seed the oracle does not flag as tie-sensitive, states and covariances within
+the frozen FP32 tolerances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import report
+from paper_1702_06359_amd import abi, synth
+from parity_util import assert_build_parity, compare_build
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("par", "cov", "hits", "n_hits", "n_holes", "chi2", "status", "ndof")
+
+
+def _ctx(k, **tuning):
+    c = abi.Context(abi.config_from_geometry(synth.Geometry(), max_cands=k))
+    if tuning:
+        c.set_tuning(**tuning)
+    return c
+
+
+@pytest.fixture(scope="module")
+def ctx1(gpu_required):
+    c = _ctx(1)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx6(gpu_required):
+    c = _ctx(6)
+    yield c
+    c.close()
+
+
+def _equal(a, b):
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def _oracle(ev, k, rows=None, threads=8):
+    cfg = oracle.config(ev.geometry, max_cands=k)
+    return cfg, oracle.build_tracks(cfg, ev.hits, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=rows,
+                                    n_threads=threads)
+
+
+def test_best_hit_parity_1000_tracks(ctx1):
+    ev = synth.best_hit_event(1000)
+    print("case best_hit n=1000 k=1 plain", flush=True)
+    h = ctx1.load_event(ev)
+    try:
+        g = ctx1.build(h, ev.n_seeds)
+    finally:
+        ctx1.unload_event(h)
+    cfg, o = _oracle(ev, 1)
+    rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov)
+    report("best_hit_1000", rep)
+    assert_build_parity(rep)
+    eff = (g["hits"] == ev.truth_hit).all(1).mean()
+    assert eff >= 0.95
+
+
+def test_combinatorial_parity_ragged(ctx6):
+    ev = synth.make_event(2003, cfg=210, event=0, noise=0.1)
+    print("case ckf n=2003 k=6 noise=0.1 plain+batched", flush=True)
+    h = ctx6.load_event(ev)
+    try:
+        g = ctx6.build(h, ev.n_seeds)
+        gb = ctx6.build_batch([h], [ev.n_seeds])[0]
+    finally:
+        ctx6.unload_event(h)
+    _equal(g, gb)
+    cfg, o = _oracle(ev, 6)
+    rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov)
+    report("ckf_2003", rep)
+    assert_build_parity(rep)
+
+
+def test_combinatorial_parity_high_occupancy(ctx6):
+    ev = synth.make_event(1500, cfg=211, event=0, noise=0.5)
+    print("case ckf n=1500 k=6 noise=0.5", flush=True)
+    h = ctx6.load_event(ev)
+    try:
+        g = ctx6.build_batch([h], [ev.n_seeds])[0]
+    finally:
+        ctx6.unload_event(h)
+    cfg, o = _oracle(ev, 6)
+    rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov)
+    report("ckf_1500_noise50", rep)
+    assert_build_parity(rep)
+
+
+def test_full_size_events_sampled_seeds(ctx6):
+    """Two 20,000-track events (10 % noise) in the batched launch the
+    benchmark times; 150 sampled seeds per event checked against the oracle."""
+    evs = synth.ckf_events(2, 20000, 0.10)
+    hs = [ctx6.load_event(e) for e in evs]
+    try:
+        print("case ckf full size 2x20000 batched persistent", flush=True)
+        outs = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
+    finally:
+        for h in hs:
+            ctx6.unload_event(h)
+    rng = np.random.default_rng(7)
+    for i, (ev, g) in enumerate(zip(evs, outs)):
+        rows = np.sort(rng.choice(ev.n_seeds, 150, replace=False)).astype(np.int32)
+        cfg, o = _oracle(ev, 6, rows=rows, threads=16)
+        rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov, rows=rows)
+        report(f"ckf_full_event{i}", rep)
+        assert_build_parity(rep, max_tie_frac=0.02)
+        eff = (g["hits"] == ev.truth_hit).all(1).mean()
+        assert eff >= 0.75      # the oracle agrees seed by seed; 20k-track events are crowded
+
+
+def test_launch_shapes_do_not_change_results(gpu_required):
+    """Bin grid, lanes per seed, waves per block, persistent or not, graph or
+    not, plain or batched: bit-identical tracks."""
+    ev = synth.make_event(1200, cfg=212, event=0, noise=0.3)
+    ref = None
+    shapes = [dict(), dict(bins_phi=64, bins_z=4), dict(bins_phi=1024, bins_z=64), dict(waves_per_block=1),
+              dict(persistent=0), dict(lanes_per_seed=2), dict(lanes_per_seed=8, waves_per_block=2)]
+    for k in (1, 2):
+        for sh in shapes:
+            if sh.get("lanes_per_seed", 8) < k:
+                continue
+            c = _ctx(k, **sh)
+            try:
+                print(f"case shapes k={k} {sh}", flush=True)
+                h = c.load_event(ev)
+                a = c.build(h, ev.n_seeds)
+                b = c.build_batch([h], [ev.n_seeds])[0]
+                gr = c.build_batch([h], [ev.n_seeds], flags=abi.BATCH_GRAPH)[0]
+                gr2 = c.build_batch([h], [ev.n_seeds], flags=abi.BATCH_GRAPH)[0]
+            finally:
+                c.close()
+            _equal(a, b)
+            _equal(a, gr)
+            _equal(a, gr2)
+            if sh == {}:
+                ref = a
+            else:
+                _equal(ref, a)
+        ref = None
+
+
+def test_repeat_and_batch_composition_are_deterministic(ctx6):
+    evs = [synth.make_event(n, cfg=213, event=i, noise=0.2) for i, n in enumerate((900, 2500, 333))]
+    hs = [ctx6.load_event(e) for e in evs]
+    try:
+        print("case determinism 3 events", flush=True)
+        all3 = ctx6.build_batch(hs, [e.n_seeds for e in evs])
+        again = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
+        rev = ctx6.build_batch(hs[::-1], [e.n_seeds for e in evs[::-1]])[::-1]
+        alone = [ctx6.build(h, e.n_seeds) for h, e in zip(hs, evs)]
+    finally:
+        for h in hs:
+            ctx6.unload_event(h)
+    for a, b, c, d in zip(all3, again, rev, alone):
+        _equal(a, b)
+        _equal(a, c)
+        _equal(a, d)
+
+
+def test_work_counters_match_oracle(ctx6):
+    ev = synth.make_event(800, cfg=214, event=0, noise=0.2)
+    h = ctx6.load_event(ev)
+    try:
+        print("case counters n=800", flush=True)
+        g = ctx6.build_batch([h], [ev.n_seeds], flags=abi.BATCH_STATS)[0]
+        st = ctx6.get_stats(h)
+    finally:
+        ctx6.unload_event(h)
+    cfg, o = _oracle(ev, 6)
+    same = (g["hits"] == o["hits"][:, :10]).all(1)
+    report("counters", dict(gpu=st, oracle=dict(prop=int(o["n_prop"].sum()), acc=int(o["n_accept"].sum()),
+                                                   upd=int(o["n_update"].sum())), identical=int(same.sum())))
+    if same.all():
+        assert st["cand_layers"] == int(o["n_prop"].sum())
+        assert st["accepted"] == int(o["n_accept"].sum())
+        assert st["updates"] == int(o["n_update"].sum())
+    assert st["chi2_evals"] >= st["accepted"]
+    assert st["hits_scanned"] >= st["chi2_evals"]
+
+
+def test_edge_cases(ctx6):
+    geo = synth.Geometry()
+    # no seeds
+    ev = synth.make_event(50, cfg=215, event=0)
+    h = ctx6.load_event(abi.EventArrays(ev.hits, ev.seed_par[:0], ev.seed_cov[:0], ev.seed_hits[:0]))
+    print("case edge: zero seeds", flush=True)
+    out = ctx6.build(h, 0)
+    assert out["par"].shape == (0, 6)
+    assert ctx6.build_batch([h], [0])[0]["hits"].shape == (0, 10)
+    ctx6.unload_event(h)
+    # empty outer layers -> hole then stop; and one seed whose helix cannot reach layer 6
+    hits = [x.copy() for x in ev.hits]
+    for L in (7, 8, 9):
+        hits[L] = np.zeros((0, 3))
+    sp = ev.seed_par.copy()
+    ea = abi.EventArrays(hits, sp, ev.seed_cov, ev.seed_hits)
+    h = ctx6.load_event(ea)
+    print("case edge: empty outer layers", flush=True)
+    g = ctx6.build(h, ev.n_seeds)
+    ctx6.unload_event(h)
+    cfg, o = _oracle(synth.Event(geo, hits, sp, ev.seed_cov, ev.seed_hits, ev.truth_hit, ev.truth_par,
+                                 ev.vertex_par, ev.prior_par, ev.prior_cov, ev.n_noise), 6)
+    rep = compare_build(g, o, cfg, hits, sp, ev.seed_cov)
+    assert_build_parity(rep)
+    assert (g["status"] == 1).all()
+    low = synth.make_event(40, cfg=216, event=0, pt_range=(0.15, 0.15), eta_max=0.5)
+    h = ctx6.load_event(low)
+    print("case edge: curling tracks", flush=True)
+    g = ctx6.build(h, low.n_seeds)
+    ctx6.unload_event(h)
+    assert (g["status"] == 2).all()
+    # all hits of a layer in one bin (far outside the z grid)
+    crowd = [x.copy() for x in ev.hits]
+    crowd[5] = np.concatenate([crowd[5], np.tile([[20.0, 0.0, 1e4]], (5000, 1))])
+    h = ctx6.load_event(abi.EventArrays(crowd, ev.seed_par, ev.seed_cov, ev.seed_hits))
+    print("case edge: crowded edge bin", flush=True)
+    g = ctx6.build(h, ev.n_seeds)
+    ctx6.unload_event(h)
+    cfg, o = _oracle(synth.Event(geo, crowd, ev.seed_par, ev.seed_cov, ev.seed_hits, ev.truth_hit,
+                                 ev.truth_par, ev.vertex_par, ev.prior_par, ev.prior_cov, ev.n_noise), 6)
+    assert_build_parity(compare_build(g, o, cfg, crowd, ev.seed_par, ev.seed_cov))
+
+
+def test_abi_errors(ctx6):
+    ev = synth.make_event(20, cfg=217, event=0)
+    h = ctx6.load_event(ev)
+    try:
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.build(h + 1000, ev.n_seeds)
+        assert e.value.status == abi.E_NOTFOUND
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.build(h, ev.n_seeds + 1)
+        assert e.value.status == abi.E_INVALID
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.build_batch([h, h], [ev.n_seeds, ev.n_seeds])
+        assert e.value.status == abi.E_INVALID
+        bad = [x.copy() for x in ev.hits]
+        bad[2][0, 1] = np.nan
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.load_event(abi.EventArrays(bad, ev.seed_par, ev.seed_cov, ev.seed_hits))
+        assert e.value.status == abi.E_INVALID
+        sh = ev.seed_hits.copy()
+        sh[0, 1] = 10 ** 6
+        with pytest.raises(abi.MkfError):
+            ctx6.load_event(abi.EventArrays(ev.hits, ev.seed_par, ev.seed_cov, sh))
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.set_tuning(lanes_per_seed=4)      # fewer lanes than candidates
+        assert e.value.status == abi.E_INVALID
+        # the context still works after the errors
+        assert ctx6.build(h, ev.n_seeds)["status"].shape == (20,)
+    finally:
+        ctx6.unload_event(h)

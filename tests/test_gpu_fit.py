@@ -1,0 +1,111 @@
+"""GPU KF fit against the FP64 oracle (element by element on seeded inputs)."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import report
+from paper_1702_06359_amd import abi, synth
+from parity_util import TOL, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_required):
+    c = abi.Context(abi.config_from_geometry(synth.Geometry(), max_cands=6))
+    yield c
+    c.close()
+
+
+def _fit_both(ctx, ev, hits_assign, prior_par=None, prior_cov=None):
+    prior_par = ev.prior_par if prior_par is None else prior_par
+    prior_cov = ev.prior_cov if prior_cov is None else prior_cov
+    h = ctx.load_event(abi.EventArrays(ev.hits))
+    try:
+        g = ctx.fit(h, prior_par, prior_cov, hits_assign)
+    finally:
+        ctx.unload_event(h)
+    o = oracle.fit(oracle.config(ev.geometry), ev.hits, prior_par, prior_cov, hits_assign, n_threads=8)
+    return g, o
+
+
+def _check(name, g, o, tol=None):
+    tol = tol or TOL["fit"]
+    assert (g["status"] == o["status"]).all()
+    ok = o["status"] == 0
+    assert (g["ndof"][ok] == o["ndof"][ok]).all()
+    dpar, dcov = state_errors(g["par"][ok], g["cov"][ok], o["par"][ok], o["cov"][ok])
+    dchi = np.abs(g["chi2"][ok] - o["chi2"][ok]) / (1.0 + o["chi2"][ok])
+    rep = dict(n=int(ok.sum()), max_dpar_sigma=dpar.max(), p9999_dpar_sigma=np.quantile(dpar, 0.9999),
+               p99_dpar_sigma=np.quantile(dpar, 0.99), max_dcov_rel=dcov.max(),
+               p9999_dcov_rel=np.quantile(dcov, 0.9999), max_dchi2_rel=dchi.max(),
+               p9999_dchi2_rel=np.quantile(dchi, 0.9999))
+    report(name, rep)
+    assert rep["max_dpar_sigma"] <= tol["tau_par_sigma"], rep
+    assert rep["max_dcov_rel"] <= tol["tau_cov_rel"], rep
+    assert rep["max_dchi2_rel"] <= tol["eps_chi2_rel"], rep
+
+
+def test_fit_parity_true_hits(ctx):
+    ev = synth.make_event(3001, cfg=200, event=0, noise=0.1)
+    print("case fit_parity_true_hits n=3001", flush=True)
+    g, o = _fit_both(ctx, ev, ev.truth_hit)
+    _check("fit_parity_true_hits", g, o)
+
+
+def test_fit_parity_with_skipped_layers(ctx):
+    ev = synth.make_event(2500, cfg=201, event=0, noise=0.0)
+    rng = np.random.default_rng(5)
+    assign = ev.truth_hit.copy()
+    drop = rng.uniform(size=assign.shape) < 0.2
+    drop[:, 0] = False
+    assign[drop] = -1
+    print("case fit_parity_with_skipped_layers n=2500", flush=True)
+    g, o = _fit_both(ctx, ev, assign)
+    _check("fit_parity_with_skipped_layers", g, o)
+    assert (g["n_hits"] == (assign >= 0).sum(1)).all()
+
+
+def test_fit_propagation_failure_status(ctx):
+    ev = synth.make_event(64, cfg=202, event=0, noise=0.0, pt_range=(0.15, 0.15), eta_max=0.5)
+    print("case fit_propagation_failure n=64", flush=True)
+    g, o = _fit_both(ctx, ev, ev.truth_hit)
+    assert (o["status"] == 2).all() and (g["status"] == 2).all()
+
+
+def test_fit_batch_uneven_equals_single_fits(ctx):
+    sizes = [2000, 37, 5001, 1, 640]
+    evs = [synth.make_event(n, cfg=203, event=i, noise=0.05) for i, n in enumerate(sizes)]
+    hs = [ctx.load_event(abi.EventArrays.from_synth(e, with_seeds=False, with_tracks=True)) for e in evs]
+    try:
+        print(f"case fit_batch sizes={sizes}", flush=True)
+        outs = ctx.fit_batch(hs, sizes)
+        for e, h, out in zip(evs, hs, outs):
+            single = ctx.fit(h, e.prior_par, e.prior_cov, e.truth_hit)
+            for k in ("par", "cov", "chi2", "n_hits", "status", "ndof"):
+                assert np.array_equal(out[k], single[k]), k
+        o = oracle.fit(oracle.config(evs[2].geometry), evs[2].hits, evs[2].prior_par, evs[2].prior_cov,
+                       evs[2].truth_hit, n_threads=8)
+        _check("fit_batch_event2", outs[2], o)
+    finally:
+        for h in hs:
+            ctx.unload_event(h)
+
+
+def test_fit_rejects_bad_input(ctx):
+    ev = synth.make_event(10, cfg=204, event=0)
+    h = ctx.load_event(abi.EventArrays(ev.hits))
+    try:
+        bad = ev.truth_hit.copy()
+        bad[3, 4] = ev.hits[4].shape[0]
+        with pytest.raises(abi.MkfError) as e:
+            ctx.fit(h, ev.prior_par, ev.prior_cov, bad)
+        assert e.value.status == abi.E_INVALID
+        par = ev.prior_par.copy()
+        par[2, 1] = np.nan
+        with pytest.raises(abi.MkfError):
+            ctx.fit(h, par, ev.prior_cov, ev.truth_hit)
+        empty = ctx.fit(h, np.zeros((0, 6)), np.zeros((0, 21)), np.zeros((0, 10), np.int32))
+        assert empty["par"].shape == (0, 6)
+    finally:
+        ctx.unload_event(h)
