@@ -31,6 +31,8 @@ FLOP_PER_CAND_LAYER = 480     # scattering 40 + propagation and Jacobian 138 + t
 FLOP_PER_CHI2 = 36            # tangent-plane residual, 2x2 innovation, chi2
 FLOP_PER_UPDATE = 186         # gain, state and covariance update
 FLOP_PER_FIT_LAYER = 40 + 138 + 272 + 186   # scattering, propagation, transport, update
+FLOP_PER_UPDATE_JOSEPH = 466  # fit update in Joseph form
+BYTES_PER_FIT_TRACK = 216 + 40 + 10 * 16 + 216 + 20   # prior, hit ids, hits, fitted state, chi2/counts
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_SEED_IO = 228 + 280     # seed in (par, cov, hits) + track out (par, cov, hits, counts, chi2)
@@ -200,6 +202,160 @@ def workload_ckf(args):
     return result
 
 
+def workload_fit(args):
+    """KF fit of 1,000,000 tracks with known hits in 64 uneven batches, one launch."""
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    sizes = synth.fit_batch_sizes(64, 1_000_000, 2000, 30000)
+    log("generating 64 fit batches")
+    evs = [synth.make_event(int(n), cfg=2, event=i, noise=0.0) for i, n in enumerate(sizes)]
+    ctx = make_ctx(6)
+    handles = [ctx.load_event(abi.EventArrays.from_synth(e, with_seeds=False, with_tracks=True)) for e in evs]
+    sync = torch.cuda.synchronize
+    for _ in range(args.warmup):
+        ctx.fit_batch(handles)
+    sync()
+    ctx.timer_reset()
+    elapsed = time_steps(lambda: ctx.fit_batch(handles), args.steps, 0, sync)
+    fit_ms, fit_n = ctx.timer_read(abi.TIMER_FIT)
+    n = int(sizes.sum())
+    hits = int(sum((e.truth_hit >= 0).sum() for e in evs))
+    flops = n * 9 * (FLOP_PER_FIT_LAYER - FLOP_PER_UPDATE) + hits * FLOP_PER_UPDATE_JOSEPH
+    avg_ms = fit_ms / max(fit_n, 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    bytes_ = n * BYTES_PER_FIT_TRACK
+    gbs = bytes_ / (avg_ms * 1e-3) / 1e9
+    res = {
+        "metric": "fitted tracks/sec (1,000,000 tracks in 64 uneven batches, one launch)",
+        "value": round(n * args.steps / elapsed, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "KF fit with known hits, 1,000,000 tracks, batches of 2,000-30,000, 10 layers",
+                   "batches": 64},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
+                     "kernel": "k_fit", "kernel_avg_ms": round(avg_ms, 4), "flop_per_launch": int(flops),
+                     "hbm_algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 5)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        ev = evs[0]
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.fit(oracle.config(ev.geometry), ev.hits, ev.prior_par, ev.prior_cov, ev.truth_hit, n_threads=threads)
+        wall = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": ev.n_seeds / wall, "unit": "tracks/s", "cores": threads, "kind": "oracle",
+                               "sample": f"batch 0 ({ev.n_seeds} tracks), {wall:.2f} s wall"}
+    ctx.close()
+    return res
+
+
+def workload_batched(args):
+    """256 uneven events in one batched launch vs the plain per-event builder."""
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    log("generating 256 uneven events")
+    evs = synth.batched_events(256, 500, 20000)
+    ctx = make_ctx(6, args.tuning)
+    handles = [ctx.load_event(e) for e in evs]
+    if args.tune:
+        log("autotuned:", ctx.autotune(handles).as_dict())
+    sync = torch.cuda.synchronize
+    tracks = int(sum(e.n_seeds for e in evs))
+    for _ in range(args.warmup):
+        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX)
+    sync()
+    ctx.timer_reset()
+    t_batch = time_steps(lambda: ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX), args.steps, 0, sync)
+    build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
+    n_plain = max(1, args.steps // 5)
+    t_plain = time_steps(lambda: [lib_build_plain(ctx, h) for h in handles], n_plain, 1, sync)
+    res = {
+        "metric": "tracks built/sec, 256 uneven events in one batched launch",
+        "value": round(tracks * args.steps / t_batch, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_batch / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256 events, tracks log-uniform in [500, 20000], noise U[0.1,0.5] per layer, k=6",
+                   "tracks": tracks, "tuning": ctx.get_tuning().as_dict()},
+        "build_kernel_avg_ms": round(build_ms / max(build_n, 1), 4),
+        "plain_builder_tracks_per_s": round(tracks * n_plain / t_plain, 1),
+        "speedup_vs_plain": round((tracks * args.steps / t_batch) / (tracks * n_plain / t_plain), 3),
+    }
+    ctx.close()
+    return res
+
+
+def workload_serve(args):
+    """Poisson arrivals of events (500-50,000 tracks, 30 % noise), served with
+    continuous batching; latency p50/p99 against the plain builder serving the
+    same arrivals one event at a time."""
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    n_pool = 48
+    sizes = synth.loguniform_sizes(n_pool, 500, 50000, cfg=4)
+    log(f"generating a pool of {n_pool} events")
+    pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(sizes)]
+    ctx = make_ctx(6, args.tuning)
+    ctx.serve_config(16 << 30, max_in_flight=64)
+    serve_latency(ctx, pool, 64, 1e9)                 # warm-up
+    t0 = time.perf_counter()
+    serve_latency(ctx, pool, 256, 1e9)
+    sat = 256 / (time.perf_counter() - t0)
+    out = {"metric": "served events/sec and p50/p99 latency (Poisson arrivals)", "unit": "events/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "events with tracks log-uniform in [500, 50000], 30% noise, k=6, budget 16 GiB",
+                      "pool": n_pool, "mean_tracks": float(sizes.mean())},
+           "saturated_events_per_s": round(sat, 1), "rates": []}
+    for frac in (0.5, 0.8):
+        rate = frac * sat
+        n = args.serve_events
+        t0 = time.perf_counter()
+        lat = serve_latency(ctx, pool, n, rate, seed=int(frac * 10))
+        wall = time.perf_counter() - t0
+        # the plain builder on the same arrival process, one event at a time
+        rng = np.random.default_rng(int(frac * 10))
+        gaps = rng.exponential(1.0 / rate, n)
+        order = rng.integers(0, len(pool), n)
+        arr = np.cumsum(gaps) - gaps[0]
+        plain_lat = []
+        t_start = time.perf_counter()
+        arrays = [abi.EventArrays.from_synth(e) for e in pool]
+        for j in range(min(n, args.serve_events)):
+            while time.perf_counter() - t_start < arr[j]:
+                pass
+            e = pool[order[j]]
+            h = ctx.load_event(arrays[order[j]])
+            ctx.build(h, e.n_seeds)
+            ctx.unload_event(h)
+            plain_lat.append(time.perf_counter() - t_start - arr[j])
+        plain_lat = np.array(plain_lat)
+        out["rates"].append({"rate_events_per_s": round(rate, 1), "events": n,
+                             "events_per_s": round(n / wall, 1),
+                             "tracks_per_s": round(float(sizes.mean()) * n / wall, 1),
+                             "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                             "plain_latency_p50_ms": round(float(np.percentile(plain_lat, 50)) * 1e3, 3),
+                             "plain_latency_p99_ms": round(float(np.percentile(plain_lat, 99)) * 1e3, 3)})
+    out["value"] = out["rates"][-1]["events_per_s"]
+    ctx.close()
+    return out
+
+
+def workload_calib(args):
+    """Plain device copy of a known size (calibrates hardware memory counters)."""
+    import torch
+    nbytes = 256 << 20
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    ctx = make_ctx(1)
+    for _ in range(args.steps):
+        ctx.calib_copy(src.data_ptr(), dst.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    ctx.close()
+    return {"metric": "calibration copy", "bytes_per_launch": nbytes, "launches": args.steps}
+
+
 def lib_build_plain(ctx, h):
     from paper_1702_06359_amd import abi
     abi.check(abi.lib().mkf_build(ctx.h, int(h), None))
@@ -210,7 +366,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ckf", choices=["ckf"])
+    ap.add_argument("--workload", default="ckf", choices=["ckf", "fit", "batched", "serve", "calib"])
+    ap.add_argument("--serve-events", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--quick", action="store_true", help="headline number only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -218,7 +375,8 @@ def main():
     args = ap.parse_args()
     gpu_count_guard(args.gpus)
     args.tuning = None
-    res = {"ckf": workload_ckf}[args.workload](args)
+    res = {"ckf": workload_ckf, "fit": workload_fit, "batched": workload_batched, "serve": workload_serve,
+           "calib": workload_calib}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

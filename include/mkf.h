@@ -136,11 +136,11 @@ typedef struct {
 /* Launch shapes.  None of them changes any result. */
 typedef struct {
     int32_t lanes_per_seed;   /* 1, 2, 4 or 8, >= max_cands; 0 = smallest valid */
-    int32_t waves_per_block;  /* 1 .. 16; 0 = 4 */
-    int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 256 */
-    int32_t bins_z;           /* hit-index bins in z per layer, 1 .. 1024; 0 = 16 */
+    int32_t waves_per_block;  /* 1 .. 4; 0 = 4 */
+    int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 1024 */
+    int32_t bins_z;           /* hit-index bins in z per layer, 1 .. 1024; 0 = 32 */
     int32_t persistent;       /* batched build: 1 = persistent waves on a work queue */
-    int32_t blocks_per_cu;    /* persistent grid size per compute unit, 1 .. 32; 0 = 8 */
+    int32_t blocks_per_cu;    /* persistent grid size per compute unit, 1 .. 32; 0 = 4 */
 } mkf_tuning;
 
 /* Counters of the last build of an event (zero unless MKF_BATCH_STATS). */

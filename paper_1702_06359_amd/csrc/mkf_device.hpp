@@ -95,7 +95,7 @@ __device__ __forceinline__ void turn_terms(float a, float &S1, float &C1, float 
     } else {
         float sa, ca;
         sincosf(a, &sa, &ca);
-        const float ia = 1.f / a;
+        const float ia = fast_rcp(a);
         S1 = sa * ia;
         C1 = (1.f - ca) * ia;
         S2 = (a * ca - sa) * ia * ia;
@@ -103,14 +103,33 @@ __device__ __forceinline__ void turn_terms(float a, float &S1, float &C1, float 
     }
 }
 
-// atan(u)/u
+// atan(u)/u: series below |u| = 0.25 (error < 1e-9), the library atan above
 __device__ __forceinline__ float atanc(float u)
 {
-    if (fabsf(u) < 1e-2f) {
-        const float u2 = u * u;
-        return fmaf(u2, fmaf(u2, 0.2f, -1.f / 3.f), 1.f);
+    if (fabsf(u) < 0.25f) {
+        const float v = u * u;
+        // 1 - v/3 + v^2/5 - v^3/7 + v^4/9 - v^5/11 + v^6/13
+        float r = fmaf(v, 1.f / 13.f, -1.f / 11.f);
+        r = fmaf(v, r, 1.f / 9.f);
+        r = fmaf(v, r, -1.f / 7.f);
+        r = fmaf(v, r, 1.f / 5.f);
+        r = fmaf(v, r, -1.f / 3.f);
+        return fmaf(v, r, 1.f);
     }
-    return atanf(u) / u;
+    return atanf(u) * fast_rcp(u);
+}
+
+// sines and cosines of the momentum angles of a state
+struct Trig {
+    float sph, cph, sth, cth;
+};
+
+__device__ __forceinline__ Trig trig_of(const float (&p)[6])
+{
+    Trig t;
+    sincosf(p[4], &t.sph, &t.cph);
+    sincosf(p[5], &t.sth, &t.cth);
+    return t;
 }
 
 // Propagate state p to the cylinder of radius r along the helix of the
@@ -121,37 +140,41 @@ __device__ __forceinline__ float atanc(float u)
 // straight line.  Writes the new state o and the Jacobian F = d o / d p on
 // the cylinder (the derivative at fixed s plus the change of s that keeps the
 // end point on the cylinder).  Returns false when r is never reached.
-__device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_per_qpt, float (&o)[6],
-                                          float (&F)[6][6])
+__device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
+                                          float (&o)[6], float (&F)[6][6])
 {
-    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4], th = p[5];
+    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
+    const float sph = tg.sph, cph = tg.cph;
     const float w = w_per_qpt * q;
-    float sph, cph;
-    sincosf(phi, &sph, &cph);
     const float b = fmaf(x, cph, y * sph);
     const float e = fmaf(y, cph, -x * sph);
     const float D = fmaf(r, r, -fmaf(x, x, y * y));
     const float alpha = fmaf(w, e, 1.f) - 0.25f * w * w * D;
     const float disc = fmaf(b, b, alpha * D);
     if (!(disc >= 0.f)) return false;
-    const float qd = sqrtf(disc);
-    const float roots[2] = {(b + qd != 0.f) ? 0.5f * D / (b + qd) : kInf,
-                            (alpha != 0.f) ? -(b + qd) / (2.f * alpha) : kInf};
+    const float qd = __builtin_amdgcn_sqrtf(disc);
     const float smin = 1e-6f * r;
-    float s = kInf;
+    // near-half root: when valid it is the first crossing, since every
+    // far-half solution is longer than pi/|w|
+    const float T1 = (b + qd != 0.f) ? 0.5f * D * fast_rcp(b + qd) : kInf;
+    float s = (fabsf(T1) < kInf) ? 2.f * T1 * atanc(w * T1) : -1.f;
+    if (!(s > smin && s * fabsf(w) <= kPi)) {
+        s = kInf;
+        const float roots[2] = {T1, (alpha != 0.f) ? -(b + qd) / (2.f * alpha) : kInf};
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float T = roots[i];
-        if (!(fabsf(T) < kInf)) continue;
-        const float u = w * T;
-        const float s1 = 2.f * T * atanc(u);
-        if (s1 > smin && s1 < s) s = s1;
-        if (w != 0.f) {
-            const float s2 = 2.f * (atanf(u) + copysignf(kPi, w)) / w;
-            if (s2 > smin && s2 < s) s = s2;
+        for (int i = 0; i < 2; ++i) {
+            const float T = roots[i];
+            if (!(fabsf(T) < kInf)) continue;
+            const float u = w * T;
+            const float s1 = 2.f * T * atanc(u);
+            if (s1 > smin && s1 < s) s = s1;
+            if (w != 0.f) {
+                const float s2 = 2.f * (atanf(u) + copysignf(kPi, w)) / w;
+                if (s2 > smin && s2 < s) s = s2;
+            }
         }
+        if (!(s < kInf)) return false;
     }
-    if (!(s < kInf)) return false;
 
     const float a = w * s;
     float S1, C1, S2, C2;
@@ -160,10 +183,8 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_
     const float B = fmaf(cph, C1, sph * S1);      // (cos phi - cos(phi+a))/a
     const float gx = fmaf(cph, S2, -sph * C2);    // dA/da
     const float gy = fmaf(sph, S2, cph * C2);     // dB/da
-    float sth, cth;
-    sincosf(th, &sth, &cth);
-    const float ist = 1.f / sth;
-    const float cot = cth * ist;
+    const float ist = fast_rcp(tg.sth);
+    const float cot = tg.cth * ist;
     const float nx = fmaf(s, A, x), ny = fmaf(s, B, y);
     const float ca = fmaf(-a, C1, 1.f), sa = a * S1;       // cos a, sin a
     const float cn = fmaf(cph, ca, -sph * sa), sn = fmaf(sph, ca, cph * sa);
@@ -172,7 +193,7 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_
     o[2] = fmaf(s, cot, z);
     o[3] = q;
     o[4] = wrap_pi(phi + a);
-    o[5] = th;
+    o[5] = p[5];
 
     // derivatives at fixed path
     const float Pxq = s * s * gx * w_per_qpt, Pxp = -s * B;
@@ -180,7 +201,7 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_
     const float Pzt = -s * ist * ist;
     const float Ppq = s * w_per_qpt;
     // d s / d p from x'^2 + y'^2 = r^2
-    const float iden = -1.f / fmaf(nx, cn, ny * sn);
+    const float iden = -fast_rcp(fmaf(nx, cn, ny * sn));
     const float dsx = nx * iden, dsy = ny * iden;
     const float dsq = fmaf(nx, Pxq, ny * Pyq) * iden;
     const float dsp = fmaf(nx, Pxp, ny * Pyp) * iden;
@@ -211,22 +232,20 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], float r, float w_
 // Multiple scattering in a layer of x0 radiation lengths, crossed at the
 // state's position: Highland angle th0 with the path factor 1/|cos alpha|,
 // added to (q/pT, phi, theta) at fixed |p|.
-__device__ __forceinline__ void add_scattering(const float (&p)[6], float x0, float mass2, float (&c)[21])
+__device__ __forceinline__ void add_scattering(const float (&p)[6], const Trig &tg, float x0, float mass2,
+                                               float (&c)[21])
 {
     if (!(x0 > 0.f)) return;
     const float x = p[0], y = p[1], q = p[3];
-    float sph, cph, sth, cth;
-    sincosf(p[4], &sph, &cph);
-    sincosf(p[5], &sth, &cth);
-    const float ir0 = rsqrtf(fmaf(x, x, y * y));
-    const float cosa = fmaxf(fabsf(sth * fmaf(cph, x * ir0, sph * y * ir0)), 1e-6f);
-    const float t = x0 / cosa;
-    const float k = fabsf(q) * sth;                           // 1/|p|
-    const float inv_bp = k * sqrtf(fmaf(mass2 * k, k, 1.f));  // 1/(beta p)
-    const float th0 = 0.0136f * inv_bp * sqrtf(t) * fmaf(0.038f, logf(t), 1.f);
+    const float ir0 = __builtin_amdgcn_rsqf(fmaf(x, x, y * y));
+    const float cosa = fmaxf(fabsf(tg.sth * fmaf(tg.cph, x * ir0, tg.sph * y * ir0)), 1e-6f);
+    const float t = x0 * fast_rcp(cosa);
+    const float k = fabsf(q) * tg.sth;                                          // 1/|p|
+    const float inv_bp = k * __builtin_amdgcn_sqrtf(fmaf(mass2 * k, k, 1.f));    // 1/(beta p)
+    const float th0 = 0.0136f * inv_bp * __builtin_amdgcn_sqrtf(t) * fmaf(0.038f, __logf(t), 1.f);
     const float v = th0 * th0;
-    const float ist = 1.f / sth;
-    const float cot = cth * ist;
+    const float ist = fast_rcp(tg.sth);
+    const float cot = tg.cth * ist;
     c[sym(4, 4)] += v * ist * ist;
     c[sym(5, 5)] += v;
     c[sym(3, 3)] += q * q * cot * cot * v;
@@ -264,7 +283,7 @@ __device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], float 
     const float suu = fmaf(-sh, Mu[0], fmaf(ch, Mu[1], var_u));
     const float suz = Mu[2];
     const float szz = Mz[2] + var_z;
-    const float idet = 1.f / fmaf(suu, szz, -suz * suz);
+    const float idet = fast_rcp(fmaf(suu, szz, -suz * suz));
     const float i00 = szz * idet, i01 = -suz * idet, i11 = suu * idet;
     const float chi2 = fmaf(ru, fmaf(i00, ru, i01 * rz), rz * fmaf(i01, ru, i11 * rz));
     float K0[6], K1[6];

@@ -224,29 +224,28 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const LayerParam lp = P.layer[L];
     const bool active = S.live && !S.stopped;
 
-    float pp[6], pc[21];    // state offered to this lane's children
-#pragma unroll
-    for (int i = 0; i < 6; ++i) pp[i] = S.p[i];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) pc[i] = S.c[i];
-
-    // 1. scattering of the layer being left, propagation, transport
+    // 1. scattering of the layer being left, propagation, transport.  The
+    //    prediction replaces the state in place; a lane whose helix misses
+    //    the layer keeps its state and stops.
     bool predicted = false;
     if (active) {
         float np[6], F[6][6];
-        const bool ok = propagate(S.p, lp.r, P.w_per_qpt, np, F);
+        const Trig tg = trig_of(S.p);
+        const bool ok = propagate(S.p, tg, lp.r, P.w_per_qpt, np, F);
         if (kStats) cnt.prop++;
         if (ok) {
-            add_scattering(S.p, P.layer[L - 1].x0, P.mass2, pc);
-            transport(F, pc);
+            add_scattering(S.p, tg, P.layer[L - 1].x0, P.mass2, S.c);
+            transport(F, S.c);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) pp[i] = np[i];
+            for (int i = 0; i < 6; ++i) S.p[i] = np[i];
             predicted = true;
         } else {
             S.stopped = 1;
             S.status = 2;
         }
     }
+    const float (&pp)[6] = S.p;
+    const float (&pc)[21] = S.c;
 
     // 2. windowed hit search: keep this lane's best K hit children
     float lc[K];
@@ -266,7 +265,9 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         const float du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
         const float dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
         const float phipos = atan2f(pp[1], pp[0]);
-        const float dphi = (du >= lp.r ? 0.5f * kPi : asinf(du / lp.r)) + 1e-5f;
+        // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
+        const float xr = du / lp.r;
+        const float dphi = (xr >= 0.7f ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
         const int nphi = P.bins_phi;
         if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
             const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
@@ -325,15 +326,12 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         if (kStats) cnt.acc += nacc;
     }
 
-    // 3. hole child, or stop on this surface when neither a hit nor a hole is left
+    // 3. hole child, or stop on this surface (with the prediction as state)
+    //    when neither a hit nor a hole is left
     const bool hole = predicted && (nacc == 0 || P.hole_always) && S.n_holes < P.max_holes;
     if (predicted && nacc == 0 && S.n_holes >= P.max_holes) {
         S.stopped = 1;
         S.status = 1;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) S.p[i] = pp[i];
-#pragma unroll
-        for (int i = 0; i < 21; ++i) S.c[i] = pc[i];
     }
     bool tail = S.live && (S.stopped || hole);
     const unsigned long long tail_key = beam_key(S.n_hits, S.chi2, slot, kHoleId);
@@ -374,9 +372,9 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const int parent = alive ? key_parent(mine) : slot;
     const int src = gbase + parent;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.p[i] = __shfl(pp[i], src);
+    for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) S.c[i] = __shfl(pc[i], src);
+    for (int i = 0; i < 21; ++i) S.c[i] = __shfl(S.c[i], src);
     const int p_holes = __shfl(S.n_holes, src);
     const int p_stopped = __shfl(S.stopped, src);
     const int p_status = __shfl(S.status, src);
@@ -545,11 +543,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int L = 0; L < P.n_layers; ++L) {
         if (L > 0) {
             float np[6], F[6][6];
-            if (!propagate(p, P.layer[L].r, P.w_per_qpt, np, F)) {
+            const Trig tg = trig_of(p);
+            if (!propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F)) {
                 status = 2;
                 break;
             }
-            add_scattering(p, P.layer[L - 1].x0, P.mass2, c);
+            add_scattering(p, tg, P.layer[L - 1].x0, P.mass2, c);
             transport(F, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];

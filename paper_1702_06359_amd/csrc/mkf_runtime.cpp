@@ -232,13 +232,13 @@ mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
     if (G < c.max_cands) return fail(MKF_E_INVALID, "lanes_per_seed must be >= max_cands");
     if (t->waves_per_block == 0) t->waves_per_block = 4;
     if (t->waves_per_block < 1 || t->waves_per_block > 4) return fail(MKF_E_INVALID, "waves_per_block must be 1..4");
-    if (t->bins_phi == 0) t->bins_phi = 256;
-    if (t->bins_z == 0) t->bins_z = 16;
+    if (t->bins_phi == 0) t->bins_phi = 1024;
+    if (t->bins_z == 0) t->bins_z = 32;
     if (t->bins_phi < 1 || t->bins_phi > 4096 || t->bins_z < 1 || t->bins_z > 1024 ||
         (long long)t->bins_phi * t->bins_z > (1 << 20))
         return fail(MKF_E_INVALID, "bins out of range (phi 1..4096, z 1..1024, product <= 2^20)");
     if (t->persistent != 0 && t->persistent != 1) return fail(MKF_E_INVALID, "persistent must be 0 or 1");
-    if (t->blocks_per_cu == 0) t->blocks_per_cu = 8;
+    if (t->blocks_per_cu == 0) t->blocks_per_cu = 4;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 32) return fail(MKF_E_INVALID, "blocks_per_cu must be 1..32");
     return MKF_OK;
 }
