@@ -26,17 +26,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic FP32 operation counts per unit of work, counted from the kernel
-# source (fma = 2, add/mul/div/sqrt/transcendental = 1).
-FLOP_PER_CAND_LAYER = 480     # scattering 40 + propagation and Jacobian 138 + transport 272 + window 30
-FLOP_PER_CHI2 = 36            # tangent-plane residual, 2x2 innovation, chi2
-FLOP_PER_UPDATE = 186         # gain, state and covariance update
-FLOP_PER_FIT_LAYER = 40 + 138 + 272 + 186   # scattering, propagation, transport, update
-FLOP_PER_UPDATE_JOSEPH = 466  # fit update in Joseph form
-BYTES_PER_FIT_TRACK = 216 + 40 + 10 * 16 + 216 + 20   # prior, hit ids, hits, fitted state, chi2/counts
+# source (fma = 2; add, sub, mul, rcp, sqrt, rsq, sin, cos, log, atan = 1;
+# compares, selects and integer work not counted).
+FLOP_SCATTER = 40             # Highland angle and the 4 noise terms
+FLOP_PROPAGATE = 160          # path root, helix step and the Jacobian
+FLOP_TRANSPORT = 272          # F C F^T against the Jacobian's sparsity
+FLOP_WINDOW = 37              # search window and bin range
+FLOP_PER_CAND_LAYER = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT + FLOP_WINDOW   # 509
+FLOP_PER_CHI2 = 39            # window tests, tangent-plane residual, 2x2 innovation, chi2
+FLOP_PER_UPDATE = 187         # gain, state and covariance update
+FLOP_PER_UPDATE_JOSEPH = 445  # fit update in Joseph form
+FLOP_PER_FIT_STEP = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT   # 472, layers 1..9 of a fit
+BYTES_PER_FIT_TRACK = 216 + 40 + 10 * 16 + 232   # prior (f64), hit ids, hits (float4), fit result
+BYTES_PER_SEED_IO = 228 + 276     # seed in (f64 state, cov, hit ids) + track out
+BYTES_PER_HIT = 16                # binned hit read once
+BYTES_PER_BIN = 4                 # bin offset read once
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_SEED_IO = 228 + 280     # seed in (par, cov, hits) + track out (par, cov, hits, counts, chi2)
-BYTES_PER_HIT = 16                # binned hit read once
 
 
 def log(*a):
@@ -220,7 +226,7 @@ def workload_fit(args):
     fit_ms, fit_n = ctx.timer_read(abi.TIMER_FIT)
     n = int(sizes.sum())
     hits = int(sum((e.truth_hit >= 0).sum() for e in evs))
-    flops = n * 9 * (FLOP_PER_FIT_LAYER - FLOP_PER_UPDATE) + hits * FLOP_PER_UPDATE_JOSEPH
+    flops = n * 9 * FLOP_PER_FIT_STEP + hits * FLOP_PER_UPDATE_JOSEPH
     avg_ms = fit_ms / max(fit_n, 1)
     achieved = flops / (avg_ms * 1e-3) / 1e12
     bytes_ = n * BYTES_PER_FIT_TRACK

@@ -117,7 +117,8 @@ typedef struct {
  *  n_holes: holes taken (building) / layers without a hit (fitting).
  *  chi2: sum of the accepted hits' chi2 on the building layers / over all
  *        updates of the fit.
- *  ndof: 2 * updates - 5 (fitting); 2 * building hits (building).
+ *  ndof: 2 * n_hits - 5 (two measured coordinates per hit, five track
+ *        parameters).
  *  status: 0 reached the last layer, 1 stopped when no hit and no hole was
  *        left, 2 the helix does not reach the next layer. */
 typedef struct {

@@ -28,6 +28,61 @@ __device__ __forceinline__ float wrap_pi(float a)
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reads through a pointer known to address global memory (emits global
+// rather than flat loads for pointers that were themselves loaded from memory).
+__device__ __forceinline__ int load_global(const int *p)
+{
+    typedef const __attribute__((address_space(1))) int *gptr;
+    return *(gptr)p;
+}
+
+__device__ __forceinline__ float4 load_global(const float4 *p)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) v4 *gptr;
+    const v4 v = *(gptr)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// atan2 to ~2e-7 rad: octant reduction and an odd degree-15 polynomial
+// (least-squares fit to atan on [0, 1], max error 1.1e-7 in FP32).  Used only
+// for the search-window centre, whose bins are padded well beyond this error.
+__device__ __forceinline__ float fast_atan2(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mn * fast_rcp(mx);
+    const float v = t * t;
+    float r = fmaf(v, -0.00405456058f, 0.0218629526f);
+    r = fmaf(v, r, -0.0559123558f);
+    r = fmaf(v, r, 0.0964220321f);
+    r = fmaf(v, r, -0.13908634f);
+    r = fmaf(v, r, 0.199465672f);
+    r = fmaf(v, r, -0.33329861f);
+    r = fmaf(v, r, 0.999999336f);
+    float a = t * r;
+    if (ay > ax) a = 1.57079632679f - a;
+    if (x < 0.f) a = 3.14159265359f - a;
+    return copysignf(a, y);
+}
+
+// (sin, cos) of an angle advanced by a small increment d: series below
+// |d| = 0.25 (error < 1e-9), the library sincos above.
+__device__ __forceinline__ void rotate(float &s, float &c, float d)
+{
+    float sd, cd;
+    if (fabsf(d) < 0.25f) {
+        const float d2 = d * d;
+        sd = d * fmaf(d2, fmaf(d2, fmaf(d2, -1.f / 5040.f, 1.f / 120.f), -1.f / 6.f), 1.f);
+        cd = fmaf(d2, fmaf(d2, fmaf(d2, -1.f / 720.f, 1.f / 24.f), -0.5f), 1.f);
+    } else {
+        sincosf(d, &sd, &cd);
+    }
+    const float ns = fmaf(s, cd, c * sd);
+    c = fmaf(c, cd, -s * sd);
+    s = ns;
+}
+
 // Structure of the propagation Jacobian in (x, y, z, q/pT, phi, theta):
 // 0 = known zero, 2 = known one, 1 = computed.  The transport below is
 // unrolled against this pattern so known zeros and ones cost nothing (the
@@ -132,16 +187,18 @@ __device__ __forceinline__ Trig trig_of(const float (&p)[6])
     return t;
 }
 
-// Propagate state p to the cylinder of radius r along the helix of the
+// Propagate state p (with the sines and cosines of its angles in tg) to the
+// cylinder of radius r along the helix of the
 // uniform field (curvature w = w_per_qpt * q/pT, w > 0 turning
 // counter-clockwise).  The transverse path s is the smallest positive root of
 // the half-turn-angle quadratic  alpha T^2 + b T - D/4 = 0  (T = tan(a/2)/w,
 // a = w s) of the chord condition |(x,y) + chord| = r; its w -> 0 limit is the
 // straight line.  Writes the new state o and the Jacobian F = d o / d p on
 // the cylinder (the derivative at fixed s plus the change of s that keeps the
-// end point on the cylinder).  Returns false when r is never reached.
+// end point on the cylinder), and the sine and cosine of the new momentum
+// azimuth.  Returns false when r is never reached.
 __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
-                                          float (&o)[6], float (&F)[6][6])
+                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
 {
     const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
     const float sph = tg.sph, cph = tg.cph;
@@ -194,6 +251,8 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
     o[3] = q;
     o[4] = wrap_pi(phi + a);
     o[5] = p[5];
+    sn_out = sn;
+    cn_out = cn;
 
     // derivatives at fixed path
     const float Pxq = s * s * gx * w_per_qpt, Pxp = -s * B;
@@ -269,7 +328,7 @@ __device__ __forceinline__ float hit_chi2(const float (&p)[6], const float (&c)[
 
 // Kalman update with one hit.  K = C H^T S^-1, p += K r, C -= K (H C) on the
 // upper triangle (so C stays exactly symmetric).  Returns the hit's chi2.
-__device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], float ch, float sh, float zh,
+__device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], Trig &tg, float ch, float sh, float zh,
                                            float var_u, float var_z)
 {
     const float ru = fmaf(p[0], sh, -p[1] * ch);
@@ -292,9 +351,15 @@ __device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], float 
         K0[j] = fmaf(Mu[j], i00, Mz[j] * i01);
         K1[j] = fmaf(Mu[j], i01, Mz[j] * i11);
     }
+    float dp[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) p[j] = fmaf(K0[j], ru, fmaf(K1[j], rz, p[j]));
+    for (int j = 0; j < 6; ++j) {
+        dp[j] = fmaf(K0[j], ru, K1[j] * rz);
+        p[j] += dp[j];
+    }
     p[4] = wrap_pi(p[4]);
+    rotate(tg.sph, tg.cph, dp[4]);
+    rotate(tg.sth, tg.cth, dp[5]);
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -306,8 +371,8 @@ __device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], float 
 // Used where the prediction is much looser than the hit (a fit starting
 // from a wide prior): there C - K H C subtracts two nearly equal numbers and
 // loses FP32 digits, while the Joseph form only scales them by (I - K H).
-__device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21], float ch, float sh, float zh,
-                                                  float var_u, float var_z)
+__device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21], Trig &tg, float ch, float sh,
+                                                  float zh, float var_u, float var_z)
 {
     const float ru = fmaf(p[0], sh, -p[1] * ch);
     const float rz = zh - p[2];
@@ -329,9 +394,15 @@ __device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21],
         K0[j] = fmaf(Mu[j], i00, Mz[j] * i01);
         K1[j] = fmaf(Mu[j], i01, Mz[j] * i11);
     }
+    float dp[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) p[j] = fmaf(K0[j], ru, fmaf(K1[j], rz, p[j]));
+    for (int j = 0; j < 6; ++j) {
+        dp[j] = fmaf(K0[j], ru, K1[j] * rz);
+        p[j] += dp[j];
+    }
     p[4] = wrap_pi(p[4]);
+    rotate(tg.sph, tg.cph, dp[4]);
+    rotate(tg.sth, tg.cth, dp[5]);
     // one row of D = (I - K H) C at a time; the result goes to a fresh array
     // because every row of D reads the old C
     float nc[21];

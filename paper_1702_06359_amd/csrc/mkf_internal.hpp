@@ -21,7 +21,8 @@ struct LayerParam {
     float x0;
     float inv_dphi;    // bins_phi / (2 pi)
     float inv_dz;      // bins_z / (2 half_z)
-    float pad0, pad1, pad2;
+    float inv_r;
+    float pad1, pad2;
 };
 
 // Building and fitting parameters for one launch.
@@ -81,6 +82,7 @@ struct DevEvent {
     // plain per-layer builder state (slots = n_seeds * lanes_per_seed)
     float *st_par;                       // [6][slots]
     float *st_cov;                       // [21][slots]
+    float *st_trig;                      // [4][slots] sin, cos of phi and theta
     float *st_chi2;                      // [slots]
     int *st_meta;                        // [slots]
     int *st_hist_hit;                    // [n_layers][slots]

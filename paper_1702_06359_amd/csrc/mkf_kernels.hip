@@ -151,6 +151,7 @@ __global__ void k_index_scatter(const Params P, const BatchArgs B)
 struct Lane {
     float p[6];
     float c[21];
+    Trig tg;           // sines and cosines of p[4] (phi) and p[5] (theta)
     float chi2;
     int n_hits;
     int n_holes;
@@ -199,6 +200,7 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
     S.n_holes = 0;
     S.chi2 = 0.f;
     S.n_hits = 0;
+    S.tg = Trig{0.f, 1.f, 1.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 6; ++i) S.p[i] = 0.f;
 #pragma unroll
@@ -209,6 +211,7 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
 #pragma unroll
     for (int i = 0; i < 21; ++i) S.c[i] = (float)E.seed_cov[21 * (size_t)seed + i];
     for (int L = 0; L < P.n_seed_layers; ++L) S.n_hits += E.seed_hits[(size_t)seed * P.n_seed_layers + L] >= 0;
+    S.tg = trig_of(S.p);
 }
 
 // One building layer for every lane of a wavefront (Section 2: propagate the
@@ -229,15 +232,16 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     //    the layer keeps its state and stops.
     bool predicted = false;
     if (active) {
-        float np[6], F[6][6];
-        const Trig tg = trig_of(S.p);
-        const bool ok = propagate(S.p, tg, lp.r, P.w_per_qpt, np, F);
+        float np[6], F[6][6], sn, cn;
+        const bool ok = propagate(S.p, S.tg, lp.r, P.w_per_qpt, np, F, sn, cn);
         if (kStats) cnt.prop++;
         if (ok) {
-            add_scattering(S.p, tg, P.layer[L - 1].x0, P.mass2, S.c);
+            add_scattering(S.p, S.tg, P.layer[L - 1].x0, P.mass2, S.c);
             transport(F, S.c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) S.p[i] = np[i];
+            S.tg.sph = sn;
+            S.tg.cph = cn;
             predicted = true;
         } else {
             S.stopped = 1;
@@ -264,9 +268,9 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
         const float du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
         const float dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
-        const float phipos = atan2f(pp[1], pp[0]);
+        const float phipos = fast_atan2(pp[1], pp[0]);
         // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
-        const float xr = du / lp.r;
+        const float xr = du * lp.inv_r;
         const float dphi = (xr >= 0.7f ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
         const int nphi = P.bins_phi;
         if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
@@ -299,12 +303,12 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
                 for (int sg = 0; sg < 2; ++sg) {
                     const int lo = sg ? s1lo : s0lo, hi = sg ? s1hi : s0hi;
                     if (lo > hi) continue;
-                    const int beg = off[row + lo], end = off[row + hi + 1];
+                    const int beg = load_global(off + row + lo), end = load_global(off + row + hi + 1);
                     for (int h0 = beg; h0 < end; h0 += kHitUnroll) {
                         // issue the loads of several hits before using any (latency hiding)
                         float4 hv[kHitUnroll];
 #pragma unroll
-                        for (int u = 0; u < kHitUnroll; ++u) hv[u] = bh[min(h0 + u, end - 1)];
+                        for (int u = 0; u < kHitUnroll; ++u) hv[u] = load_global(bh + min(h0 + u, end - 1));
 #pragma unroll
                         for (int u = 0; u < kHitUnroll; ++u) {
                             if (h0 + u >= end) break;
@@ -375,6 +379,10 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
 #pragma unroll
     for (int i = 0; i < 21; ++i) S.c[i] = __shfl(S.c[i], src);
+    S.tg.sph = __shfl(S.tg.sph, src);
+    S.tg.cph = __shfl(S.tg.cph, src);
+    S.tg.sth = __shfl(S.tg.sth, src);
+    S.tg.cth = __shfl(S.tg.cth, src);
     const int p_holes = __shfl(S.n_holes, src);
     const int p_stopped = __shfl(S.stopped, src);
     const int p_status = __shfl(S.status, src);
@@ -387,8 +395,8 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     S.stopped = p_stopped;
     S.status = p_status;
     if (hid != kHoleId) {
-        const float4 hv = E.hits[E.layer_off[L] + (int)hid];
-        kf_update(S.p, S.c, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+        const float4 hv = load_global(E.hits + E.layer_off[L] + (int)hid);
+        kf_update(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, P.var_z);
         if (kStats) cnt.upd++;
         H.put(L, lane, (int)hid, parent);
     } else {
@@ -506,6 +514,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int i = 0; i < 6; ++i) S.p[i] = S.live ? E.st_par[i * ns + slot] : 0.f;
 #pragma unroll
         for (int i = 0; i < 21; ++i) S.c[i] = S.live ? E.st_cov[i * ns + slot] : 0.f;
+        S.tg = S.live ? Trig{E.st_trig[0 * ns + slot], E.st_trig[1 * ns + slot], E.st_trig[2 * ns + slot],
+                             E.st_trig[3 * ns + slot]}
+                      : Trig{0.f, 1.f, 1.f, 0.f};
     }
     Count cnt;
     layer_step<G, kStats>(S, L, P, E, lane, H, cnt);
@@ -519,6 +530,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             for (int i = 0; i < 6; ++i) E.st_par[i * ns + slot] = S.p[i];
 #pragma unroll
             for (int i = 0; i < 21; ++i) E.st_cov[i * ns + slot] = S.c[i];
+            E.st_trig[0 * ns + slot] = S.tg.sph;
+            E.st_trig[1 * ns + slot] = S.tg.cph;
+            E.st_trig[2 * ns + slot] = S.tg.sth;
+            E.st_trig[3 * ns + slot] = S.tg.cth;
         }
     }
     flush_counts<kStats>(cnt, E, lane);
@@ -540,25 +555,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int i = 0; i < 21; ++i) oc[i] = c[i] = (float)E.track_cov[21 * t + i];
     float chi2 = 0.f;
     int nupd = 0, status = 0;
+    Trig tg = trig_of(p);
     for (int L = 0; L < P.n_layers; ++L) {
         if (L > 0) {
-            float np[6], F[6][6];
-            const Trig tg = trig_of(p);
-            if (!propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F)) {
+            float np[6], F[6][6], sn, cn;
+            if (!propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn)) {
                 status = 2;
                 break;
             }
             add_scattering(p, tg, P.layer[L - 1].x0, P.mass2, c);
+            tg.sph = sn;
+            tg.cph = cn;
             transport(F, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
         const int h = E.track_hits[t * P.n_layers + L];
         if (h >= 0) {
-            const float4 hv = E.hits[E.layer_off[L] + h];
+            const float4 hv = load_global(E.hits + E.layer_off[L] + h);
             // Joseph form: a fit starts from a wide prior, where the plain
             // form C - K H C would lose FP32 digits
-            chi2 += kf_update_joseph(p, c, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+            chi2 += kf_update_joseph(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_z);
             ++nupd;
 #pragma unroll
             for (int i = 0; i < 6; ++i) op[i] = p[i];

@@ -154,6 +154,7 @@ size_t carve_plain(const EventShape &s, int slots, void *base, DevEvent *v)
     const size_t S = (size_t)slots;
     v->st_par = c.take<float>(6 * S);
     v->st_cov = c.take<float>(21 * S);
+    v->st_trig = c.take<float>(4 * S);
     v->st_chi2 = c.take<float>(S);
     v->st_meta = c.take<int>(S);
     v->st_hist_hit = c.take<int>((size_t)s.n_layers * S);
@@ -181,6 +182,7 @@ void derive_params(mkf_ctx *ctx)
         P.layer[L].x0 = (float)c.layer_x0[L];
         P.layer[L].inv_dphi = (float)(t.bins_phi / (2.0 * M_PI));
         P.layer[L].inv_dz = (float)(t.bins_z / (2.0 * c.layer_half_z[L]));
+        P.layer[L].inv_r = (float)(1.0 / c.layer_r[L]);
     }
     P.n_layers = c.n_layers;
     P.n_seed_layers = c.n_seed_layers;

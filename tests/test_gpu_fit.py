@@ -40,17 +40,21 @@ def _check(name, g, o, tol=None, prior_cov=None):
     dpar, dcov = state_errors(g["par"][ok], g["cov"][ok], o["par"][ok], o["cov"][ok])
     dchi = np.abs(g["chi2"][ok] - o["chi2"][ok]) / (1.0 + o["chi2"][ok])
     cov_tol = np.full(int(ok.sum()), tol["tau_cov_rel"])
+    chi_tol = np.full(int(ok.sum()), tol["eps_chi2_rel"])
     if prior_cov is not None:
+        # each chi2 term is r^2/S with S built from that covariance
         R = conditioning(prior_cov[ok], o["par"][ok], o["cov"][ok])
         cov_tol = np.maximum(cov_tol, tol["cov_conditioning_factor"] * R * 2.0 ** -24)
+        chi_tol = np.maximum(chi_tol, tol["cov_conditioning_factor"] * R * 2.0 ** -24)
     rep = dict(n=int(ok.sum()), max_dpar_sigma=dpar.max(), p9999_dpar_sigma=np.quantile(dpar, 0.9999),
                p99_dpar_sigma=np.quantile(dpar, 0.99), max_dcov_rel=dcov.max(),
                p9999_dcov_rel=np.quantile(dcov, 0.9999), max_dchi2_rel=dchi.max(),
-               p9999_dchi2_rel=np.quantile(dchi, 0.9999), max_dcov_over_tol=(dcov / cov_tol).max())
+               p9999_dchi2_rel=np.quantile(dchi, 0.9999), max_dcov_over_tol=(dcov / cov_tol).max(),
+               max_dchi2_over_tol=(dchi / chi_tol).max())
     report(name, rep)
     assert rep["max_dpar_sigma"] <= tol["tau_par_sigma"], rep
     assert rep["max_dcov_over_tol"] <= 1.0, rep
-    assert rep["max_dchi2_rel"] <= tol["eps_chi2_rel"], rep
+    assert rep["max_dchi2_over_tol"] <= 1.0, rep
 
 
 def conditioning(prior_cov, par, cov):
