@@ -314,14 +314,15 @@ __device__ __forceinline__ void add_scattering(const float (&p)[6], const Trig &
 // chi2 of a hit (cos phi_h, sin phi_h, z_h) against a predicted state: the
 // residual on the plane tangent to the layer at the hit, u along
 // (-sin phi_h, cos phi_h, 0) and z, with S = H C H^T + V.
-__device__ __forceinline__ float hit_chi2(const float (&p)[6], const float (&c)[21], float ch, float sh,
-                                          float zh, float var_u, float var_z)
+__device__ __forceinline__ float hit_chi2(float x, float y, float z, float cxx, float cxy, float cyy, float cxz,
+                                          float cyz, float czz, float ch, float sh, float zh, float var_u,
+                                          float var_z)
 {
-    const float ru = fmaf(p[0], sh, -p[1] * ch);
-    const float rz = zh - p[2];
-    const float suu = fmaf(sh * sh, c[sym(0, 0)], fmaf(-2.f * sh * ch, c[sym(0, 1)], fmaf(ch * ch, c[sym(1, 1)], var_u)));
-    const float suz = fmaf(-sh, c[sym(0, 2)], ch * c[sym(1, 2)]);
-    const float szz = c[sym(2, 2)] + var_z;
+    const float ru = fmaf(x, sh, -y * ch);
+    const float rz = zh - z;
+    const float suu = fmaf(sh * sh, cxx, fmaf(-2.f * sh * ch, cxy, fmaf(ch * ch, cyy, var_u)));
+    const float suz = fmaf(-sh, cxz, ch * cyz);
+    const float szz = czz + var_z;
     const float idet = fast_rcp(fmaf(suu, szz, -suz * suz));
     return fmaf(szz * ru, ru, fmaf(-2.f * suz * ru, rz, suu * rz * rz)) * idet;
 }

@@ -56,7 +56,8 @@ struct DevEvent {
     float4 *hits;                        // [n_hits] caller order: (cos phi_h, sin phi_h, z, 0)
     float4 *binned;                      // [n_hits] grouped by layer then bin: (c, s, z, id bits)
     int *bin_of;                         // [n_hits] bin of each caller-order hit
-    int *bin_count;                      // [n_layers][n_bins] counts, then scatter cursors
+    int *bin_rank;                       // [n_hits] position of the hit inside its bin
+    int *bin_count;                      // [n_layers][n_bins] counts (zero between index builds)
     int *bin_off;                        // [n_layers][n_bins + 1] absolute index into `binned`
     const double *seed_par;              // [n_seeds][6]
     const double *seed_cov;              // [n_seeds][21]
@@ -103,7 +104,7 @@ struct BatchArgs {
     int total_hits;
     int total_tracks;
     int seeds_per_item;
-    int pad;
+    int max_layer_hits;          // largest layer of any event (index launch shape)
 };
 
 // Launch helpers implemented in mkf_kernels.hip.

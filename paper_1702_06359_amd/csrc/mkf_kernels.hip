@@ -38,6 +38,36 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src)
+{
+    const unsigned lo = __shfl((unsigned)v, src);
+    const unsigned hi = __shfl((unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Minimum of v over the G lanes of each seed group.  Power-of-two groups
+// use a butterfly; other sizes take the minimum over cyclic windows of
+// 2, 4 and 8 lanes, which covers any G <= 8.
+template <int G>
+__device__ __forceinline__ unsigned long long group_min(unsigned long long v, int gbase, int slot)
+{
+    if constexpr ((G & (G - 1)) == 0) {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const unsigned long long t = shfl_xor_u64(v, o);
+            v = t < v ? t : v;
+        }
+    } else {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int s2 = slot + o >= G ? slot + o - G : slot + o;
+            const unsigned long long t = shfl_u64(v, gbase + s2);
+            v = t < v ? t : v;
+        }
+    }
+    return v;
+}
+
 __global__ void k_fill_i32(int *__restrict__ p, int v, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,81 +98,127 @@ __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_sta
 // eta is a function of z, so the grid is (z, phi): bin = iz * bins_phi + iphi.
 // A counting sort over all events of a batch at once.
 
-// Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it, count.
-__global__ void k_index_prep(const Params P, const BatchArgs B)
+// Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it and
+// take its position in the bin.  Grid (chunks, event x layer).
+__global__ void __launch_bounds__(256) k_index_prep(const Params P, const BatchArgs B)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= B.total_hits) return;
-    const int e = upper_bound_i32(B.hit_prefix, B.n_events + 1, g) - 1;
+    const int e = blockIdx.y / P.n_layers;
+    const int L = blockIdx.y - e * P.n_layers;
     const DevEvent &E = B.events[e];
-    const int h = g - B.hit_prefix[e];
-    const int L = upper_bound_i32(E.layer_off, P.n_layers + 1, h) - 1;
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const LayerParam lp = P.layer[L];
-    const double x = E.raw_xyz[3 * (size_t)h], y = E.raw_xyz[3 * (size_t)h + 1];
-    const double ir = 1.0 / sqrt(x * x + y * y);
-    const float c = (float)(x * ir), s = (float)(y * ir);
-    const float z = (float)E.raw_xyz[3 * (size_t)h + 2];
-    const float phi = atan2f(s, c);
-    int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
-    int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
-    ip = min(max(ip, 0), P.bins_phi - 1);
-    iz = min(max(iz, 0), P.bins_z - 1);
-    const int bin = iz * P.bins_phi + ip;
-    E.hits[h] = make_float4(c, s, z, 0.f);
-    E.bin_of[h] = bin;
-    atomicAdd(&E.bin_count[L * P.bins_phi * P.bins_z + bin], 1);
+    int *cnt = E.bin_count + L * P.bins_phi * P.bins_z;
+    for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
+        const double x = E.raw_xyz[3 * (size_t)h], y = E.raw_xyz[3 * (size_t)h + 1];
+        const double ir = 1.0 / sqrt(x * x + y * y);
+        const float c = (float)(x * ir), s = (float)(y * ir);
+        const float z = (float)E.raw_xyz[3 * (size_t)h + 2];
+        const float phi = atan2f(s, c);
+        int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
+        int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
+        ip = min(max(ip, 0), P.bins_phi - 1);
+        iz = min(max(iz, 0), P.bins_z - 1);
+        const int bin = iz * P.bins_phi + ip;
+        E.hits[h] = make_float4(c, s, z, 0.f);
+        E.bin_of[h] = bin;
+        E.bin_rank[h] = atomicAdd(&cnt[bin], 1);
+    }
 }
 
 // Pass 2: one block per (event, layer): exclusive scan of the bin counts into
-// absolute offsets; counts are reset to serve as scatter cursors.
+// absolute offsets.  Each thread owns 32 consecutive bins, so a layer of up to
+// 32768 bins is one step whose loads are all in flight together; the counts are
+// cleared on the way so the next index build starts from zero.
 __global__ void __launch_bounds__(1024) k_index_scan(const Params P, const BatchArgs B)
 {
-    __shared__ int s_sum[1024];
+    constexpr int kPer = 32;   // consecutive bins per thread
+    __shared__ int s_wave[16];
     const int e = blockIdx.x / P.n_layers;
     const int L = blockIdx.x - e * P.n_layers;
     const DevEvent &E = B.events[e];
     const int nb = P.bins_phi * P.bins_z;
     int *cnt = E.bin_count + L * nb;
     int *off = E.bin_off + L * (nb + 1);
-    const int per = (nb + blockDim.x - 1) / blockDim.x;
-    const int b0 = threadIdx.x * per;
-    const int b1 = min(b0 + per, nb);
-    int local = 0;
-    for (int b = b0; b < b1; ++b) local += cnt[b];
-    s_sum[threadIdx.x] = local;
-    __syncthreads();
-    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-        const int v = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    const int n_waves = blockDim.x >> 6;
+    const bool vec = (nb & 3) == 0;   // then every thread's first bin is 16-byte aligned
+    int carry = E.layer_off[L];
+    for (int base = 0; base < nb; base += blockDim.x * kPer) {
+        const int b0 = base + threadIdx.x * kPer;
+        int v[kPer];
+        if (vec && b0 + kPer <= nb) {
+#pragma unroll
+            for (int j = 0; j < kPer; j += 4) {
+                const int4 q = *reinterpret_cast<const int4 *>(cnt + b0 + j);
+                v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) v[j] = b0 + j < nb ? cnt[b0 + j] : 0;
+        }
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) sum += v[j];
+        int x = sum;   // inclusive scan of the per-thread sums inside the wavefront
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(x, o);
+            if (lane >= o) x += t;
+        }
+        if (lane == kWave - 1) s_wave[wave] = x;
         __syncthreads();
-        s_sum[threadIdx.x] += v;
+        if (wave == 0) {
+            int w = lane < n_waves ? s_wave[lane] : 0;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const int t = __shfl_up(w, o);
+                if (lane >= o) w += t;
+            }
+            if (lane < n_waves) s_wave[lane] = w;
+        }
+        __syncthreads();
+        int run = carry + (wave > 0 ? s_wave[wave - 1] : 0) + x - sum;
+        if (vec && b0 + kPer <= nb) {
+#pragma unroll
+            for (int j = 0; j < kPer; j += 4) *reinterpret_cast<int4 *>(cnt + b0 + j) = make_int4(0, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                off[b0 + j] = run;
+                run += v[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                if (b0 + j < nb) {
+                    off[b0 + j] = run;
+                    cnt[b0 + j] = 0;
+                }
+                run += v[j];
+            }
+        }
+        carry += s_wave[n_waves - 1];
         __syncthreads();
     }
-    int run = E.layer_off[L] + s_sum[threadIdx.x] - local;
-    for (int b = b0; b < b1; ++b) {
-        const int v = cnt[b];
-        off[b] = run;
-        cnt[b] = 0;
-        run += v;
-    }
-    if (threadIdx.x == blockDim.x - 1) off[nb] = E.layer_off[L + 1];
+    if (threadIdx.x == 0) off[nb] = E.layer_off[L + 1];
 }
 
 // Pass 3: scatter each hit into its bin (order inside a bin is irrelevant:
 // every hit of a window is tested and ties are broken by hit index).
-__global__ void k_index_scatter(const Params P, const BatchArgs B)
+__global__ void __launch_bounds__(256) k_index_scatter(const Params P, const BatchArgs B)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= B.total_hits) return;
-    const int e = upper_bound_i32(B.hit_prefix, B.n_events + 1, g) - 1;
+    const int e = blockIdx.y / P.n_layers;
+    const int L = blockIdx.y - e * P.n_layers;
     const DevEvent &E = B.events[e];
-    const int h = g - B.hit_prefix[e];
-    const int L = upper_bound_i32(E.layer_off, P.n_layers + 1, h) - 1;
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const int nb = P.bins_phi * P.bins_z;
-    const int bin = E.bin_of[h];
-    const int pos = E.bin_off[L * (nb + 1) + bin] + atomicAdd(&E.bin_count[L * nb + bin], 1);
-    float4 v = E.hits[h];
-    v.w = __int_as_float(h - E.layer_off[L]);
-    E.binned[pos] = v;
+    const int *off = E.bin_off + L * (nb + 1);
+    for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
+        const int bin = E.bin_of[h];
+        const int pos = off[bin] + E.bin_rank[h];
+        float4 v = E.hits[h];
+        v.w = __int_as_float(h - h0);
+        E.binned[pos] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -171,8 +247,6 @@ struct Hist {          // per-layer record of every kept candidate: (hit, parent
     }
 };
 
-constexpr int kHitUnroll = 4;
-
 struct Count {
     unsigned long long prop = 0, chi2 = 0, acc = 0, upd = 0, scan = 0;
 };
@@ -190,6 +264,226 @@ __device__ __forceinline__ void list_insert(float (&lc)[K], unsigned (&lid)[K], 
         c = less ? tc : c;
         id = less ? ti : id;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-cooperative hit search.
+//
+// Each lane owns one candidate whose window is a few (z row, phi segment)
+// runs of the binned hit array.  The non-empty runs of all lanes are listed
+// in LDS with running offsets; the (candidate, hit) pairs they define are then
+// evaluated 64 at a time, one pair per lane whatever candidate it belongs to,
+// and the accepted ones are linked into per-candidate lists that each owner
+// finally merges into its own best-K list.  A wavefront's work so follows the
+// total number of hits in its windows instead of its largest window, and no
+// lane idles through another lane's chi2 or list insertion.
+
+constexpr int kRuns = 128;   // run records held before their pairs are evaluated
+constexpr int kAcc = 128;    // accepted entries held before the owners merge them
+constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
+
+struct SearchLds {
+    float4 own[3][kWave];    // owner state {x, y, z, chi2}, {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}
+    int4 run[kRuns];         // {first binned index, first pair index, owner lane, -}
+    int2 acc[kAcc];          // {accumulated chi2 bits, hit id << 8 | next entry}
+    int head[kWave];         // first accepted entry of each owner
+    int mark[kWave];         // run starting at each pair slot of the current round
+};
+
+// LDS written by some lanes of a wavefront and read by others: the wavefront's
+// LDS operations are executed in order, so it only takes a compiler barrier
+// and the wait for outstanding LDS operations.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
+{
+    int s = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(s, o);
+        if (lane >= o) s += t;
+    }
+    return s - x;
+}
+
+template <int K, bool kStats>
+struct WaveSearch {
+    SearchLds &W;
+    const float4 *bh;
+    const Params &P;
+    const int lane;
+    float (&lc)[K];
+    unsigned (&lid)[K];
+    Count &cnt;
+    int n_runs = 0, n_pairs = 0, n_acc = 0, n_mine = 0;
+
+    // owners merge their accepted entries into their best-K lists
+    __device__ __forceinline__ void merge()
+    {
+        wave_lds_sync();
+        int e = W.head[lane];
+        while (e != kEnd) {
+            const int2 v = W.acc[e];
+            list_insert<K>(lc, lid, __int_as_float(v.x), (unsigned)v.y >> 8);
+            ++n_mine;
+            e = v.y & kEnd;
+        }
+        W.head[lane] = kEnd;
+        n_acc = 0;
+        wave_lds_sync();
+    }
+
+    // evaluate every pair of the listed runs, one per lane and round
+    __device__ __forceinline__ void evaluate()
+    {
+        wave_lds_sync();
+        int first = 0;   // first run not yet started
+        for (int t0 = 0; t0 < n_pairs; t0 += kWave) {
+            // the run of each pair slot: runs starting in this round mark their
+            // slot, the others continue the last run started before it
+            W.mark[lane] = -1;
+            const int r = first + lane;
+            const int start = r < n_runs ? W.run[r].y : 0x7FFFFFFF;
+            const bool starts = start < t0 + kWave;
+            if (starts) W.mark[start - t0] = r;
+            const int prev = first - 1;
+            first += __popcll(__ballot(starts));
+            wave_lds_sync();
+            const int mk = W.mark[lane];
+            const unsigned long long below = __ballot(mk >= 0) & (~0ull >> (63 - lane));
+            const int from = below ? 63 - __clzll((long long)below) : 0;
+            const int mk_from = __shfl(mk, from);
+            const int rr = below ? mk_from : prev;
+            const int pair = t0 + lane;
+            bool ok = false;
+            float tot = 0.f;
+            unsigned hid = 0;
+            int o = 0;
+            if (pair < n_pairs) {
+                const int4 R = W.run[rr];
+                o = R.z;
+                const float4 hv = load_global(bh + R.x + (pair - R.y));
+                const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
+                const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
+                if (kStats) {
+                    cnt.scan++;
+                    if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd) cnt.chi2++;
+                }
+                const float c2 = hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z, P.var_u,
+                                          P.var_z);
+                ok = fwd && c2 < P.chi2_cut;
+                tot = a.w + c2;
+                hid = (unsigned)__float_as_int(hv.w);
+            }
+            const unsigned long long am = __ballot(ok);
+            const int n_new = __popcll(am);
+            if (n_acc + n_new > kAcc) merge();
+            if (ok) {
+                const int e = n_acc + lanes_below(am);
+                const int next = atomicExch(&W.head[o], e);
+                W.acc[e] = make_int2(__float_as_int(tot), (int)((hid << 8) | (unsigned)next));
+            }
+            n_acc += n_new;
+        }
+        n_runs = 0;
+        n_pairs = 0;
+    }
+
+    // list one run per lane (len 0: none)
+    __device__ __forceinline__ void add_run(int beg, int len)
+    {
+        const unsigned long long m = __ballot(len > 0);
+        const int n_new = __popcll(m);
+        if (n_runs + n_new > kRuns || n_pairs >= (1 << 29)) evaluate();
+        const int ex = wave_exclusive_sum(len, lane);
+        if (len > 0) W.run[n_runs + lanes_below(m)] = make_int4(beg, n_pairs + ex, lane, 0);
+        n_runs += n_new;
+        n_pairs += __builtin_amdgcn_readlane(ex + len, kWave - 1);
+    }
+};
+
+// Windowed search of layer L for the predicted state (pp, pc) of every lane
+// with `predicted` set: the best K accepted hits of the lane in (lc, lid),
+// sorted by accumulated chi2 then hit id; returns the lane's accepted count.
+// All lanes of the wavefront must call it together.
+template <int K, bool kStats>
+__device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], float chi2, bool predicted,
+                                            int L, const LayerParam &lp, const Params &P, const DevEvent &E,
+                                            int lane, SearchLds &W, float (&lc)[K], unsigned (&lid)[K], Count &cnt)
+{
+    int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
+    float du = 0.f, dz = 0.f;
+    if (predicted) {
+        // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
+        // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
+        const float cxx = pc[sym(0, 0)], cxy = pc[sym(0, 1)], cyy = pc[sym(1, 1)];
+        const float hd = 0.5f * (cxx - cyy);
+        const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
+        du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
+        dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
+        const float phipos = fast_atan2(pp[1], pp[0]);
+        // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
+        const float xr = du * lp.inv_r;
+        const float dphi = (xr >= 0.7f ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
+        const int nphi = P.bins_phi;
+        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
+            const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
+            const int ihi = (int)floorf((phipos + dphi + kPi) * lp.inv_dphi);
+            izlo = min(max((int)floorf((pp[2] - dz - 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
+            const int izhi = min(max((int)floorf((pp[2] + dz + 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
+            n_rows = izhi - izlo + 1;
+            if (ihi - ilo + 1 >= nphi) {
+                s0lo = 0;
+                s0hi = nphi - 1;
+            } else if (ilo < 0) {
+                s0lo = ilo + nphi;
+                s0hi = nphi - 1;
+                s1lo = 0;
+                s1hi = ihi;
+                n_seg = 2;
+            } else if (ihi >= nphi) {
+                s0lo = ilo;
+                s0hi = nphi - 1;
+                s1lo = 0;
+                s1hi = ihi - nphi;
+                n_seg = 2;
+            } else {
+                s0lo = ilo;
+                s0hi = ihi;
+            }
+        }
+    }
+    W.own[0][lane] = make_float4(pp[0], pp[1], pp[2], chi2);
+    W.own[1][lane] = make_float4(pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(0, 2)]);
+    W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
+    W.head[lane] = kEnd;
+
+    WaveSearch<K, kStats> ws{W, E.binned, P, lane, lc, lid, cnt};
+    const int n_runs = n_rows * n_seg;
+    const int *off = E.bin_off + L * (P.bins_phi * P.bins_z + 1);
+    for (int q = 0; __ballot(q < n_runs) != 0; ++q) {
+        int beg = 0, len = 0;
+        if (q < n_runs) {
+            const int sg = n_seg == 2 ? (q & 1) : 0;
+            const int row = (izlo + (n_seg == 2 ? q >> 1 : q)) * P.bins_phi;
+            beg = load_global(off + row + (sg ? s1lo : s0lo));
+            len = load_global(off + row + (sg ? s1hi : s0hi) + 1) - beg;
+        }
+        ws.add_run(beg, len);
+    }
+    ws.evaluate();
+    ws.merge();
+    return ws.n_mine;
 }
 
 __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Params &P, int seed, bool first_slot)
@@ -219,11 +513,11 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
 // 3.2.1: re-rank and prune to max_cands per seed).
 template <int G, bool kStats>
 __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
-                                           const int lane, const Hist &H, Count &cnt)
+                                           const int lane, const Hist &H, SearchLds &W, Count &cnt)
 {
-    constexpr int K = kMaxCands;
-    const int slot = lane & (G - 1);
-    const int gbase = lane & ~(G - 1);
+    constexpr int K = G;     // a parent contributes at most max_cands <= G children
+    const int gbase = (lane / G) * G;
+    const int slot = lane - gbase;
     const LayerParam lp = P.layer[L];
     const bool active = S.live && !S.stopped;
 
@@ -259,76 +553,8 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         lc[i] = kInf;
         lid[i] = 0xFFFFFFFFu;
     }
-    int nacc = 0;
-    if (predicted) {
-        // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
-        // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
-        const float cxx = pc[sym(0, 0)], cxy = pc[sym(0, 1)], cyy = pc[sym(1, 1)];
-        const float hd = 0.5f * (cxx - cyy);
-        const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
-        const float du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
-        const float dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
-        const float phipos = fast_atan2(pp[1], pp[0]);
-        // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
-        const float xr = du * lp.inv_r;
-        const float dphi = (xr >= 0.7f ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
-        const int nphi = P.bins_phi;
-        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
-            const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
-            const int ihi = (int)floorf((phipos + dphi + kPi) * lp.inv_dphi);
-            const int izlo = min(max((int)floorf((pp[2] - dz - 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
-            const int izhi = min(max((int)floorf((pp[2] + dz + 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
-            int s0lo, s0hi, s1lo = 1, s1hi = 0;
-            if (ihi - ilo + 1 >= nphi) {
-                s0lo = 0;
-                s0hi = nphi - 1;
-            } else if (ilo < 0) {
-                s0lo = ilo + nphi;
-                s0hi = nphi - 1;
-                s1lo = 0;
-                s1hi = ihi;
-            } else if (ihi >= nphi) {
-                s0lo = ilo;
-                s0hi = nphi - 1;
-                s1lo = 0;
-                s1hi = ihi - nphi;
-            } else {
-                s0lo = ilo;
-                s0hi = ihi;
-            }
-            const int *off = E.bin_off + L * (nphi * P.bins_z + 1);
-            const float4 *bh = E.binned;
-            for (int iz = izlo; iz <= izhi; ++iz) {
-                const int row = iz * nphi;
-                for (int sg = 0; sg < 2; ++sg) {
-                    const int lo = sg ? s1lo : s0lo, hi = sg ? s1hi : s0hi;
-                    if (lo > hi) continue;
-                    const int beg = load_global(off + row + lo), end = load_global(off + row + hi + 1);
-                    for (int h0 = beg; h0 < end; h0 += kHitUnroll) {
-                        // issue the loads of several hits before using any (latency hiding)
-                        float4 hv[kHitUnroll];
-#pragma unroll
-                        for (int u = 0; u < kHitUnroll; ++u) hv[u] = load_global(bh + min(h0 + u, end - 1));
-#pragma unroll
-                        for (int u = 0; u < kHitUnroll; ++u) {
-                            if (h0 + u >= end) break;
-                            if (kStats) cnt.scan++;
-                            if (fabsf(hv[u].z - pp[2]) > dz) continue;
-                            if (fabsf(fmaf(pp[0], hv[u].y, -pp[1] * hv[u].x)) > du) continue;
-                            if (fmaf(pp[0], hv[u].x, pp[1] * hv[u].y) <= 0.f) continue;
-                            if (kStats) cnt.chi2++;
-                            const float c2 = hit_chi2(pp, pc, hv[u].x, hv[u].y, hv[u].z, P.var_u, P.var_z);
-                            if (c2 < P.chi2_cut) {
-                                ++nacc;
-                                list_insert<K>(lc, lid, S.chi2 + c2, (unsigned)__float_as_int(hv[u].w));
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        if (kStats) cnt.acc += nacc;
-    }
+    const int nacc = search_layer<K, kStats>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lc, lid, cnt);
+    if (kStats) cnt.acc += nacc;
 
     // 3. hole child, or stop on this surface (with the prediction as state)
     //    when neither a hit nor a hole is left
@@ -349,12 +575,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
             if (lc[0] < kInf) hk = beam_key(child_hits, lc[0], slot, lid[0]);
             else if (tail) hk = tail_key;
         }
-        unsigned long long m = hk;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const unsigned long long t = shfl_xor_u64(m, o);
-            m = t < m ? t : m;
-        }
+        const unsigned long long m = group_min<G>(hk, gbase, slot);
         if (hk == m && m != ~0ull) {
             if (lc[0] < kInf) {
 #pragma unroll
@@ -369,12 +590,13 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         }
         if (slot == r) mine = m;
     }
+    if (lane >= (kWave / G) * G) mine = ~0ull;   // lanes outside every seed group
 
     // 5. each kept entry moves to the lane of its rank: fetch the parent's
     //    state and apply the Kalman update with the entry's hit
     const bool alive = mine != ~0ull;
     const int parent = alive ? key_parent(mine) : slot;
-    const int src = gbase + parent;
+    const int src = alive ? gbase + parent : lane;
 #pragma unroll
     for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
 #pragma unroll
@@ -411,8 +633,8 @@ template <int G>
 __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, const DevEvent &E, int lane,
                                               int seed, const Hist &H)
 {
-    const int gbase = lane & ~(G - 1);
-    if ((lane & (G - 1)) != 0 || seed >= E.n_seeds) return;
+    const int gbase = (lane / G) * G;
+    if (lane != gbase || seed >= E.n_seeds) return;
     const size_t s = (size_t)seed;
 #pragma unroll
     for (int i = 0; i < 6; ++i) E.out_par[6 * s + i] = (double)S.p[i];
@@ -447,6 +669,13 @@ __device__ __forceinline__ void flush_counts(const Count &cnt, const DevEvent &E
     }
 }
 
+// Dynamic LDS of the batched builder: the per-layer records of every wave
+// (an int and a byte per lane and layer), then one SearchLds per wave.
+__host__ __device__ constexpr int search_lds_offset(int waves, int n_layers)
+{
+    return ((waves * n_layers * kWave * 5 + 15) / 16) * 4;   // in ints, 16-byte aligned
+}
+
 // Batched builder.  Each wavefront takes work items (event, group of 64/G
 // seeds) - from a device counter when persistent, else from its block index -
 // and runs every building layer of its seeds with the state in registers.
@@ -460,6 +689,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int per_wave = P.n_layers * kWave;
     Hist H{s_dyn + wave * per_wave, reinterpret_cast<unsigned char *>(s_dyn + W * per_wave) + wave * per_wave,
            kWave};
+    SearchLds &SL = reinterpret_cast<SearchLds *>(s_dyn + search_lds_offset(W, P.n_layers))[wave];
     int item = blockIdx.x * W + wave;
     for (;;) {
         if (persistent) {
@@ -472,11 +702,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         const int e = uniform(upper_bound_i32(B.item_prefix, B.n_events + 1, item) - 1);
         const DevEvent &E = B.events[e];
         const int seed = (item - B.item_prefix[e]) * B.seeds_per_item + lane / G;
-        const bool valid = seed < E.n_seeds;
+        const bool valid = lane < (kWave / G) * G && seed < E.n_seeds;
         Lane S;
-        init_lane(S, E, P, valid ? seed : 0, valid && (lane & (G - 1)) == 0);
+        init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
         Count cnt;
-        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats>(S, L, P, E, lane, H, cnt);
+        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats>(S, L, P, E, lane, H, SL, cnt);
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
         flush_counts<kStats>(cnt, E, lane);
         if (!persistent) break;
@@ -495,13 +725,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int first = item * kSeedsPerWave;
     if (first >= E.n_seeds) return;
     const int seed = first + lane / G;
-    const bool valid = seed < E.n_seeds;
+    const bool valid = lane < kSeedsPerWave * G && seed < E.n_seeds;
     const int ns = E.st_slots;
     const int slot = item * kWave + lane;
     Hist H{E.st_hist_hit + item * kWave, E.st_hist_par + item * kWave, ns};
     Lane S;
     if (L == P.n_seed_layers) {
-        init_lane(S, E, P, valid ? seed : 0, valid && (lane & (G - 1)) == 0);
+        init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
     } else {
         const int meta = E.st_meta[slot];
         S.live = meta & 1;
@@ -518,8 +748,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                              E.st_trig[3 * ns + slot]}
                       : Trig{0.f, 1.f, 1.f, 0.f};
     }
+    extern __shared__ int s_dyn[];
+    SearchLds &SL = reinterpret_cast<SearchLds *>(s_dyn)[threadIdx.x >> 6];
     Count cnt;
-    layer_step<G, kStats>(S, L, P, E, lane, H, cnt);
+    layer_step<G, kStats>(S, L, P, E, lane, H, SL, cnt);
     if (L == P.n_layers - 1) {
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
     } else {
@@ -625,13 +857,17 @@ hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bo
 hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_hits <= 0) return hipSuccess;
-    k_index_prep<<<blocks_for(b.total_hits, 256), 256, 0, s>>>(p, b);
+    // chunks per (event, layer): about one hit per thread for the largest
+    // layer (more independent atomics in flight), striding beyond that
+    const unsigned chunks = std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256)));
+    const dim3 grid(chunks, (unsigned)(b.n_events * p.n_layers));
+    k_index_prep<<<grid, 256, 0, s>>>(p, b);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     k_index_scan<<<(unsigned)(b.n_events * p.n_layers), 1024, 0, s>>>(p, b);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    k_index_scatter<<<blocks_for(b.total_hits, 256), 256, 0, s>>>(p, b);
+    k_index_scatter<<<grid, 256, 0, s>>>(p, b);
     return hipGetLastError();
 }
 
@@ -639,7 +875,7 @@ template <int G, bool kStats>
 static hipError_t launch_batch_t(const Params &p, const BatchArgs &b, int wpb, int persistent, int n_blocks,
                                  hipStream_t s)
 {
-    const size_t lds = (size_t)wpb * p.n_layers * kWave * (sizeof(int) + 1);
+    const size_t lds = sizeof(int) * (size_t)search_lds_offset(wpb, p.n_layers) + wpb * sizeof(SearchLds);
     const unsigned grid = persistent ? (unsigned)n_blocks : blocks_for(b.total_items, wpb);
     if (grid == 0) return hipSuccess;
     k_build_batch<G, kStats><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
@@ -649,17 +885,18 @@ static hipError_t launch_batch_t(const Params &p, const BatchArgs &b, int wpb, i
 hipError_t launch_build_batch(const Params &p, const BatchArgs &b, int G, int wpb, int persistent, int n_blocks,
                               bool stats, hipStream_t s)
 {
-    switch (G * 2 + (stats ? 1 : 0)) {
-    case 2: return launch_batch_t<1, false>(p, b, wpb, persistent, n_blocks, s);
-    case 3: return launch_batch_t<1, true>(p, b, wpb, persistent, n_blocks, s);
-    case 4: return launch_batch_t<2, false>(p, b, wpb, persistent, n_blocks, s);
-    case 5: return launch_batch_t<2, true>(p, b, wpb, persistent, n_blocks, s);
-    case 8: return launch_batch_t<4, false>(p, b, wpb, persistent, n_blocks, s);
-    case 9: return launch_batch_t<4, true>(p, b, wpb, persistent, n_blocks, s);
-    case 16: return launch_batch_t<8, false>(p, b, wpb, persistent, n_blocks, s);
-    case 17: return launch_batch_t<8, true>(p, b, wpb, persistent, n_blocks, s);
+#define MKF_BATCH_CASE(g)                                                                            \
+    case g: return stats ? launch_batch_t<g, true>(p, b, wpb, persistent, n_blocks, s)              \
+                         : launch_batch_t<g, false>(p, b, wpb, persistent, n_blocks, s);
+    switch (G) {
+        MKF_BATCH_CASE(1)
+        MKF_BATCH_CASE(2)
+        MKF_BATCH_CASE(4)
+        MKF_BATCH_CASE(6)
+        MKF_BATCH_CASE(8)
     default: return hipErrorInvalidValue;
     }
+#undef MKF_BATCH_CASE
 }
 
 template <int G, bool kStats>
@@ -669,7 +906,7 @@ static hipError_t launch_layer_t(const Params &p, const DevEvent *ev_dev, int n_
     const int items = (n_seeds + kWave / G - 1) / (kWave / G);
     const unsigned grid = blocks_for(items, wpb);
     if (grid == 0) return hipSuccess;
-    k_build_layer<G, kStats><<<grid, wpb * kWave, 0, s>>>(p, ev_dev, L);
+    k_build_layer<G, kStats><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
     return hipGetLastError();
 }
 
@@ -677,17 +914,18 @@ hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const Dev
                               int wpb, bool stats, hipStream_t s)
 {
     const int n = ev_host.n_seeds;
-    switch (G * 2 + (stats ? 1 : 0)) {
-    case 2: return launch_layer_t<1, false>(p, ev_dev, n, L, wpb, s);
-    case 3: return launch_layer_t<1, true>(p, ev_dev, n, L, wpb, s);
-    case 4: return launch_layer_t<2, false>(p, ev_dev, n, L, wpb, s);
-    case 5: return launch_layer_t<2, true>(p, ev_dev, n, L, wpb, s);
-    case 8: return launch_layer_t<4, false>(p, ev_dev, n, L, wpb, s);
-    case 9: return launch_layer_t<4, true>(p, ev_dev, n, L, wpb, s);
-    case 16: return launch_layer_t<8, false>(p, ev_dev, n, L, wpb, s);
-    case 17: return launch_layer_t<8, true>(p, ev_dev, n, L, wpb, s);
+#define MKF_LAYER_CASE(g)                                                                            \
+    case g: return stats ? launch_layer_t<g, true>(p, ev_dev, n, L, wpb, s)                          \
+                         : launch_layer_t<g, false>(p, ev_dev, n, L, wpb, s);
+    switch (G) {
+        MKF_LAYER_CASE(1)
+        MKF_LAYER_CASE(2)
+        MKF_LAYER_CASE(4)
+        MKF_LAYER_CASE(6)
+        MKF_LAYER_CASE(8)
     default: return hipErrorInvalidValue;
     }
+#undef MKF_LAYER_CASE
 }
 
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)

@@ -110,6 +110,7 @@ size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_v
     v->hits = c.take<float4>(n);
     v->binned = c.take<float4>(n);
     v->bin_of = c.take<int>(n);
+    v->bin_rank = c.take<int>(n);
     v->seed_par = c.take<double>(6 * ns);
     v->seed_cov = c.take<double>(21 * ns);
     v->seed_hits = c.take<int>((size_t)s.n_seed_layers * ns);
@@ -224,13 +225,17 @@ mkf_status check_config(const mkf_config *c)
 
 mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
 {
+    static const int kLanes[] = {1, 2, 4, 6, 8};
     if (t->lanes_per_seed == 0) {
-        int G = 1;
-        while (G < c.max_cands) G <<= 1;
-        t->lanes_per_seed = G;
+        for (int g : kLanes)
+            if (g >= c.max_cands) {
+                t->lanes_per_seed = g;
+                break;
+            }
     }
     const int G = t->lanes_per_seed;
-    if (G != 1 && G != 2 && G != 4 && G != 8) return fail(MKF_E_INVALID, "lanes_per_seed must be 1, 2, 4 or 8");
+    if (G != 1 && G != 2 && G != 4 && G != 6 && G != 8)
+        return fail(MKF_E_INVALID, "lanes_per_seed must be 1, 2, 4, 6 or 8");
     if (G < c.max_cands) return fail(MKF_E_INVALID, "lanes_per_seed must be >= max_cands");
     if (t->waves_per_block == 0) t->waves_per_block = 4;
     if (t->waves_per_block < 1 || t->waves_per_block > 4) return fail(MKF_E_INVALID, "waves_per_block must be 1..4");
@@ -330,6 +335,8 @@ mkf_status ensure_batch_scratch(mkf_ctx *ctx, int n)
 mkf_status gather_events(mkf_ctx *ctx, const int32_t *handles, int32_t n, std::vector<EventRec *> *recs)
 {
     if (n < 0 || (n > 0 && !handles)) return fail(MKF_E_INVALID, "bad handle list");
+    if ((long long)n * ctx->cfg.n_layers > 65535)
+        return fail(MKF_E_INVALID, "at most %d events per batch", 65535 / ctx->cfg.n_layers);
     std::vector<int32_t> seen(handles, handles + n);
     std::sort(seen.begin(), seen.end());
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
@@ -491,7 +498,7 @@ void destroy_event(mkf_ctx *ctx, EventRec *rec)
 
 // Make sure the event's index tables match the current bin grid.  *rebuilt is
 // set when the tables were (re)allocated and the index must be built.
-mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt)
+mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s)
 {
     const int bp = ctx->tuning.bins_phi, bz = ctx->tuning.bins_z;
     *rebuilt = false;
@@ -504,6 +511,8 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt)
         return fail(MKF_E_NOMEM, "hit index: %zu bytes", bytes);
     }
     carve_index(rec->shape, bp * bz, rec->index, &rec->view);
+    // the index build expects zero bin counts (and leaves them at zero)
+    MKF_HIP(launch_fill_i32(rec->view.bin_count, 0, rec->shape.n_layers * bp * bz, s));
     rec->index_bins_phi = bp;
     rec->index_bins_z = bz;
     drop_plain_graph(rec);
@@ -533,7 +542,10 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     int *hp = reinterpret_cast<int *>(h + o_hit);
     int *tp = reinterpret_cast<int *>(h + o_trk);
     long long items = 0, hits = 0, trks = 0;
+    int max_layer = 0;
     for (int i = 0; i < n; ++i) {
+        const EventShape &sh = recs[i]->shape;
+        for (int L = 0; L < sh.n_layers; ++L) max_layer = std::max(max_layer, sh.layer_off[L + 1] - sh.layer_off[L]);
         ev[i] = recs[i]->view;
         ip[i] = (int)items;
         hp[i] = (int)hits;
@@ -559,6 +571,7 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     args->total_hits = (int)hits;
     args->total_tracks = (int)trks;
     args->seeds_per_item = spi;
+    args->max_layer_hits = max_layer;
     return MKF_OK;
 }
 
@@ -570,7 +583,9 @@ mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<E
     (void)recs;
     const Params &P = ctx->params;
     const bool stats = flags & MKF_BATCH_STATS, reindex = flags & MKF_BATCH_REINDEX;
-    if (stats || reindex) MKF_HIP(launch_batch_zero(P, args, stats, reindex, s));
+    // bin counts are left at zero by every index build; fresh tables are
+    // cleared when they are allocated
+    if (stats) MKF_HIP(launch_batch_zero(P, args, true, false, s));
     if (reindex) {
         if (timed) timer_begin(ctx, 1, s);
         MKF_HIP(launch_index(P, args, s));
@@ -726,7 +741,7 @@ mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle)
     if ((st = create_event(ctx, shape, &ctx->heap, &rec)) != MKF_OK) return st;
     bool rebuilt = false;
     if ((st = upload_event(ctx, rec.get(), ev, ctx->stream)) != MKF_OK ||
-        (st = ensure_index(ctx, rec.get(), &rebuilt)) != MKF_OK ||
+        (st = ensure_index(ctx, rec.get(), &rebuilt, ctx->stream)) != MKF_OK ||
         (st = upload_view(rec.get(), ctx->stream)) != MKF_OK ||
         (st = ensure_batch_scratch(ctx, 1)) != MKF_OK) {
         destroy_event(ctx, rec.get());
@@ -739,7 +754,7 @@ mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle)
         destroy_event(ctx, rec.get());
         return st;
     }
-    hipError_t e = launch_batch_zero(ctx->params, args, true, true, ctx->stream);
+    hipError_t e = launch_batch_zero(ctx->params, args, true, false, ctx->stream);
     if (e == hipSuccess) e = launch_index(ctx->params, args, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -769,7 +784,7 @@ static mkf_status reindex_if_needed(mkf_ctx *ctx, const std::vector<EventRec *> 
     *any = false;
     for (EventRec *r : recs) {
         bool rebuilt = false;
-        mkf_status st = ensure_index(ctx, r, &rebuilt);
+        mkf_status st = ensure_index(ctx, r, &rebuilt, ctx->stream);
         if (st != MKF_OK) return st;
         if (rebuilt) {
             if ((st = upload_view(r, ctx->stream)) != MKF_OK) return st;
@@ -797,7 +812,6 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
         if ((st = stage_batch(ctx, one, ctx->batch_dev, ctx->batch_host, seeds_per_item(G), &args, ctx->stream)) !=
             MKF_OK)
             return st;
-        MKF_HIP(launch_batch_zero(ctx->params, args, false, true, ctx->stream));
         MKF_HIP(launch_index(ctx->params, args, ctx->stream));
     }
     if (rec->plain_G != G || !rec->plain) {
@@ -1134,7 +1148,7 @@ mkf_status mkf_autotune(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tun
     double cur_ms = 0;
     if ((st = measure(cur, &cur_ms)) != MKF_OK) return st;
     std::vector<int> lanes;
-    for (int G = 1; G <= kMaxCands; G <<= 1)
+    for (int G : {1, 2, 4, 6, 8})
         if (G >= ctx->cfg.max_cands) lanes.push_back(G);
     const std::vector<int> waves = {1, 2, 4};
     const std::vector<int> bphi = {64, 128, 256, 512, 1024};

@@ -142,7 +142,7 @@ mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *s
 mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap, std::unique_ptr<EventRec> *out);
 mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s);
 void destroy_event(mkf_ctx *ctx, EventRec *rec);
-mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt);
+mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s);
 mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
                        BatchArgs *args, hipStream_t s);
 size_t batch_scratch_bytes(int n_events);

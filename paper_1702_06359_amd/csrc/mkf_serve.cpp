@@ -298,7 +298,7 @@ struct Server {
                     std::unique_ptr<EventRec> rec;
                     if (create_event(ctx, t->shape, slab.get(), &rec) != MKF_OK) break;
                     bool rebuilt = false;
-                    if (ensure_index(ctx, rec.get(), &rebuilt) != MKF_OK) {
+                    if (ensure_index(ctx, rec.get(), &rebuilt, streams[si]) != MKF_OK) {
                         destroy_event(ctx, rec.get());
                         break;
                     }

@@ -123,7 +123,7 @@ def test_launch_shapes_do_not_change_results(gpu_required):
     ev = synth.make_event(1200, cfg=212, event=0, noise=0.3)
     ref = None
     shapes = [dict(), dict(bins_phi=64, bins_z=4), dict(bins_phi=1024, bins_z=64), dict(waves_per_block=1),
-              dict(persistent=0), dict(lanes_per_seed=2), dict(lanes_per_seed=8, waves_per_block=2)]
+              dict(persistent=0), dict(lanes_per_seed=2), dict(lanes_per_seed=6), dict(lanes_per_seed=8, waves_per_block=2)]
     for k in (1, 2):
         for sh in shapes:
             if sh.get("lanes_per_seed", 8) < k:
