@@ -256,7 +256,7 @@ __device__ __forceinline__ void list_insert(float (&lc)[K], unsigned (&lid)[K], 
 {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const bool less = (c < lc[i]) || (c == lc[i] && id < lid[i]);
+        const bool less = (c < lc[i]) | ((c == lc[i]) & (id < lid[i]));   // no short-circuit branches
         const float tc = lc[i];
         const unsigned ti = lid[i];
         lc[i] = less ? c : tc;
@@ -343,36 +343,52 @@ struct WaveSearch {
         wave_lds_sync();
     }
 
-    // evaluate every pair of the listed runs, one per lane and round
+    // Pair slot t0 + lane of a round: its owner and hit (the load is left in
+    // flight).  Runs starting in the round mark their slot; the other slots
+    // continue the last run started before them.
+    __device__ __forceinline__ bool fetch_pair(int t0, int &first, int &o, float4 &hv)
+    {
+        W.mark[lane] = -1;
+        const int r = first + lane;
+        const int start = r < n_runs ? W.run[r].y : 0x7FFFFFFF;
+        const bool starts = start < t0 + kWave;
+        if (starts) W.mark[start - t0] = r;
+        const int prev = first - 1;
+        first += __popcll(__ballot(starts));
+        wave_lds_sync();
+        const int mk = W.mark[lane];
+        const unsigned long long below = __ballot(mk >= 0) & (~0ull >> (63 - lane));
+        const int from = below ? 63 - __clzll((long long)below) : 0;
+        const int mk_from = __shfl(mk, from);
+        const int rr = below ? mk_from : prev;
+        const int pair = t0 + lane;
+        const bool valid = pair < n_pairs;
+        o = 0;
+        if (valid) {
+            const int4 R = W.run[rr];
+            o = R.z;
+            hv = load_global(bh + R.x + (pair - R.y));
+        }
+        return valid;
+    }
+
+    // evaluate every pair of the listed runs, one per lane and round; the hits
+    // of the next round are loaded while this round's are tested
     __device__ __forceinline__ void evaluate()
     {
         wave_lds_sync();
         int first = 0;   // first run not yet started
+        int o = 0;
+        float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
+        bool valid = n_pairs > 0 && fetch_pair(0, first, o, hv);
         for (int t0 = 0; t0 < n_pairs; t0 += kWave) {
-            // the run of each pair slot: runs starting in this round mark their
-            // slot, the others continue the last run started before it
-            W.mark[lane] = -1;
-            const int r = first + lane;
-            const int start = r < n_runs ? W.run[r].y : 0x7FFFFFFF;
-            const bool starts = start < t0 + kWave;
-            if (starts) W.mark[start - t0] = r;
-            const int prev = first - 1;
-            first += __popcll(__ballot(starts));
-            wave_lds_sync();
-            const int mk = W.mark[lane];
-            const unsigned long long below = __ballot(mk >= 0) & (~0ull >> (63 - lane));
-            const int from = below ? 63 - __clzll((long long)below) : 0;
-            const int mk_from = __shfl(mk, from);
-            const int rr = below ? mk_from : prev;
-            const int pair = t0 + lane;
+            int o_next = 0;
+            float4 hv_next = make_float4(1.f, 0.f, 0.f, 0.f);
+            const bool valid_next = t0 + kWave < n_pairs && fetch_pair(t0 + kWave, first, o_next, hv_next);
             bool ok = false;
             float tot = 0.f;
             unsigned hid = 0;
-            int o = 0;
-            if (pair < n_pairs) {
-                const int4 R = W.run[rr];
-                o = R.z;
-                const float4 hv = load_global(bh + R.x + (pair - R.y));
+            if (valid) {
                 const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
                 const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
                 if (kStats) {
@@ -381,7 +397,7 @@ struct WaveSearch {
                 }
                 const float c2 = hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z, P.var_u,
                                           P.var_z);
-                ok = fwd && c2 < P.chi2_cut;
+                ok = fwd & (c2 < P.chi2_cut);
                 tot = a.w + c2;
                 hid = (unsigned)__float_as_int(hv.w);
             }
@@ -394,6 +410,9 @@ struct WaveSearch {
                 W.acc[e] = make_int2(__float_as_int(tot), (int)((hid << 8) | (unsigned)next));
             }
             n_acc += n_new;
+            valid = valid_next;
+            o = o_next;
+            hv = hv_next;
         }
         n_runs = 0;
         n_pairs = 0;
@@ -471,14 +490,19 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     WaveSearch<K, kStats> ws{W, E.binned, P, lane, lc, lid, cnt};
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * (P.bins_phi * P.bins_z + 1);
+    // bin offsets of run q: [off[row + lo], off[row + hi + 1])
+    auto run_bounds = [&](int q, int &b, int &e) {
+        const int sg = n_seg == 2 ? (q & 1) : 0;
+        const int row = (izlo + (n_seg == 2 ? q >> 1 : q)) * P.bins_phi;
+        b = load_global(off + row + (sg ? s1lo : s0lo));
+        e = load_global(off + row + (sg ? s1hi : s0hi) + 1);
+    };
+    int nb = 0, ne = 0;   // next run, loaded one iteration ahead
+    if (n_runs > 0) run_bounds(0, nb, ne);
     for (int q = 0; __ballot(q < n_runs) != 0; ++q) {
-        int beg = 0, len = 0;
-        if (q < n_runs) {
-            const int sg = n_seg == 2 ? (q & 1) : 0;
-            const int row = (izlo + (n_seg == 2 ? q >> 1 : q)) * P.bins_phi;
-            beg = load_global(off + row + (sg ? s1lo : s0lo));
-            len = load_global(off + row + (sg ? s1hi : s0hi) + 1) - beg;
-        }
+        const int beg = nb, len = ne - nb;
+        nb = ne = 0;
+        if (q + 1 < n_runs) run_bounds(q + 1, nb, ne);
         ws.add_run(beg, len);
     }
     ws.evaluate();
@@ -570,25 +594,20 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     // 4. keep the max_cands best entries of the seed: repeated group minimum
     unsigned long long mine = ~0ull;
     for (int r = 0; r < P.max_cands; ++r) {
-        unsigned long long hk = ~0ull;
-        if (S.live) {
-            if (lc[0] < kInf) hk = beam_key(child_hits, lc[0], slot, lid[0]);
-            else if (tail) hk = tail_key;
-        }
+        const bool has_hit = S.live && lc[0] < kInf;
+        const unsigned long long hk =
+            has_hit ? beam_key(child_hits, lc[0], slot, lid[0]) : (tail ? tail_key : ~0ull);
         const unsigned long long m = group_min<G>(hk, gbase, slot);
-        if (hk == m && m != ~0ull) {
-            if (lc[0] < kInf) {
+        const bool won = (hk == m) & (m != ~0ull);
+        const bool pop = won & has_hit;
 #pragma unroll
-                for (int i = 0; i < K - 1; ++i) {
-                    lc[i] = lc[i + 1];
-                    lid[i] = lid[i + 1];
-                }
-                lc[K - 1] = kInf;
-            } else {
-                tail = false;
-            }
+        for (int i = 0; i < K - 1; ++i) {
+            lc[i] = pop ? lc[i + 1] : lc[i];
+            lid[i] = pop ? lid[i + 1] : lid[i];
         }
-        if (slot == r) mine = m;
+        lc[K - 1] = pop ? kInf : lc[K - 1];
+        tail = tail & !(won & !has_hit);
+        mine = slot == r ? m : mine;
     }
     if (lane >= (kWave / G) * G) mine = ~0ull;   // lanes outside every seed group
 
@@ -597,6 +616,10 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const bool alive = mine != ~0ull;
     const int parent = alive ? key_parent(mine) : slot;
     const int src = alive ? gbase + parent : lane;
+    const unsigned hid = key_hit(mine);
+    const bool with_hit = alive && hid != kHoleId;
+    float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
+    if (with_hit) hv = load_global(E.hits + E.layer_off[L] + (int)hid);   // in flight during the shuffles
 #pragma unroll
     for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
 #pragma unroll
@@ -610,14 +633,12 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const int p_status = __shfl(S.status, src);
     S.live = alive;
     if (!alive) return;
-    const unsigned hid = key_hit(mine);
     S.n_hits = key_nhits(mine);
     S.chi2 = key_chi2(mine);
     S.n_holes = p_holes;
     S.stopped = p_stopped;
     S.status = p_status;
-    if (hid != kHoleId) {
-        const float4 hv = load_global(E.hits + E.layer_off[L] + (int)hid);
+    if (with_hit) {
         kf_update(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, P.var_z);
         if (kStats) cnt.upd++;
         H.put(L, lane, (int)hid, parent);
