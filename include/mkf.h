@@ -137,10 +137,11 @@ typedef struct {
 /* Launch shapes.  None of them changes any result. */
 typedef struct {
     int32_t lanes_per_seed;   /* 1, 2, 4, 6 or 8, >= max_cands; 0 = smallest valid */
-    int32_t waves_per_block;  /* 1 .. 4; 0 = 4 */
+    int32_t waves_per_block;  /* 1 .. 4; 0 = 1 */
     int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 1024 */
     int32_t bins_z;           /* hit-index bins in z per layer, 1 .. 1024; 0 = 32 */
-    int32_t persistent;       /* batched build: 1 = persistent waves on a work queue */
+    int32_t persistent;       /* batched build: 1 = persistent waves on a device work queue,
+                                 0 = one wave per work item dispatched by the hardware (default) */
     int32_t blocks_per_cu;    /* persistent grid size per compute unit, 1 .. 32; 0 = 4 */
 } mkf_tuning;
 
@@ -199,10 +200,11 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 #define MKF_BATCH_STATS 0x2u     /* count work (mkf_get_stats); slower */
 #define MKF_BATCH_GRAPH 0x4u     /* run the pipeline as a captured hipGraph, cached per handle list */
 
-/* Batched builder: all listed events in one launch of persistent waves that
- * take (event, seed group) work items from a device queue, with every layer
- * of a candidate kept in registers (Section 2.3: small units of work with
- * dynamic assignment against uneven events; Section 4: seeds of several
+/* Batched builder: all listed events in one launch whose waves each take
+ * (event, seed group) work items - one per wave as the hardware dispatches
+ * them, or in turn from a device queue with persistent waves - with every
+ * layer of a candidate kept in registers (Section 2.3: small units of work
+ * with dynamic assignment against uneven events; Section 4: seeds of several
  * events processed together).  Results equal mkf_build's.  outs: n entries
  * or NULL (results stay on the device; see mkf_fetch_tracks). */
 mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags,

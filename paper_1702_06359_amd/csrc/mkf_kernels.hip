@@ -251,18 +251,18 @@ struct Count {
     unsigned long long prop = 0, chi2 = 0, acc = 0, upd = 0, scan = 0;
 };
 
+// Best-K list of one candidate's hit children, ascending 64-bit keys
+// (accumulated chi2 bits << 32 | hit id; chi2 >= 0 so its bits order as the
+// value, and equal chi2 falls back to the hit id); empty slots hold ~0.
 template <int K>
-__device__ __forceinline__ void list_insert(float (&lc)[K], unsigned (&lid)[K], float c, unsigned id)
+__device__ __forceinline__ void list_insert(unsigned long long (&lk)[K], unsigned long long key)
 {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const bool less = (c < lc[i]) | ((c == lc[i]) & (id < lid[i]));   // no short-circuit branches
-        const float tc = lc[i];
-        const unsigned ti = lid[i];
-        lc[i] = less ? c : tc;
-        lid[i] = less ? id : ti;
-        c = less ? tc : c;
-        id = less ? ti : id;
+        const unsigned long long t = lk[i];
+        const bool less = key < t;
+        lk[i] = less ? key : t;
+        key = less ? t : key;
     }
 }
 
@@ -322,8 +322,7 @@ struct WaveSearch {
     const float4 *bh;
     const Params &P;
     const int lane;
-    float (&lc)[K];
-    unsigned (&lid)[K];
+    unsigned long long (&lk)[K];
     Count &cnt;
     int n_runs = 0, n_pairs = 0, n_acc = 0, n_mine = 0;
 
@@ -334,7 +333,7 @@ struct WaveSearch {
         int e = W.head[lane];
         while (e != kEnd) {
             const int2 v = W.acc[e];
-            list_insert<K>(lc, lid, __int_as_float(v.x), (unsigned)v.y >> 8);
+            list_insert<K>(lk, ((unsigned long long)(unsigned)v.x << 32) | ((unsigned)v.y >> 8));
             ++n_mine;
             e = v.y & kEnd;
         }
@@ -438,7 +437,7 @@ struct WaveSearch {
 template <int K, bool kStats>
 __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], float chi2, bool predicted,
                                             int L, const LayerParam &lp, const Params &P, const DevEvent &E,
-                                            int lane, SearchLds &W, float (&lc)[K], unsigned (&lid)[K], Count &cnt)
+                                            int lane, SearchLds &W, unsigned long long (&lk)[K], Count &cnt)
 {
     int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
     float du = 0.f, dz = 0.f;
@@ -487,7 +486,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
     W.head[lane] = kEnd;
 
-    WaveSearch<K, kStats> ws{W, E.binned, P, lane, lc, lid, cnt};
+    WaveSearch<K, kStats> ws{W, E.binned, P, lane, lk, cnt};
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * (P.bins_phi * P.bins_z + 1);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
@@ -570,14 +569,10 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const float (&pc)[21] = S.c;
 
     // 2. windowed hit search: keep this lane's best K hit children
-    float lc[K];
-    unsigned lid[K];
+    unsigned long long lk[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        lc[i] = kInf;
-        lid[i] = 0xFFFFFFFFu;
-    }
-    const int nacc = search_layer<K, kStats>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lc, lid, cnt);
+    for (int i = 0; i < K; ++i) lk[i] = ~0ull;
+    const int nacc = search_layer<K, kStats>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
     if (kStats) cnt.acc += nacc;
 
     // 3. hole child, or stop on this surface (with the prediction as state)
@@ -594,18 +589,17 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     // 4. keep the max_cands best entries of the seed: repeated group minimum
     unsigned long long mine = ~0ull;
     for (int r = 0; r < P.max_cands; ++r) {
-        const bool has_hit = S.live && lc[0] < kInf;
+        const bool has_hit = S.live && lk[0] != ~0ull;
         const unsigned long long hk =
-            has_hit ? beam_key(child_hits, lc[0], slot, lid[0]) : (tail ? tail_key : ~0ull);
+            has_hit ? beam_key(child_hits, __uint_as_float((unsigned)(lk[0] >> 32)), slot, (unsigned)lk[0])
+                    : (tail ? tail_key : ~0ull);
+        if (__ballot(hk != ~0ull) == 0) break;   // every seed of the wavefront is exhausted
         const unsigned long long m = group_min<G>(hk, gbase, slot);
         const bool won = (hk == m) & (m != ~0ull);
         const bool pop = won & has_hit;
 #pragma unroll
-        for (int i = 0; i < K - 1; ++i) {
-            lc[i] = pop ? lc[i + 1] : lc[i];
-            lid[i] = pop ? lid[i + 1] : lid[i];
-        }
-        lc[K - 1] = pop ? kInf : lc[K - 1];
+        for (int i = 0; i < K - 1; ++i) lk[i] = pop ? lk[i + 1] : lk[i];
+        lk[K - 1] = pop ? ~0ull : lk[K - 1];
         tail = tail & !(won & !has_hit);
         mine = slot == r ? m : mine;
     }

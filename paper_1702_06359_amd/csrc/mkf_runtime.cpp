@@ -237,7 +237,7 @@ mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
     if (G != 1 && G != 2 && G != 4 && G != 6 && G != 8)
         return fail(MKF_E_INVALID, "lanes_per_seed must be 1, 2, 4, 6 or 8");
     if (G < c.max_cands) return fail(MKF_E_INVALID, "lanes_per_seed must be >= max_cands");
-    if (t->waves_per_block == 0) t->waves_per_block = 4;
+    if (t->waves_per_block == 0) t->waves_per_block = 1;
     if (t->waves_per_block < 1 || t->waves_per_block > 4) return fail(MKF_E_INVALID, "waves_per_block must be 1..4");
     if (t->bins_phi == 0) t->bins_phi = 1024;
     if (t->bins_z == 0) t->bins_z = 32;
@@ -680,7 +680,6 @@ mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *h
         ctx->own_stream = true;
     }
     std::memset(&ctx->tuning, 0, sizeof(ctx->tuning));
-    ctx->tuning.persistent = 1;
     if ((st = check_tuning(ctx->cfg, &ctx->tuning)) != MKF_OK) return st;
     derive_params(ctx.get());
     for (auto &t : ctx->timers) {
@@ -1151,7 +1150,7 @@ mkf_status mkf_autotune(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tun
     for (int G : {1, 2, 4, 6, 8})
         if (G >= ctx->cfg.max_cands) lanes.push_back(G);
     const std::vector<int> waves = {1, 2, 4};
-    const std::vector<int> bphi = {64, 128, 256, 512, 1024};
+    const std::vector<int> bphi = {128, 256, 512, 1024, 2048};
     const std::vector<int> bz = {4, 8, 16, 32, 64};
     const std::vector<int> pers = {0, 1};
     const std::vector<int> bpc = {2, 4, 8, 16};

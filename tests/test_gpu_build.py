@@ -101,7 +101,7 @@ def test_full_size_events_sampled_seeds(ctx6):
     evs = synth.ckf_events(2, 20000, 0.10)
     hs = [ctx6.load_event(e) for e in evs]
     try:
-        print("case ckf full size 2x20000 batched persistent", flush=True)
+        print("case ckf full size 2x20000 batched", flush=True)
         outs = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
     finally:
         for h in hs:
@@ -122,8 +122,9 @@ def test_launch_shapes_do_not_change_results(gpu_required):
     not, plain or batched: bit-identical tracks."""
     ev = synth.make_event(1200, cfg=212, event=0, noise=0.3)
     ref = None
-    shapes = [dict(), dict(bins_phi=64, bins_z=4), dict(bins_phi=1024, bins_z=64), dict(waves_per_block=1),
-              dict(persistent=0), dict(lanes_per_seed=2), dict(lanes_per_seed=6), dict(lanes_per_seed=8, waves_per_block=2)]
+    shapes = [dict(), dict(bins_phi=64, bins_z=4), dict(bins_phi=1024, bins_z=64), dict(waves_per_block=4),
+              dict(persistent=1), dict(persistent=1, blocks_per_cu=1, waves_per_block=3), dict(lanes_per_seed=2),
+              dict(lanes_per_seed=6), dict(lanes_per_seed=8, waves_per_block=2)]
     for k in (1, 2):
         for sh in shapes:
             if sh.get("lanes_per_seed", 8) < k:
