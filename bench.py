@@ -43,6 +43,25 @@ BYTES_PER_HIT = 16                # binned hit read once
 BYTES_PER_BIN = 4                 # bin offset read once
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1702_06359_amd/csrc/mkf_kernels.hip", "paper_1702_06359_amd/csrc/mkf_device.hpp",
+                  "paper_1702_06359_amd/csrc/mkf_internal.hpp")
+
+
+def measured_traffic(kernel):
+    """Calibrated bytes per launch of `kernel` (read + written) from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/traffic.json,
+    or None when the kernel sources changed since those runs."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return int(round(rec["kernels"][kernel]["bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -165,7 +184,8 @@ def workload_ckf(args):
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
-                "traffic": None, "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
+                "traffic": measured_traffic("k_build_batch<6,false>") if tuning["lanes_per_seed"] == 6 else None,
+                "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
                 "flop_per_launch": int(flops), "counters": st}
     plain_rate = None
     if not args.quick:
@@ -239,8 +259,8 @@ def workload_fit(args):
         "config": {"workload": "KF fit with known hits, 1,000,000 tracks, batches of 2,000-30,000, 10 layers",
                    "batches": 64},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
-                     "kernel": "k_fit", "kernel_avg_ms": round(avg_ms, 4), "flop_per_launch": int(flops),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
+                     "traffic": measured_traffic("k_fit"), "kernel": "k_fit", "kernel_avg_ms": round(avg_ms, 4), "flop_per_launch": int(flops),
                      "hbm_algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 5)},
     }
     if not args.no_cpu_baseline:
