@@ -95,6 +95,31 @@ def test_combinatorial_parity_high_occupancy(ctx6):
     assert_build_parity(rep)
 
 
+def test_crowded_layers(ctx6):
+    """3,000 tracks with fifteen noise hits per true hit (48k hits per layer):
+    about three accepted children per candidate and layer, more than a
+    wavefront's LDS child list holds, so it is merged into the candidates'
+    best-K lists while the search is still running.  200 sampled seeds
+    against the oracle; batched and plain builders identical."""
+    ev = synth.make_event(3000, cfg=218, event=0, noise=15.0)
+    print("case ckf n=3000 k=6 noise=15 (crowded layers)", flush=True)
+    h = ctx6.load_event(ev)
+    try:
+        g = ctx6.build_batch([h], [ev.n_seeds], flags=abi.BATCH_STATS)[0]
+        st = ctx6.get_stats(h)
+        plain = ctx6.build(h, ev.n_seeds)
+    finally:
+        ctx6.unload_event(h)
+    _equal(g, plain)
+    rows = np.sort(np.random.default_rng(11).choice(ev.n_seeds, 200, replace=False)).astype(np.int32)
+    cfg, o = _oracle(ev, 6, rows=rows, threads=16)
+    rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov, rows=rows)
+    per_wave_layer = 60.0 * st["accepted"] / st["cand_layers"]
+    report("ckf_3000_noise1500", dict(rep, accepted_per_wave_layer=per_wave_layer))
+    assert_build_parity(rep, max_tie_frac=0.05)
+    assert per_wave_layer > 150
+
+
 def test_full_size_events_sampled_seeds(ctx6):
     """Two 20,000-track events (10 % noise) in the batched launch the
     benchmark times; 150 sampled seeds per event checked against the oracle."""
