@@ -159,9 +159,12 @@ def workload_ckf(args):
     tuning = ctx.get_tuning().as_dict()
 
     def step():
-        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX)
+        # queued without waiting: the steps run back to back on the device
+        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC)
 
-    sync = torch.cuda.synchronize
+    def sync():
+        ctx.sync()
+        torch.cuda.synchronize()
     log("warmup + timed steps")
     for _ in range(args.warmup):
         step()
@@ -201,9 +204,9 @@ def workload_ckf(args):
         "config": {"workload": "combinatorial KF building, 10 events x 20,000 tracks, 10% noise hits, "
                                "k=6 candidates/seed, chi2<30, 1 hole, 10-layer barrel, 3.8 T",
                    "events": n_events, "tracks_per_event": n_tracks, "noise": noise, "max_cands": k,
-                   "step": "hit index + batched build of all events", "tuning": tuning},
+                   "step": "hit index + batched build of all events, steps queued back to back", "tuning": tuning},
         "roofline": roofline,
-        "index_kernels_avg_ms": round(index_ms / max(index_n, 1), 4),
+        "index_build_ms_per_step": round(index_ms / max(index_n, 1), 4),
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:

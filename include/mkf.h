@@ -199,6 +199,9 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 #define MKF_BATCH_REINDEX 0x1u   /* rebuild every event's hit index first (same stream) */
 #define MKF_BATCH_STATS 0x2u     /* count work (mkf_get_stats); slower */
 #define MKF_BATCH_GRAPH 0x4u     /* run the pipeline as a captured hipGraph, cached per handle list */
+#define MKF_BATCH_ASYNC 0x8u     /* return once the work is queued on the context stream (outs must be
+                                    NULL); results, counters and timers are final after mkf_sync or
+                                    any call that waits for the stream (fetch, stats, timers) */
 
 /* Batched builder: all listed events in one launch whose waves each take
  * (event, seed group) work items - one per wave as the hardware dispatches
@@ -230,12 +233,17 @@ mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double 
 mkf_status mkf_fit_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tracks *outs);
 
 /* Device time of the library's kernels, from HIP events recorded on the
- * context stream around each launch of non-graph calls.  which: 0 = build
- * (batched build kernel, or the plain per-layer kernels), 1 = hit index,
- * 2 = fit.  Returns the summed milliseconds and launch count since the last
- * reset. */
+ * context stream around each launch of non-graph calls (waits for the
+ * stream first).  which: 0 = build
+ * (batched build kernel, or the plain per-layer kernels), 1 = hit index
+ * (one count per index build of a batch), 2 = fit.  Returns the summed
+ * milliseconds and launch count since the last reset. */
 mkf_status mkf_timer_read(mkf_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
 mkf_status mkf_timer_reset(mkf_ctx *ctx);
+
+/* Wait until all work queued on the context stream (asynchronous batches
+ * included) has finished.  Errors: MKF_E_INVALID (NULL), MKF_E_DEVICE. */
+mkf_status mkf_sync(mkf_ctx *ctx);
 
 /* Autotune: time the batched build of the given events over a grid of
  * launch shapes, keep the fastest (applied to ctx and written to *best).

@@ -24,7 +24,7 @@ MAX_CANDS = 8
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_AGAIN, E_NOTFOUND, E_STATE = 0, -1, -2, -3, -4, -5, -6
 HOLE_ALWAYS = 0x1
-BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH = 0x1, 0x2, 0x4
+BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC = 0x1, 0x2, 0x4, 0x8
 TIMER_BUILD, TIMER_INDEX, TIMER_FIT = 0, 1, 2
 
 _STATUS_NAMES = {0: "MKF_OK", -1: "MKF_E_INVALID", -2: "MKF_E_NOMEM", -3: "MKF_E_DEVICE",
@@ -112,6 +112,7 @@ _PROTOS = {
     "mkf_fit_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, _P(Tracks)]),
     "mkf_timer_read": (C.c_int, [_ctx_p, C.c_int32, _P(C.c_double), _P(C.c_int64)]),
     "mkf_timer_reset": (C.c_int, [_ctx_p]),
+    "mkf_sync": (C.c_int, [_ctx_p]),
     "mkf_autotune": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, _P(Tuning)]),
     "mkf_serve_config": (C.c_int, [_ctx_p, C.c_uint64, C.c_int32, C.c_int32]),
     "mkf_serve_submit": (C.c_int, [_ctx_p, _P(Event), _P(Tracks), _P(C.c_uint64)]),
@@ -390,6 +391,10 @@ class Context:
 
     def timer_reset(self):
         check(lib().mkf_timer_reset(self.h))
+
+    def sync(self):
+        """Wait for all work queued on the context stream (asynchronous batches)."""
+        check(lib().mkf_sync(self.h))
 
     # -- serving
     def serve_config(self, hbm_budget_bytes: int, max_in_flight: int, max_batch_events: int = 0):

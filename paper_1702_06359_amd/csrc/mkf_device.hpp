@@ -28,12 +28,50 @@ __device__ __forceinline__ float wrap_pi(float a)
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Reads through a pointer known to address global memory (emits global
-// rather than flat loads for pointers that were themselves loaded from memory).
+// Reads and writes through a pointer known to address global memory (global
+// rather than flat instructions for pointers that were themselves loaded from
+// memory; flat ones also count against the LDS wait counter).
 __device__ __forceinline__ int load_global(const int *p)
 {
     typedef const __attribute__((address_space(1))) int *gptr;
     return *(gptr)p;
+}
+
+__device__ __forceinline__ float load_global(const float *p)
+{
+    typedef const __attribute__((address_space(1))) float *gptr;
+    return *(gptr)p;
+}
+
+__device__ __forceinline__ void store_global(float *p, float v)
+{
+    typedef __attribute__((address_space(1))) float *gptr;
+    *(gptr)p = v;
+}
+
+__device__ __forceinline__ double load_global(const double *p)
+{
+    typedef const __attribute__((address_space(1))) double *gptr;
+    return *(gptr)p;
+}
+
+__device__ __forceinline__ void store_global(double *p, double v)
+{
+    typedef __attribute__((address_space(1))) double *gptr;
+    *(gptr)p = v;
+}
+
+__device__ __forceinline__ void store_global(int *p, int v)
+{
+    typedef __attribute__((address_space(1))) int *gptr;
+    *(gptr)p = v;
+}
+
+__device__ __forceinline__ void store_global(float4 *p, float4 v)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) v4 *gptr;
+    *(gptr)p = v4{v.x, v.y, v.z, v.w};
 }
 
 __device__ __forceinline__ float4 load_global(const float4 *p)

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "mkf_device.hpp"
 
@@ -98,6 +99,155 @@ __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_sta
 // eta is a function of z, so the grid is (z, phi): bin = iz * bins_phi + iphi.
 // A counting sort over all events of a batch at once.
 
+// A caller-order hit as (cos phi, sin phi, z, 0) and its (z row, phi) bin.
+__device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const double *xyz, float4 *out)
+{
+    const double x = xyz[0], y = xyz[1];
+    const double ir = 1.0 / sqrt(x * x + y * y);
+    const float c = (float)(x * ir), s = (float)(y * ir);
+    const float z = (float)xyz[2];
+    const float phi = atan2f(s, c);
+    int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
+    int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
+    ip = min(max(ip, 0), P.bins_phi - 1);
+    iz = min(max(iz, 0), P.bins_z - 1);
+    *out = make_float4(c, s, z, 0.f);
+    return iz * P.bins_phi + ip;
+}
+
+// Conversion and binning of every hit of a batch, no atomics: grid
+// (chunks, event x layer).  Precedes k_index_lds.
+__global__ void __launch_bounds__(256) k_index_bin(const Params P, const BatchArgs B)
+{
+    const int e = blockIdx.y / P.n_layers;
+    const int L = blockIdx.y - e * P.n_layers;
+    const DevEvent &E = B.events[e];
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
+    const LayerParam lp = P.layer[L];
+    for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
+        float4 v;
+        store_global(E.bin_of + h, bin_hit(P, lp, E.raw_xyz + 3 * (size_t)h, &v));
+        store_global(E.hits + h, v);
+    }
+}
+
+// Ranks and bin offsets of a layer whose bin counters fit in LDS (between
+// k_index_bin and k_index_scatter): one 1024-thread block per (event, layer)
+// ranks its hits in their bins with LDS atomics and scans the counts in LDS,
+// so there is no device-wide atomic and no count array to clear.  kShort
+// packs two 16-bit counters per word (layers of at most 65,535 hits).
+template <bool kShort>
+__global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchArgs B)
+{
+    extern __shared__ unsigned s_cnt[];
+    __shared__ int s_wave[16];
+    const int e = blockIdx.x / P.n_layers;
+    const int L = blockIdx.x - e * P.n_layers;
+    const DevEvent &E = B.events[e];
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
+    const int nb = P.bins_phi * P.bins_z;
+    const int nw = kShort ? (nb + 1) / 2 : nb;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    // four hits per thread and step, their loads issued together
+    constexpr int kU = 4;
+    const int stride = blockDim.x;
+    for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
+        int bins[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bins[u] = load_global(E.bin_of + min(h + u * stride, h1 - 1));
+        int rank[kU];   // all atomics of the step in flight before their results are stored
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int bin = bins[u];
+            const bool in = h + u * stride < h1;
+            if (kShort) {
+                const int sh = (bin & 1) * 16;
+                rank[u] = in ? (int)((atomicAdd(&s_cnt[bin >> 1], 1u << sh) >> sh) & 0xFFFFu) : 0;
+            } else {
+                rank[u] = in ? (int)atomicAdd(&s_cnt[bin], 1u) : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (h + u * stride < h1) store_global(E.bin_rank + h + u * stride, rank[u]);
+    }
+    __syncthreads();
+    // exclusive scan of the counts into offsets relative to the layer, kept
+    // in LDS (same packing) and written out absolute; each thread owns 32
+    // consecutive bins (one step for up to 32,768 bins)
+    constexpr int kPer = 32;
+    constexpr int kWords = kShort ? kPer / 2 : kPer;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    int *off = E.bin_off + L * (nb + 1);
+    int carry = 0;
+    for (int base = 0; base < nb; base += blockDim.x * kPer) {
+        const int b0 = base + threadIdx.x * kPer;   // a multiple of 32: its words are 16-byte aligned
+        const int w0 = kShort ? b0 / 2 : b0;
+        unsigned w[kWords];
+        if (w0 + kWords <= nw) {
+#pragma unroll
+            for (int j = 0; j < kWords; j += 4) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(s_cnt + w0 + j);
+                w[j] = q.x; w[j + 1] = q.y; w[j + 2] = q.z; w[j + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWords; ++j) w[j] = w0 + j < nw ? s_cnt[w0 + j] : 0u;
+        }
+        int v[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            v[j] = b0 + j >= nb ? 0 : kShort ? (int)((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) : (int)w[j];
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) sum += v[j];
+        int x = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(x, o);
+            if (lane >= o) x += t;
+        }
+        if (lane == kWave - 1) s_wave[wave] = x;
+        __syncthreads();
+        if (wave == 0) {
+            int t2 = lane < n_waves ? s_wave[lane] : 0;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const int t = __shfl_up(t2, o);
+                if (lane >= o) t2 += t;
+            }
+            if (lane < n_waves) s_wave[lane] = t2;
+        }
+        __syncthreads();
+        int run = carry + (wave > 0 ? s_wave[wave - 1] : 0) + x - sum;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int r = run;
+            run += v[j];
+            if (kShort) {
+                if (j & 1) w[j >> 1] |= (unsigned)r << 16;
+                else w[j >> 1] = (unsigned)r;
+            } else {
+                w[j] = (unsigned)r;
+            }
+            if (b0 + j < nb) store_global(off + b0 + j, h0 + r);
+        }
+        if (w0 + kWords <= nw) {
+#pragma unroll
+            for (int j = 0; j < kWords; j += 4)
+                *reinterpret_cast<uint4 *>(s_cnt + w0 + j) = make_uint4(w[j], w[j + 1], w[j + 2], w[j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWords; ++j)
+                if (w0 + j < nw) s_cnt[w0 + j] = w[j];
+        }
+        carry += s_wave[n_waves - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nb] = h1;
+}
+
 // Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it and
 // take its position in the bin.  Grid (chunks, event x layer).
 __global__ void __launch_bounds__(256) k_index_prep(const Params P, const BatchArgs B)
@@ -109,17 +259,9 @@ __global__ void __launch_bounds__(256) k_index_prep(const Params P, const BatchA
     const LayerParam lp = P.layer[L];
     int *cnt = E.bin_count + L * P.bins_phi * P.bins_z;
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
-        const double x = E.raw_xyz[3 * (size_t)h], y = E.raw_xyz[3 * (size_t)h + 1];
-        const double ir = 1.0 / sqrt(x * x + y * y);
-        const float c = (float)(x * ir), s = (float)(y * ir);
-        const float z = (float)E.raw_xyz[3 * (size_t)h + 2];
-        const float phi = atan2f(s, c);
-        int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
-        int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
-        ip = min(max(ip, 0), P.bins_phi - 1);
-        iz = min(max(iz, 0), P.bins_z - 1);
-        const int bin = iz * P.bins_phi + ip;
-        E.hits[h] = make_float4(c, s, z, 0.f);
+        float4 v;
+        const int bin = bin_hit(P, lp, E.raw_xyz + 3 * (size_t)h, &v);
+        E.hits[h] = v;
         E.bin_of[h] = bin;
         E.bin_rank[h] = atomicAdd(&cnt[bin], 1);
     }
@@ -213,11 +355,9 @@ __global__ void __launch_bounds__(256) k_index_scatter(const Params P, const Bat
     const int nb = P.bins_phi * P.bins_z;
     const int *off = E.bin_off + L * (nb + 1);
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
-        const int bin = E.bin_of[h];
-        const int pos = off[bin] + E.bin_rank[h];
-        float4 v = E.hits[h];
-        v.w = __int_as_float(h - h0);
-        E.binned[pos] = v;
+        const int pos = load_global(off + load_global(E.bin_of + h)) + load_global(E.bin_rank + h);
+        const float4 v = load_global(E.hits + h);
+        store_global(E.binned + pos, make_float4(v.x, v.y, v.z, __int_as_float(h - h0)));
     }
 }
 
@@ -524,10 +664,10 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
     for (int i = 0; i < 21; ++i) S.c[i] = 0.f;
     if (!first_slot) return;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.p[i] = (float)E.seed_par[6 * (size_t)seed + i];
+    for (int i = 0; i < 6; ++i) S.p[i] = (float)load_global(E.seed_par + 6 * (size_t)seed + i);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) S.c[i] = (float)E.seed_cov[21 * (size_t)seed + i];
-    for (int L = 0; L < P.n_seed_layers; ++L) S.n_hits += E.seed_hits[(size_t)seed * P.n_seed_layers + L] >= 0;
+    for (int i = 0; i < 21; ++i) S.c[i] = (float)load_global(E.seed_cov + 21 * (size_t)seed + i);
+    for (int L = 0; L < P.n_seed_layers; ++L) S.n_hits += load_global(E.seed_hits + (size_t)seed * P.n_seed_layers + L) >= 0;
     S.tg = trig_of(S.p);
 }
 
@@ -652,18 +792,18 @@ __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, co
     if (lane != gbase || seed >= E.n_seeds) return;
     const size_t s = (size_t)seed;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) E.out_par[6 * s + i] = (double)S.p[i];
+    for (int i = 0; i < 6; ++i) store_global(E.out_par + 6 * s + i, (double)S.p[i]);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) E.out_cov[21 * s + i] = (double)S.c[i];
-    E.out_chi2[s] = (double)S.chi2;
-    E.out_nhits[s] = S.n_hits;
-    E.out_nholes[s] = S.n_holes;
-    E.out_status[s] = S.status;
+    for (int i = 0; i < 21; ++i) store_global(E.out_cov + 21 * s + i, (double)S.c[i]);
+    store_global(E.out_chi2 + s, (double)S.chi2);
+    store_global(E.out_nhits + s, S.n_hits);
+    store_global(E.out_nholes + s, S.n_holes);
+    store_global(E.out_status + s, S.status);
     int *oh = E.out_hits + s * P.n_layers;
-    for (int L = 0; L < P.n_seed_layers; ++L) oh[L] = E.seed_hits[s * P.n_seed_layers + L];
+    for (int L = 0; L < P.n_seed_layers; ++L) store_global(oh + L, load_global(E.seed_hits + s * P.n_seed_layers + L));
     int cur = 0;
     for (int L = P.n_layers - 1; L >= P.n_seed_layers; --L) {
-        oh[L] = H.hit[L * H.stride + gbase + cur];
+        store_global(oh + L, H.hit[L * H.stride + gbase + cur]);
         cur = H.par[L * H.stride + gbase + cur];
     }
 }
@@ -748,19 +888,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     if (L == P.n_seed_layers) {
         init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
     } else {
-        const int meta = E.st_meta[slot];
+        const int meta = load_global(E.st_meta + slot);
         S.live = meta & 1;
         S.stopped = (meta >> 1) & 1;
         S.status = (meta >> 2) & 3;
         S.n_hits = (meta >> 4) & 31;
         S.n_holes = (meta >> 9) & 15;
-        S.chi2 = E.st_chi2[slot];
+        S.chi2 = load_global(E.st_chi2 + slot);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) S.p[i] = S.live ? E.st_par[i * ns + slot] : 0.f;
+        for (int i = 0; i < 6; ++i) S.p[i] = S.live ? load_global(E.st_par + i * ns + slot) : 0.f;
 #pragma unroll
-        for (int i = 0; i < 21; ++i) S.c[i] = S.live ? E.st_cov[i * ns + slot] : 0.f;
-        S.tg = S.live ? Trig{E.st_trig[0 * ns + slot], E.st_trig[1 * ns + slot], E.st_trig[2 * ns + slot],
-                             E.st_trig[3 * ns + slot]}
+        for (int i = 0; i < 21; ++i) S.c[i] = S.live ? load_global(E.st_cov + i * ns + slot) : 0.f;
+        S.tg = S.live ? Trig{load_global(E.st_trig + 0 * ns + slot), load_global(E.st_trig + 1 * ns + slot),
+                             load_global(E.st_trig + 2 * ns + slot), load_global(E.st_trig + 3 * ns + slot)}
                       : Trig{0.f, 1.f, 1.f, 0.f};
     }
     extern __shared__ int s_dyn[];
@@ -770,17 +910,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     if (L == P.n_layers - 1) {
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
     } else {
-        E.st_meta[slot] = S.live | (S.stopped << 1) | (S.status << 2) | (S.n_hits << 4) | (S.n_holes << 9);
-        E.st_chi2[slot] = S.chi2;
+        store_global(E.st_meta + slot, S.live | (S.stopped << 1) | (S.status << 2) | (S.n_hits << 4) | (S.n_holes << 9));
+        store_global(E.st_chi2 + slot, S.chi2);
         if (S.live) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) E.st_par[i * ns + slot] = S.p[i];
+            for (int i = 0; i < 6; ++i) store_global(E.st_par + i * ns + slot, S.p[i]);
 #pragma unroll
-            for (int i = 0; i < 21; ++i) E.st_cov[i * ns + slot] = S.c[i];
-            E.st_trig[0 * ns + slot] = S.tg.sph;
-            E.st_trig[1 * ns + slot] = S.tg.cph;
-            E.st_trig[2 * ns + slot] = S.tg.sth;
-            E.st_trig[3 * ns + slot] = S.tg.cth;
+            for (int i = 0; i < 21; ++i) store_global(E.st_cov + i * ns + slot, S.c[i]);
+            store_global(E.st_trig + 0 * ns + slot, S.tg.sph);
+            store_global(E.st_trig + 1 * ns + slot, S.tg.cph);
+            store_global(E.st_trig + 2 * ns + slot, S.tg.sth);
+            store_global(E.st_trig + 3 * ns + slot, S.tg.cth);
         }
     }
     flush_counts<kStats>(cnt, E, lane);
@@ -797,9 +937,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const size_t t = (size_t)(g - B.track_prefix[e]);
     float p[6], c[21], op[6], oc[21];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) op[i] = p[i] = (float)E.track_par[6 * t + i];
+    for (int i = 0; i < 6; ++i) op[i] = p[i] = (float)load_global(E.track_par + 6 * t + i);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) oc[i] = c[i] = (float)E.track_cov[21 * t + i];
+    for (int i = 0; i < 21; ++i) oc[i] = c[i] = (float)load_global(E.track_cov + 21 * t + i);
     float chi2 = 0.f;
     int nupd = 0, status = 0;
     Trig tg = trig_of(p);
@@ -817,7 +957,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
-        const int h = E.track_hits[t * P.n_layers + L];
+        const int h = load_global(E.track_hits + t * P.n_layers + L);
         if (h >= 0) {
             const float4 hv = load_global(E.hits + E.layer_off[L] + h);
             // Joseph form: a fit starts from a wide prior, where the plain
@@ -831,12 +971,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         }
     }
 #pragma unroll
-    for (int i = 0; i < 6; ++i) E.fit_par[6 * t + i] = (double)op[i];
+    for (int i = 0; i < 6; ++i) store_global(E.fit_par + 6 * t + i, (double)op[i]);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) E.fit_cov[21 * t + i] = (double)oc[i];
-    E.fit_chi2[t] = (double)chi2;
-    E.fit_nupd[t] = nupd;
-    E.fit_status[t] = status;
+    for (int i = 0; i < 21; ++i) store_global(E.fit_cov + 21 * t + i, (double)oc[i]);
+    store_global(E.fit_chi2 + t, (double)chi2);
+    store_global(E.fit_nupd + t, nupd);
+    store_global(E.fit_status + t, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -869,13 +1009,60 @@ hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bo
     return hipGetLastError();
 }
 
+// LDS one block may use on the current device (queried once per device;
+// lowered to the 64 KB default if a larger launch is refused).
+static std::atomic<int> g_lds_limit[64];
+
+static size_t lds_per_block()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536 - 1024;
+    int v = g_lds_limit[dev & 63].load();
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        g_lds_limit[dev & 63].store(v);
+    }
+    return (size_t)v - 1024;   // room for the kernel's static LDS
+}
+
+static void lds_refused()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) g_lds_limit[dev & 63].store(65536);
+}
+
 hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_hits <= 0) return hipSuccess;
+    const size_t nb = (size_t)p.bins_phi * p.bins_z;
+    const size_t lds = lds_per_block();
+    const unsigned blocks = (unsigned)(b.n_events * p.n_layers);
+    const bool fits = nb * 4 <= lds || ((nb + 1) / 2 * 4 <= lds && b.max_layer_hits <= 0xFFFF);
     // chunks per (event, layer): about one hit per thread for the largest
-    // layer (more independent atomics in flight), striding beyond that
-    const unsigned chunks = std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256)));
-    const dim3 grid(chunks, (unsigned)(b.n_events * p.n_layers));
+    // layer, striding beyond that
+    const dim3 grid(std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256))), blocks);
+    if (fits) {
+        k_index_bin<<<grid, 256, 0, s>>>(p, b);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    bool ranked = false;
+    if (nb * 4 <= lds) {
+        k_index_lds<false><<<blocks, 1024, nb * 4, s>>>(p, b);
+        ranked = hipGetLastError() == hipSuccess;
+        if (!ranked) lds_refused();   // not launched: try a smaller form
+    }
+    if (!ranked && (nb + 1) / 2 * 4 <= lds_per_block() && b.max_layer_hits <= 0xFFFF) {
+        k_index_lds<true><<<blocks, 1024, (nb + 1) / 2 * 4, s>>>(p, b);
+        ranked = hipGetLastError() == hipSuccess;
+        if (!ranked) lds_refused();
+    }
+    if (ranked) {
+        k_index_scatter<<<grid, 256, 0, s>>>(p, b);
+        return hipGetLastError();
+    }
+    // bins beyond one block's LDS: device-wide counting atomics
     k_index_prep<<<grid, 256, 0, s>>>(p, b);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;

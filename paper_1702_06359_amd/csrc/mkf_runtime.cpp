@@ -250,32 +250,45 @@ mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
     return MKF_OK;
 }
 
+void timers_collect(mkf_ctx *ctx, bool wait);
+
 void timer_begin(mkf_ctx *ctx, int which, hipStream_t s)
 {
     Timer &t = ctx->timers[which];
-    if (s != ctx->stream || t.pending) return;
-    (void)hipEventRecord(t.start, s);
+    if (s != ctx->stream) return;
+    if (t.count == Timer::kRing) timers_collect(ctx, true);
+    (void)hipEventRecord(t.start[(t.head + t.count) % Timer::kRing], s);
+    t.open = true;
 }
 
 void timer_end(mkf_ctx *ctx, int which, hipStream_t s, long long launches)
 {
     Timer &t = ctx->timers[which];
-    if (s != ctx->stream || t.pending) return;
-    (void)hipEventRecord(t.stop, s);
-    t.pending = true;
-    t.pending_launches = launches;
+    if (s != ctx->stream || !t.open) return;
+    const int slot = (t.head + t.count) % Timer::kRing;
+    (void)hipEventRecord(t.stop[slot], s);
+    t.ring_launches[slot] = launches;
+    ++t.count;
+    t.open = false;
 }
 
-void timers_collect(mkf_ctx *ctx)
+// Adds the recorded intervals to the totals: all of them (waiting for the
+// device) or only those already complete.
+void timers_collect(mkf_ctx *ctx, bool wait)
 {
     for (auto &t : ctx->timers) {
-        if (!t.pending) continue;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
-            t.total_ms += ms;
-            t.launches += t.pending_launches;
+        while (t.count > 0) {
+            const int slot = t.head;
+            if (wait) (void)hipEventSynchronize(t.stop[slot]);
+            else if (hipEventQuery(t.stop[slot]) != hipSuccess) break;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t.start[slot], t.stop[slot]) == hipSuccess) {
+                t.total_ms += ms;
+                t.launches += t.ring_launches[slot];
+            }
+            t.head = (t.head + 1) % Timer::kRing;
+            --t.count;
         }
-        t.pending = false;
     }
 }
 
@@ -291,6 +304,7 @@ void drop_graphs_with(mkf_ctx *ctx, int32_t handle)
     for (size_t i = 0; i < g.size();) {
         const bool hit = handle < 0 || std::find(g[i]->handles.begin(), g[i]->handles.end(), handle) != g[i]->handles.end();
         if (hit) {
+            (void)hipStreamSynchronize(ctx->stream);   // a queued replay may still use its scratch
             (void)hipGraphExecDestroy(g[i]->exec);
             ctx->heap.release(g[i]->scratch);
             g.erase(g.begin() + i);
@@ -316,6 +330,11 @@ mkf_status upload_view(EventRec *rec, hipStream_t s)
 mkf_status ensure_batch_scratch(mkf_ctx *ctx, int n)
 {
     const size_t need = batch_scratch_bytes(n);
+    if (ctx->batch_dev_bytes < need || ctx->batch_host_bytes < need) {
+        MKF_HIP(hipStreamSynchronize(ctx->stream));   // queued work may still read the buffers
+        ctx->stage_pending = false;
+        ctx->staged_image.clear();
+    }
     if (ctx->batch_dev_bytes < need) {
         ctx->heap.release(ctx->batch_dev);
         ctx->batch_dev = ctx->heap.alloc(need);
@@ -503,6 +522,7 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t 
     const int bp = ctx->tuning.bins_phi, bz = ctx->tuning.bins_z;
     *rebuilt = false;
     if (rec->index && rec->index_bins_phi == bp && rec->index_bins_z == bz) return MKF_OK;
+    if (rec->index) MKF_HIP(hipStreamSynchronize(ctx->stream));   // queued builds may still read it
     rec->heap->release(rec->index);
     const size_t bytes = event_index_bytes(rec->shape, bp * bz);
     rec->index = rec->heap->alloc(bytes);
@@ -523,9 +543,7 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t 
 mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
                        BatchArgs *args, hipStream_t s)
 {
-    (void)ctx;
     const int n = (int)recs.size();
-    char *h = static_cast<char *>(host);
     size_t off = 0;
     auto place = [&](size_t bytes) {
         const size_t o = off;
@@ -537,6 +555,8 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     const size_t o_hit = place((size_t)(n + 1) * sizeof(int));
     const size_t o_trk = place((size_t)(n + 1) * sizeof(int));
     const size_t o_q = place(sizeof(unsigned));
+    std::vector<char> image(off, 0);
+    char *h = image.data();
     DevEvent *ev = reinterpret_cast<DevEvent *>(h + o_ev);
     int *ip = reinterpret_cast<int *>(h + o_item);
     int *hp = reinterpret_cast<int *>(h + o_hit);
@@ -559,7 +579,23 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     hp[n] = (int)hits;
     tp[n] = (int)trks;
     *reinterpret_cast<unsigned *>(h + o_q) = 0;
-    MKF_HIP(hipMemcpyAsync(dev, host, off, hipMemcpyHostToDevice, s));
+    // The context's own buffer keeps the last image: an identical batch (same
+    // events, views and tuning) is not copied again.  Its pinned staging
+    // buffer is rewritten only once the previous copy out of it has run.
+    const bool own = dev == ctx->batch_dev;
+    if (!own || image != ctx->staged_image) {
+        if (host == ctx->batch_host && ctx->stage_pending) {
+            MKF_HIP(hipEventSynchronize(ctx->stage_done));
+            ctx->stage_pending = false;
+        }
+        std::memcpy(host, image.data(), off);
+        MKF_HIP(hipMemcpyAsync(dev, host, off, hipMemcpyHostToDevice, s));
+        if (host == ctx->batch_host) {
+            MKF_HIP(hipEventRecord(ctx->stage_done, s));
+            ctx->stage_pending = true;
+        }
+        if (own) ctx->staged_image.swap(image);
+    }
     char *d = static_cast<char *>(dev);
     args->events = reinterpret_cast<const DevEvent *>(d + o_ev);
     args->item_prefix = reinterpret_cast<const int *>(d + o_item);
@@ -589,7 +625,7 @@ mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<E
     if (reindex) {
         if (timed) timer_begin(ctx, 1, s);
         MKF_HIP(launch_index(P, args, s));
-        if (timed) timer_end(ctx, 1, s, 3);
+        if (timed) timer_end(ctx, 1, s, 1);   // one index build of the batch
     }
     const mkf_tuning &t = ctx->tuning;
     if (t.persistent) MKF_HIP(launch_fill_i32(reinterpret_cast<int *>(args.queue), 0, 1, s));
@@ -682,10 +718,12 @@ mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *h
     std::memset(&ctx->tuning, 0, sizeof(ctx->tuning));
     if ((st = check_tuning(ctx->cfg, &ctx->tuning)) != MKF_OK) return st;
     derive_params(ctx.get());
-    for (auto &t : ctx->timers) {
-        MKF_HIP(hipEventCreate(&t.start));
-        MKF_HIP(hipEventCreate(&t.stop));
-    }
+    for (auto &t : ctx->timers)
+        for (int i = 0; i < Timer::kRing; ++i) {
+            MKF_HIP(hipEventCreate(&t.start[i]));
+            MKF_HIP(hipEventCreate(&t.stop[i]));
+        }
+    MKF_HIP(hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming));
     *out = ctx.release();
     return MKF_OK;
 }
@@ -700,10 +738,12 @@ void mkf_destroy(mkf_ctx *ctx)
     ctx->events.clear();
     ctx->heap.release(ctx->batch_dev);
     if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
-    for (auto &t : ctx->timers) {
-        (void)hipEventDestroy(t.start);
-        (void)hipEventDestroy(t.stop);
-    }
+    for (auto &t : ctx->timers)
+        for (int i = 0; i < Timer::kRing; ++i) {
+            if (t.start[i]) (void)hipEventDestroy(t.start[i]);
+            if (t.stop[i]) (void)hipEventDestroy(t.stop[i]);
+        }
+    if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -814,6 +854,7 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
         MKF_HIP(launch_index(ctx->params, args, ctx->stream));
     }
     if (rec->plain_G != G || !rec->plain) {
+        if (rec->plain) MKF_HIP(hipStreamSynchronize(ctx->stream));
         drop_plain_graph(rec);
         rec->heap->release(rec->plain);
         const int slots = plain_slots(rec->shape.n_seeds, G);
@@ -854,7 +895,7 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
     }
     if (out && (st = copy_tracks_out(ctx, rec, out, ctx->stream)) != MKF_OK) return st;
     MKF_HIP(hipStreamSynchronize(ctx->stream));
-    timers_collect(ctx);
+    timers_collect(ctx, true);
     finish_ndof(out);
     return MKF_OK;
 }
@@ -862,7 +903,11 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
 mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags, mkf_tracks *outs)
 {
     if (!ctx) return fail(MKF_E_INVALID, "NULL context");
-    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH)) return fail(MKF_E_INVALID, "unknown flags");
+    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH | MKF_BATCH_ASYNC))
+        return fail(MKF_E_INVALID, "unknown flags");
+    const bool async = flags & MKF_BATCH_ASYNC;
+    flags &= ~MKF_BATCH_ASYNC;
+    if (async && outs) return fail(MKF_E_INVALID, "an asynchronous batch returns no host outputs (outs must be NULL)");
     std::vector<EventRec *> recs;
     mkf_status st = gather_events(ctx, handles, n, &recs);
     if (st != MKF_OK) return st;
@@ -928,11 +973,15 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
         if ((st = stage_batch(ctx, recs, ctx->batch_dev, ctx->batch_host, spi, &args, ctx->stream)) != MKF_OK) return st;
         if ((st = run_pipeline(ctx, args, recs, flags, true, ctx->stream)) != MKF_OK) return st;
     }
+    if (async) {
+        timers_collect(ctx, false);
+        return MKF_OK;
+    }
     if (outs)
         for (int i = 0; i < n; ++i)
             if ((st = copy_tracks_out(ctx, recs[i], &outs[i], ctx->stream)) != MKF_OK) return st;
     MKF_HIP(hipStreamSynchronize(ctx->stream));
-    timers_collect(ctx);
+    timers_collect(ctx, true);
     if (outs)
         for (int i = 0; i < n; ++i) finish_ndof(&outs[i]);
     return MKF_OK;
@@ -1013,7 +1062,7 @@ mkf_status mkf_fit_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tr
         for (int i = 0; i < n; ++i)
             if ((st = copy_fit_out(recs[i], recs[i]->view, &outs[i], ctx->stream)) != MKF_OK) return st;
     MKF_HIP(hipStreamSynchronize(ctx->stream));
-    timers_collect(ctx);
+    timers_collect(ctx, true);
     if (outs)
         for (int i = 0; i < n; ++i) finish_fit_out(&outs[i], recs[i]->shape.n_layers);
     return MKF_OK;
@@ -1095,7 +1144,7 @@ mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double 
     if (out && (st = copy_fit_out(&tmp, v, out, s)) != MKF_OK) return cleanup(st);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return cleanup(fail(MKF_E_DEVICE, "fit: %s", hipGetErrorString(e)));
-    timers_collect(ctx);
+    timers_collect(ctx, true);
     finish_fit_out(out, ts.n_layers);
     return cleanup(MKF_OK);
 }
@@ -1103,6 +1152,8 @@ mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double 
 mkf_status mkf_timer_read(mkf_ctx *ctx, int32_t which, double *total_ms, int64_t *launches)
 {
     if (!ctx || which < 0 || which > 2) return fail(MKF_E_INVALID, "bad timer");
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx, true);
     if (total_ms) *total_ms = ctx->timers[which].total_ms;
     if (launches) *launches = ctx->timers[which].launches;
     return MKF_OK;
@@ -1111,10 +1162,20 @@ mkf_status mkf_timer_read(mkf_ctx *ctx, int32_t which, double *total_ms, int64_t
 mkf_status mkf_timer_reset(mkf_ctx *ctx)
 {
     if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx, true);
     for (auto &t : ctx->timers) {
         t.total_ms = 0;
         t.launches = 0;
     }
+    return MKF_OK;
+}
+
+mkf_status mkf_sync(mkf_ctx *ctx)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx, true);
     return MKF_OK;
 }
 

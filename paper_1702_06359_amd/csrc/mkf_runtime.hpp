@@ -91,12 +91,17 @@ struct BatchGraph {
     hipGraphExec_t exec = nullptr;
 };
 
+// Device time of the timed phases: a ring of event pairs, so that calls
+// that return before the device finishes (asynchronous batches) each keep
+// their own interval until it is collected.
 struct Timer {
-    hipEvent_t start = nullptr, stop = nullptr;
+    static constexpr int kRing = 32;
+    hipEvent_t start[kRing] = {}, stop[kRing] = {};
+    long long ring_launches[kRing] = {};
+    int head = 0, count = 0;   // recorded intervals not yet collected
+    bool open = false;         // between timer_begin and timer_end
     double total_ms = 0.0;
     long long launches = 0;
-    bool pending = false;
-    long long pending_launches = 0;
 };
 
 struct Server;   // serving state (mkf_serve.cpp)
@@ -130,6 +135,9 @@ struct mkf_ctx {
     size_t batch_dev_bytes = 0;
     void *batch_host = nullptr;
     size_t batch_host_bytes = 0;
+    hipEvent_t stage_done = nullptr;    // last copy out of batch_host
+    bool stage_pending = false;
+    std::vector<char> staged_image;     // what batch_dev holds (empty: unknown)
     std::vector<std::unique_ptr<mkf::BatchGraph>> graphs;
     mkf::Timer timers[3];
     std::unique_ptr<mkf::Server, mkf::ServerDeleter> server;

@@ -192,6 +192,32 @@ def test_repeat_and_batch_composition_are_deterministic(ctx6):
         _equal(a, d)
 
 
+def test_async_batches_equal_synchronous_ones(ctx6):
+    """Batches queued without waiting (the staging copy skipped when the
+    batch repeats) give the tracks of a waited-for batch; every queued launch
+    is timed."""
+    evs = [synth.make_event(n, cfg=219, event=i, noise=0.2) for i, n in enumerate((1500, 700))]
+    hs = [ctx6.load_event(e) for e in evs]
+    try:
+        print("case async batches 2 events x 5", flush=True)
+        ref = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
+        ctx6.timer_reset()
+        for _ in range(5):
+            assert ctx6.build_batch(hs, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC) is None
+        ctx6.sync()
+        ms, n = ctx6.timer_read(abi.TIMER_BUILD)
+        got = [ctx6.fetch_tracks(h, e.n_seeds) for h, e in zip(hs, evs)]
+        with pytest.raises(abi.MkfError) as e:
+            ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_ASYNC)
+        assert e.value.status == abi.E_INVALID
+    finally:
+        for h in hs:
+            ctx6.unload_event(h)
+    assert n == 5 and ms > 0
+    for a, b in zip(ref, got):
+        _equal(a, b)
+
+
 def test_work_counters_match_oracle(ctx6):
     ev = synth.make_event(800, cfg=214, event=0, noise=0.2)
     h = ctx6.load_event(ev)
