@@ -190,6 +190,16 @@ def workload_ckf(args):
                 "traffic": measured_traffic("k_build_batch<6,false>") if tuning["lanes_per_seed"] == 6 else None,
                 "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
                 "flop_per_launch": int(flops), "counters": st}
+    # the same steps with the final fit of every built track chained on the device
+    def step_fit():
+        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC | abi.BATCH_FIT)
+
+    step_fit()
+    sync()
+    ctx.timer_reset()
+    fit_steps = max(1, args.steps // 2)
+    fit_elapsed = time_steps(step_fit, fit_steps, 0, sync)
+    refit_ms, refit_n = ctx.timer_read(abi.TIMER_FIT)
     plain_rate = None
     if not args.quick:
         # the plain per-event builder (one launch per layer) on the same events
@@ -207,6 +217,9 @@ def workload_ckf(args):
                    "step": "hit index + batched build of all events, steps queued back to back", "tuning": tuning},
         "roofline": roofline,
         "index_build_ms_per_step": round(index_ms / max(index_n, 1), 4),
+        "build_and_fit": {"tracks_per_s": round(tracks * fit_steps / fit_elapsed, 1),
+                          "ms_per_step": round(fit_elapsed / fit_steps * 1e3, 4),
+                          "final_fit_kernel_ms": round(refit_ms / max(refit_n, 1), 4)},
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:

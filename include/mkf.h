@@ -202,6 +202,7 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 #define MKF_BATCH_ASYNC 0x8u     /* return once the work is queued on the context stream (outs must be
                                     NULL); results, counters and timers are final after mkf_sync or
                                     any call that waits for the stream (fetch, stats, timers) */
+#define MKF_BATCH_FIT 0x10u      /* then fit every built track on the device (mkf_fetch_fit) */
 
 /* Batched builder: all listed events in one launch whose waves each take
  * (event, seed group) work items - one per wave as the hardware dispatches
@@ -215,6 +216,19 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
 
 /* Copy the last build results of an event to the host. */
 mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
+
+/* Final fit of the built tracks of an event, from the last mkf_build_batch
+ * with MKF_BATCH_FIT (Section 2: once a track is complete, a last KF pass
+ * over its hits).  Prior: the helix through the track's hits on layers 0, 1
+ * and 2 (circle through the transverse points, z linear in the arc length)
+ * at the first hit, covariance diag(1 cm, 10 cm, 1/GeV, 0.1, 0.1)^2 in the
+ * frame (u, z, q/pT, phi, theta) of the layer tangent there; then the KF fit
+ * over the built hit list as mkf_fit.  out (n = the event's seeds): par/cov
+ * after the last update, hits and n_holes of the build, n_hits = updates,
+ * chi2, ndof = 2 n_hits - 5, status 0 / 2 (propagation failure) / 3 (no
+ * hit on one of layers 0-2, or collinear points: no prior, nothing fitted).
+ * Waits for the stream.  Errors: MKF_E_INVALID, MKF_E_NOTFOUND, MKF_E_DEVICE. */
+mkf_status mkf_fetch_fit(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 
 /* Work counters of the last build of an event. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out);

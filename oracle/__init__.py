@@ -92,6 +92,8 @@ def lib():
         L.orc_build.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip, ip,
                                 C.c_int32, C.POINTER(OrcTrack), C.c_int32]
         L.orc_replay.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), dp, dp, ip, dp, ip]
+        L.orc_circle_prior.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, ip, dp, dp, dp, ip]
+        L.orc_circle_prior.restype = None
         L.orc_replay.restype = C.c_double
         _lib = L
     return _lib
@@ -203,6 +205,25 @@ def fit(cfg: OrcConfig, hits, init_par, init_cov, track_hits, n_threads=1, want_
     if hc is not None:
         res["hit_chi2"] = hc
     return res
+
+
+FIT_PRIOR_SIGMA = (1.0, 10.0, 1.0, 0.1, 0.1)   # (u cm, z cm, q/pT 1/GeV, phi, theta)
+
+
+def circle_prior(cfg: OrcConfig, hits, track_hits, sig=FIT_PRIOR_SIGMA):
+    """Prior of the final fit of built tracks: helix through the hits on
+    layers 0-2, at the first hit, loose diagonal local covariance.  Returns
+    (par, cov, ok)."""
+    hs = hits if isinstance(hits, HitSet) else HitSet(hits)
+    th = np.ascontiguousarray(track_hits, dtype=np.int32)
+    n = th.shape[0]
+    th = th.reshape(n, cfg.n_layers)
+    par = np.zeros((n, 6))
+    cov = np.zeros((n, 21))
+    ok = np.zeros(n, dtype=np.int32)
+    sg = np.ascontiguousarray(sig, dtype=np.float64)
+    lib().orc_circle_prior(C.byref(cfg), C.byref(hs.s), n, _ip(th), _dp(sg), _dp(par), _dp(cov), _ip(ok))
+    return par, cov, ok.astype(bool)
 
 
 def build_tracks(cfg: OrcConfig, hits, seed_par, seed_cov, seed_hits, seed_ids=None, n_threads=1):

@@ -421,6 +421,66 @@ void orc_fit(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks, cons
     parallel_for(n_tracks, n_threads, 64, fit_one, &c);
 }
 
+/* ------------------------------------------------------------ fit prior */
+
+void orc_circle_prior(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
+                      const int32_t *track_hits, const double sig[5], double *out_par, double *out_cov,
+                      int32_t *out_ok)
+{
+    const int nl = cfg->n_layers;
+    for (int32_t i = 0; i < n_tracks; ++i) {
+        double *par = out_par + 6 * (int64_t)i, *cov = out_cov + 21 * (int64_t)i;
+        memset(par, 0, 6 * sizeof(double));
+        memset(cov, 0, 21 * sizeof(double));
+        out_ok[i] = 0;
+        const double *p[3];
+        int missing = 0;
+        for (int L = 0; L < 3; ++L) {
+            const int32_t h = track_hits[(int64_t)i * nl + L];
+            if (h < 0) missing = 1;
+            else p[L] = hits->xyz[L] + 3 * (int64_t)h;
+        }
+        if (missing) continue;
+        /* transverse circle through the three points: signed curvature from
+         * the triangle (twice its signed area over the product of its sides) */
+        const double ax = p[1][0] - p[0][0], ay = p[1][1] - p[0][1];
+        const double bx = p[2][0] - p[1][0], by = p[2][1] - p[1][1];
+        const double cx = p[2][0] - p[0][0], cy = p[2][1] - p[0][1];
+        const double area2 = ax * cy - ay * cx;
+        const double la = hypot(ax, ay), lb = hypot(bx, by), lc = hypot(cx, cy);
+        if (!(la > 0 && lb > 0 && lc > 0) || area2 == 0.0) continue;
+        const double w = 2.0 * area2 / (la * lb * lc);        /* > 0: counter-clockwise */
+        /* the chord to the second point turns by half the arc's angle from
+         * the tangent at the first point */
+        const double phi = wrap_angle(atan2(ay, ax) - asin(fmax(-1.0, fmin(1.0, 0.5 * w * la))));
+        /* arc length from the first to the third point, z linear in it */
+        const double t = 0.5 * w * lc;
+        const double arc = fabs(t) < 1e-12 ? lc : 2.0 * asin(fmax(-1.0, fmin(1.0, t))) / w;
+        const double cot = (p[2][2] - p[0][2]) / arc;
+        par[0] = p[0][0];
+        par[1] = p[0][1];
+        par[2] = p[0][2];
+        par[3] = -w / (KAPPA * cfg->bz);
+        par[4] = phi;
+        par[5] = 0.5 * PI - atan(cot);
+        /* covariance: local diagonal rotated to (x, y) by the hit's azimuth */
+        const double a = atan2(p[0][1], p[0][0]);
+        const double s = sin(a), c = cos(a);
+        double C[36];
+        memset(C, 0, sizeof(C));
+        const double vu = sig[0] * sig[0];
+        C[0] = s * s * vu;
+        C[1] = C[6] = -s * c * vu;
+        C[7] = c * c * vu;
+        C[14] = sig[1] * sig[1];
+        C[21] = sig[2] * sig[2];
+        C[28] = sig[3] * sig[3];
+        C[35] = sig[4] * sig[4];
+        pack21(C, cov);
+        out_ok[i] = 1;
+    }
+}
+
 /* ------------------------------------------------------------ building */
 
 typedef struct {

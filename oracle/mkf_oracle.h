@@ -96,6 +96,17 @@ void orc_fit(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
              double *out_par, double *out_cov, double *out_chi2, int32_t *out_ndof,
              int32_t *out_status, double *hit_chi2, int32_t n_threads);
 
+/* Prior for the final fit of a built track (Section 2: a fit over the hits of
+ * a complete track), from its hits on layers 0, 1 and 2: the helix through
+ * them - the circle through the three transverse points, z linear in the arc
+ * length - evaluated at the first hit, with the covariance
+ * diag(sig[0..4])^2 in the frame (u, z, q/pT, phi, theta), u along the layer
+ * tangent at the hit's azimuth.  out_ok[i] = 0 when a hit is missing or the
+ * three points are collinear (then out_par/out_cov are zero). */
+void orc_circle_prior(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
+                      const int32_t *track_hits, const double sig[5], double *out_par, double *out_cov,
+                      int32_t *out_ok);
+
 /* Combinatorial KF building of the listed seeds (all if seed_ids == NULL).
  * Output row i belongs to seed_ids[i]. */
 void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total,

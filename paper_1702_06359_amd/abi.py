@@ -24,7 +24,7 @@ MAX_CANDS = 8
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_AGAIN, E_NOTFOUND, E_STATE = 0, -1, -2, -3, -4, -5, -6
 HOLE_ALWAYS = 0x1
-BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC = 0x1, 0x2, 0x4, 0x8
+BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC, BATCH_FIT = 0x1, 0x2, 0x4, 0x8, 0x10
 TIMER_BUILD, TIMER_INDEX, TIMER_FIT = 0, 1, 2
 
 _STATUS_NAMES = {0: "MKF_OK", -1: "MKF_E_INVALID", -2: "MKF_E_NOMEM", -3: "MKF_E_DEVICE",
@@ -106,6 +106,7 @@ _PROTOS = {
     "mkf_build": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_build_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
     "mkf_fetch_tracks": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
+    "mkf_fetch_fit": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_get_stats": (C.c_int, [_ctx_p, C.c_int32, _P(BuildStats)]),
     "mkf_fit": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_double), _P(C.c_double), _P(C.c_int32),
                           _P(Tracks)]),
@@ -355,6 +356,12 @@ class Context:
     def fetch_tracks(self, handle: int, n_seeds: int):
         out = TrackArrays(n_seeds, self.n_layers)
         check(lib().mkf_fetch_tracks(self.h, int(handle), C.byref(out.tracks)))
+        return out.as_dict()
+
+    def fetch_fit(self, handle: int, n_seeds: int):
+        """Final fit of the built tracks (after build_batch with BATCH_FIT)."""
+        out = TrackArrays(n_seeds, self.n_layers)
+        check(lib().mkf_fetch_fit(self.h, int(handle), C.byref(out.tracks)))
         return out.as_dict()
 
     def get_stats(self, handle: int) -> Dict[str, int]:

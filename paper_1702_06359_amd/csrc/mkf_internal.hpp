@@ -79,6 +79,11 @@ struct DevEvent {
     double *fit_chi2;
     int *fit_nupd;
     int *fit_status;
+    double *rf_par;                      // [n_seeds][6] final fit of the built tracks
+    double *rf_cov;                      // [n_seeds][21]
+    double *rf_chi2;                     // [n_seeds]
+    int *rf_nupd;                        // [n_seeds]
+    int *rf_status;                      // [n_seeds]
     unsigned long long *stats;           // [5] mkf_build_stats counters
     // plain per-layer builder state (slots = n_seeds * lanes_per_seed)
     float *st_par;                       // [6][slots]
@@ -98,11 +103,13 @@ struct BatchArgs {
     const int *item_prefix;      // [n_events + 1] work items (seed groups) before each event
     const int *hit_prefix;       // [n_events + 1] hits before each event
     const int *track_prefix;     // [n_events + 1] tracks before each event
+    const int *seed_prefix;      // [n_events + 1] seeds before each event
     unsigned int *queue;         // work-queue counter (persistent kernels)
     int n_events;
     int total_items;
     int total_hits;
     int total_tracks;
+    int total_seeds;
     int seeds_per_item;
     int max_layer_hits;          // largest layer of any event (index launch shape)
 };
@@ -116,6 +123,7 @@ hipError_t launch_build_batch(const Params &p, const BatchArgs &b, int lanes_per
 hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const DevEvent &ev_host, int layer,
                               int lanes_per_seed, int waves_per_block, bool stats, hipStream_t s);
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s);
+hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 }  // namespace mkf

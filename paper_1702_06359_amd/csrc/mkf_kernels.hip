@@ -927,21 +927,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // ---------------------------------------------------------------------------
-// Fit with known hits: one lane per track, no branching beyond skipped layers.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
+// KF fit over a fixed hit list: from the prior (p, c) on layer 0, for each
+// layer the scattering of the previous one, propagation, transport, and the
+// update with that layer's hit if it has one (hit_of(L) >= 0).  (op, oc) is
+// the state after the last update.
+template <class HitOf>
+__device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, float (&p)[6], float (&c)[21],
+                                          HitOf hit_of, float (&op)[6], float (&oc)[21], float &chi2, int &nupd,
+                                          int &status)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= B.total_tracks) return;
-    const int e = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
-    const DevEvent &E = B.events[e];
-    const size_t t = (size_t)(g - B.track_prefix[e]);
-    float p[6], c[21], op[6], oc[21];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) op[i] = p[i] = (float)load_global(E.track_par + 6 * t + i);
+    for (int i = 0; i < 6; ++i) op[i] = p[i];
 #pragma unroll
-    for (int i = 0; i < 21; ++i) oc[i] = c[i] = (float)load_global(E.track_cov + 21 * t + i);
-    float chi2 = 0.f;
-    int nupd = 0, status = 0;
+    for (int i = 0; i < 21; ++i) oc[i] = c[i];
+    chi2 = 0.f;
+    nupd = 0;
+    status = 0;
     Trig tg = trig_of(p);
     for (int L = 0; L < P.n_layers; ++L) {
         if (L > 0) {
@@ -957,7 +958,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
-        const int h = load_global(E.track_hits + t * P.n_layers + L);
+        const int h = hit_of(L);
         if (h >= 0) {
             const float4 hv = load_global(E.hits + E.layer_off[L] + h);
             // Joseph form: a fit starts from a wide prior, where the plain
@@ -970,6 +971,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             for (int i = 0; i < 21; ++i) oc[i] = c[i];
         }
     }
+}
+
+// Fit with known hits: one lane per track, no branching beyond skipped layers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B.total_tracks) return;
+    const int e = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
+    const DevEvent &E = B.events[e];
+    const size_t t = (size_t)(g - B.track_prefix[e]);
+    float p[6], c[21], op[6], oc[21], chi2;
+    int nupd, status;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = (float)load_global(E.track_par + 6 * t + i);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = (float)load_global(E.track_cov + 21 * t + i);
+    fit_track(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc, chi2,
+              nupd, status);
 #pragma unroll
     for (int i = 0; i < 6; ++i) store_global(E.fit_par + 6 * t + i, (double)op[i]);
 #pragma unroll
@@ -977,6 +996,89 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     store_global(E.fit_chi2 + t, (double)chi2);
     store_global(E.fit_nupd + t, nupd);
     store_global(E.fit_status + t, status);
+}
+
+// Prior of the final fit of a built track: the helix through its hits on
+// layers 0, 1 and 2 (the transverse circle through the three points; z
+// linear in the arc length), at the first hit, with a loose diagonal
+// covariance in the frame (u, z, q/pT, phi, theta) of the layer tangent at
+// that hit: sigma = (1 cm, 10 cm, 1 / GeV, 0.1, 0.1).  Computed in double
+// from the caller's coordinates; false without three usable points.
+__device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params &P, const int *hits, float (&p)[6],
+                                                float (&c)[21])
+{
+    double q[3][3];
+    for (int L = 0; L < 3; ++L) {
+        const int h = hits[L];
+        if (h < 0) return false;
+        const double *x = E.raw_xyz + 3 * (size_t)(E.layer_off[L] + h);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[L][j] = load_global(x + j);
+    }
+    const double d1x = q[1][0] - q[0][0], d1y = q[1][1] - q[0][1];   // first to second
+    const double d3x = q[2][0] - q[0][0], d3y = q[2][1] - q[0][1];   // first to third
+    const double l1 = sqrt(d1x * d1x + d1y * d1y), l3 = sqrt(d3x * d3x + d3y * d3y);
+    const double ex = q[2][0] - q[1][0], ey = q[2][1] - q[1][1];
+    const double l2 = sqrt(ex * ex + ey * ey);
+    const double twice_area = d1x * d3y - d1y * d3x;
+    if (!(l1 > 0.0 && l2 > 0.0 && l3 > 0.0) || twice_area == 0.0) return false;
+    const double curv = 2.0 * twice_area / (l1 * l2 * l3);           // > 0 turning counter-clockwise
+    // tangent at the first point: the chord to the second point, turned back
+    // by half the angle the arc between them sweeps
+    const double half = asin(fmin(1.0, fmax(-1.0, 0.5 * curv * l1)));
+    double phi = atan2(d1y, d1x) - half;
+    constexpr double kPiD = 3.14159265358979323846;
+    phi = phi > kPiD ? phi - 2.0 * kPiD : (phi <= -kPiD ? phi + 2.0 * kPiD : phi);
+    const double u3 = 0.5 * curv * l3;
+    const double arc3 = fabs(u3) < 1e-12 ? l3 : 2.0 * asin(fmin(1.0, fmax(-1.0, u3))) / curv;
+    const double theta = 0.5 * kPiD - atan((q[2][2] - q[0][2]) / arc3);
+    p[0] = (float)q[0][0];
+    p[1] = (float)q[0][1];
+    p[2] = (float)q[0][2];
+    p[3] = (float)(curv / (double)P.w_per_qpt);
+    p[4] = (float)phi;
+    p[5] = (float)theta;
+    const double a = atan2(q[0][1], q[0][0]);
+    const double sa = sin(a), ca = cos(a);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = 0.f;
+    c[sym(0, 0)] = (float)(sa * sa);
+    c[sym(0, 1)] = (float)(-sa * ca);
+    c[sym(1, 1)] = (float)(ca * ca);
+    c[sym(2, 2)] = 100.f;
+    c[sym(3, 3)] = 1.f;
+    c[sym(4, 4)] = 0.01f;
+    c[sym(5, 5)] = 0.01f;
+    return true;
+}
+
+// Final fit of every built track of a batch (after the build): one lane per
+// seed, hits from the build's output.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_refit(const Params P, const BatchArgs B)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B.total_seeds) return;
+    const int e = upper_bound_i32(B.seed_prefix, B.n_events + 1, g) - 1;
+    const DevEvent &E = B.events[e];
+    const size_t t = (size_t)(g - B.seed_prefix[e]);
+    const int *hits = E.out_hits + t * P.n_layers;
+    float p[6], c[21], op[6], oc[21], chi2 = 0.f;
+    int nupd = 0, status = 3;
+    if (final_fit_prior(E, P, hits, p, c))
+        fit_track(P, E, p, c, [&](int L) { return load_global(hits + L); }, op, oc, chi2, nupd, status);
+    else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) op[i] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 21; ++i) oc[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) store_global(E.rf_par + 6 * t + i, (double)op[i]);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) store_global(E.rf_cov + 21 * t + i, (double)oc[i]);
+    store_global(E.rf_chi2 + t, (double)chi2);
+    store_global(E.rf_nupd + t, nupd);
+    store_global(E.rf_status + t, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,6 +1230,13 @@ hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const Dev
     default: return hipErrorInvalidValue;
     }
 #undef MKF_LAYER_CASE
+}
+
+hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s)
+{
+    if (b.total_seeds <= 0) return hipSuccess;
+    k_refit<<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)

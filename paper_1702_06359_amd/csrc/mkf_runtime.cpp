@@ -129,6 +129,11 @@ size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_v
     v->fit_chi2 = c.take<double>(nt);
     v->fit_nupd = c.take<int>(nt);
     v->fit_status = c.take<int>(nt);
+    v->rf_par = c.take<double>(6 * ns);
+    v->rf_cov = c.take<double>(21 * ns);
+    v->rf_chi2 = c.take<double>(ns);
+    v->rf_nupd = c.take<int>(ns);
+    v->rf_status = c.take<int>(ns);
     v->stats = c.take<unsigned long long>(5);
     DevEvent *dv = c.take<DevEvent>(1);
     if (dev_view) *dev_view = dv;
@@ -386,7 +391,7 @@ size_t event_index_bytes(const EventShape &s, int nb)
 size_t batch_scratch_bytes(int n)
 {
     size_t b = ((size_t)n * sizeof(DevEvent) + 255) & ~size_t(255);
-    b += 3 * (((size_t)(n + 1) * sizeof(int) + 255) & ~size_t(255));
+    b += 4 * (((size_t)(n + 1) * sizeof(int) + 255) & ~size_t(255));
     return b + 256;
 }
 
@@ -554,6 +559,7 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     const size_t o_item = place((size_t)(n + 1) * sizeof(int));
     const size_t o_hit = place((size_t)(n + 1) * sizeof(int));
     const size_t o_trk = place((size_t)(n + 1) * sizeof(int));
+    const size_t o_seed = place((size_t)(n + 1) * sizeof(int));
     const size_t o_q = place(sizeof(unsigned));
     std::vector<char> image(off, 0);
     char *h = image.data();
@@ -561,7 +567,8 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     int *ip = reinterpret_cast<int *>(h + o_item);
     int *hp = reinterpret_cast<int *>(h + o_hit);
     int *tp = reinterpret_cast<int *>(h + o_trk);
-    long long items = 0, hits = 0, trks = 0;
+    int *sp = reinterpret_cast<int *>(h + o_seed);
+    long long items = 0, hits = 0, trks = 0, seeds = 0;
     int max_layer = 0;
     for (int i = 0; i < n; ++i) {
         const EventShape &sh = recs[i]->shape;
@@ -570,14 +577,18 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
         ip[i] = (int)items;
         hp[i] = (int)hits;
         tp[i] = (int)trks;
+        sp[i] = (int)seeds;
+        seeds += recs[i]->shape.n_seeds;
         items += (recs[i]->shape.n_seeds + spi - 1) / spi;
         hits += recs[i]->shape.n_hits();
         trks += recs[i]->shape.n_tracks;
     }
-    if (items > INT32_MAX || hits > INT32_MAX || trks > INT32_MAX) return fail(MKF_E_INVALID, "batch too large");
+    if (items > INT32_MAX || hits > INT32_MAX || trks > INT32_MAX || seeds > INT32_MAX)
+        return fail(MKF_E_INVALID, "batch too large");
     ip[n] = (int)items;
     hp[n] = (int)hits;
     tp[n] = (int)trks;
+    sp[n] = (int)seeds;
     *reinterpret_cast<unsigned *>(h + o_q) = 0;
     // The context's own buffer keeps the last image: an identical batch (same
     // events, views and tuning) is not copied again.  Its pinned staging
@@ -601,11 +612,13 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     args->item_prefix = reinterpret_cast<const int *>(d + o_item);
     args->hit_prefix = reinterpret_cast<const int *>(d + o_hit);
     args->track_prefix = reinterpret_cast<const int *>(d + o_trk);
+    args->seed_prefix = reinterpret_cast<const int *>(d + o_seed);
     args->queue = reinterpret_cast<unsigned *>(d + o_q);
     args->n_events = n;
     args->total_items = (int)items;
     args->total_hits = (int)hits;
     args->total_tracks = (int)trks;
+    args->total_seeds = (int)seeds;
     args->seeds_per_item = spi;
     args->max_layer_hits = max_layer;
     return MKF_OK;
@@ -633,6 +646,11 @@ mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<E
     MKF_HIP(launch_build_batch(P, args, t.lanes_per_seed, t.waves_per_block, t.persistent,
                                ctx->n_cu * t.blocks_per_cu, stats, s));
     if (timed) timer_end(ctx, 0, s, 1);
+    if (flags & MKF_BATCH_FIT) {
+        if (timed) timer_begin(ctx, 2, s);
+        MKF_HIP(launch_refit(P, args, s));
+        if (timed) timer_end(ctx, 2, s, 1);
+    }
     return MKF_OK;
 }
 
@@ -903,7 +921,7 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
 mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags, mkf_tracks *outs)
 {
     if (!ctx) return fail(MKF_E_INVALID, "NULL context");
-    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH | MKF_BATCH_ASYNC))
+    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH | MKF_BATCH_ASYNC | MKF_BATCH_FIT))
         return fail(MKF_E_INVALID, "unknown flags");
     const bool async = flags & MKF_BATCH_ASYNC;
     flags &= ~MKF_BATCH_ASYNC;
@@ -995,6 +1013,29 @@ mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
     mkf_status st = check_tracks(out, rec->shape.n_seeds, "fetch");
     if (st != MKF_OK) return st;
     if ((st = copy_tracks_out(ctx, rec, out, ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    finish_ndof(out);
+    return MKF_OK;
+}
+
+mkf_status mkf_fetch_fit(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
+{
+    if (!ctx || !out) return fail(MKF_E_INVALID, "NULL argument");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    mkf_status st = check_tracks(out, rec->shape.n_seeds, "fetch_fit");
+    if (st != MKF_OK) return st;
+    const DevEvent &v = rec->view;
+    const size_t n = (size_t)rec->shape.n_seeds, nl = (size_t)rec->shape.n_layers;
+    hipStream_t s = ctx->stream;
+    if ((st = copy_d2h(out->par, v.rf_par, 48 * n, s)) != MKF_OK || (st = copy_d2h(out->cov, v.rf_cov, 168 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->hits, v.out_hits, 4 * nl * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->n_hits, v.rf_nupd, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->n_holes, v.out_nholes, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->chi2, v.rf_chi2, 8 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->status, v.rf_status, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->ndof, v.rf_nupd, 4 * n, s)) != MKF_OK)
+        return st;
     MKF_HIP(hipStreamSynchronize(ctx->stream));
     finish_ndof(out);
     return MKF_OK;

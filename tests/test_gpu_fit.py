@@ -131,3 +131,32 @@ def test_fit_rejects_bad_input(ctx):
         assert empty["par"].shape == (0, 6)
     finally:
         ctx.unload_event(h)
+
+
+def test_build_then_fit_on_device(gpu_required):
+    """Built tracks fitted on the device without leaving it (build_batch with
+    BATCH_FIT), against the oracle's fit of the same hit lists from the
+    oracle's own prior; a track without its layer-1 hit gets no prior."""
+    c = abi.Context(abi.config_from_geometry(synth.Geometry(), max_cands=6))
+    ev = synth.make_event(2500, cfg=205, event=0, noise=0.1)
+    sh = ev.seed_hits.copy()
+    sh[7, 1] = -1
+    h = c.load_event(abi.EventArrays(ev.hits, ev.seed_par, ev.seed_cov, sh))
+    try:
+        print("case build+fit n=2500", flush=True)
+        built = c.build_batch([h], [ev.n_seeds], flags=abi.BATCH_REINDEX | abi.BATCH_FIT)[0]
+        g = c.fetch_fit(h, ev.n_seeds)
+        again = c.fetch_tracks(h, ev.n_seeds)
+    finally:
+        c.unload_event(h)
+        c.close()
+    assert np.array_equal(built["hits"], again["hits"]) and np.array_equal(g["hits"], built["hits"])
+    cfg = oracle.config(ev.geometry)
+    par, cov, ok = oracle.circle_prior(cfg, ev.hits, built["hits"])
+    assert not ok[7] and g["status"][7] == 3
+    o = oracle.fit(cfg, ev.hits, par, cov, built["hits"], n_threads=8)
+    o["status"] = np.where(ok, o["status"], 3)
+    keep = ok
+    assert (g["n_hits"][keep] == (built["hits"][keep] >= 0).sum(1)).all()
+    sub = lambda d: {k: v[keep] for k, v in d.items() if isinstance(v, np.ndarray) and v.shape[:1] == keep.shape}
+    _check("build_then_fit", sub(g), sub(o), prior_cov=cov[keep])

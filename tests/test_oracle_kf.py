@@ -250,3 +250,45 @@ def test_gluckstern_resolution_at_10_gev():
     own = np.median(np.sqrt(synth.unpack_sym(res["cov"])[:, 3, 3]) / np.abs(qt))
     assert emp == pytest.approx(g["sigma_pt_over_pt"], rel=0.15)
     assert own == pytest.approx(g["sigma_pt_over_pt"], rel=0.15)
+
+
+def test_circle_prior_recovers_exact_helix_and_frame():
+    """Final-fit prior (helix through the hits on layers 0-2): with hits
+    exactly on the generator's helix (no smearing, no scattering) it is the
+    true state at the first layer; its covariance is diag(sigma)^2 in the
+    layer-tangent frame; a missing hit gives no prior."""
+    ev = synth.make_event(800, cfg=301, event=0, noise=0.0, smear=False, scatter=False)
+    cfg = oracle.config(ev.geometry)
+    par, cov, ok = oracle.circle_prior(cfg, ev.hits, ev.truth_hit)
+    assert ok.all()
+    d = par - ev.truth_par[:, 0]
+    d[:, 4] = (d[:, 4] + np.pi) % (2 * np.pi) - np.pi
+    assert np.abs(d[:, :3]).max() < 1e-9
+    assert np.abs(d[:, 3:]).max() < 1e-9
+    sig = np.asarray(oracle.FIT_PRIOR_SIGMA)
+    Cm = synth.unpack_sym(cov)
+    for i in range(0, 800, 97):
+        a = np.arctan2(par[i, 1], par[i, 0])
+        G = np.zeros((6, 5))
+        G[:2, 0] = (-np.sin(a), np.cos(a))
+        G[2, 1] = G[3, 2] = G[4, 3] = G[5, 4] = 1.0
+        assert np.allclose(G.T @ Cm[i] @ G, np.diag(sig ** 2), rtol=1e-12, atol=1e-15)
+        n = np.array([np.cos(a), np.sin(a), 0, 0, 0, 0])   # no variance along the layer normal
+        assert abs(n @ Cm[i] @ n) < 1e-12
+    th = ev.truth_hit.copy()
+    th[5, 1] = -1
+    _, _, ok2 = oracle.circle_prior(cfg, ev.hits, th)
+    assert not ok2[5] and ok2[[4, 6]].all()
+
+
+def test_circle_prior_fit_matches_generator_prior_fit():
+    """The fit from the oracle's prior equals the fit from the generator's own
+    prior construction (independent code, same reading) on smeared events."""
+    ev = synth.make_event(400, cfg=302, event=0, noise=0.0)
+    cfg = oracle.config(ev.geometry)
+    par, cov, ok = oracle.circle_prior(cfg, ev.hits, ev.truth_hit)
+    assert ok.all()
+    a = oracle.fit(cfg, ev.hits, par, cov, ev.truth_hit, n_threads=4)
+    b = oracle.fit(cfg, ev.hits, ev.prior_par, ev.prior_cov, ev.truth_hit, n_threads=4)
+    assert np.allclose(a["par"], b["par"], rtol=1e-9, atol=1e-9)
+    assert np.allclose(a["chi2"], b["chi2"], rtol=1e-9, atol=1e-9)
