@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of the barrel Kalman-filter track builder (ctypes binding).
+"""FP64 CPU oracle of the Kalman-filter track builder, barrel and endcap (ctypes binding).
 
 TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
 benchmark's CPU-baseline leg use it.  The GPU library never imports, links or
@@ -29,6 +29,7 @@ class OrcConfig(C.Structure):
         ("radius", C.c_double * MAX_LAYERS), ("x0", C.c_double * MAX_LAYERS),
         ("bz", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double),
         ("chi2_cut", C.c_double), ("mass", C.c_double),
+        ("kind", C.c_int32 * MAX_LAYERS), ("zplane", C.c_double * MAX_LAYERS), ("sigma_r", C.c_double),
     ]
 
 
@@ -81,10 +82,12 @@ def lib():
         ip = C.POINTER(C.c_int32)
         L.orc_propagate.argtypes = [dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_propagate.restype = C.c_int
-        L.orc_add_ms.argtypes = [dp, C.c_double, C.c_double, dp]
-        L.orc_chi2.argtypes = [dp, dp, dp, C.c_double, C.c_double]
+        L.orc_propagate_plane.argtypes = [dp, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.orc_propagate_plane.restype = C.c_int
+        L.orc_add_ms.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_chi2.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double]
         L.orc_chi2.restype = C.c_double
-        L.orc_update.argtypes = [dp, dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_update.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_update.restype = C.c_double
         L.orc_transport.argtypes = [dp, dp]
         L.orc_fit.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip,
@@ -125,11 +128,15 @@ def config(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n_seed_layers=3
     for i in range(geometry.n_layers):
         c.radius[i] = geometry.radii[i]
         c.x0[i] = geometry.x0[i]
+        if geometry.is_disk:
+            c.kind[i] = 1
+            c.zplane[i] = geometry.disk_z[i]
     c.bz = geometry.bz
     c.sigma_rphi = geometry.sigma_rphi
     c.sigma_z = geometry.sigma_z
     c.chi2_cut = chi2_cut
     c.mass = geometry.mass
+    c.sigma_r = geometry.sigma_r
     return c
 
 
@@ -158,10 +165,22 @@ def propagate(par, r, bz, jacobian=True):
     return rc == 0, out, (F.reshape(6, 6) if F is not None else None), s.value, m.value
 
 
-def add_ms(par, C6, x0, mass):
+def propagate_plane(par, zd, bz, jacobian=True):
+    """Propagation to the plane z = zd; returns (ok, new_par, F or None, path, margin)."""
+    p = _f64(par, (6,))
+    out = np.zeros(6)
+    F = np.zeros(36) if jacobian else None
+    s = C.c_double(0.0)
+    m = C.c_double(0.0)
+    rc = lib().orc_propagate_plane(_dp(p), float(zd), float(bz), _dp(out),
+                                   _dp(F) if F is not None else None, C.byref(s), C.byref(m))
+    return rc == 0, out, (F.reshape(6, 6) if F is not None else None), s.value, m.value
+
+
+def add_ms(par, C6, x0, mass, kind=0):
     p = _f64(par, (6,))
     Cm = _f64(C6, (36,)).copy()
-    lib().orc_add_ms(_dp(p), float(x0), float(mass), _dp(Cm))
+    lib().orc_add_ms(_dp(p), int(kind), float(x0), float(mass), _dp(Cm))
     return Cm.reshape(6, 6)
 
 
@@ -172,16 +191,17 @@ def transport(F, C6):
     return Cm.reshape(6, 6)
 
 
-def chi2(par, C6, hit, sigma_rphi, sigma_z):
+def chi2(par, C6, hit, sigma_rphi, sigma_2, kind=0):
+    """kind 0: (r*phi, z) measurement of a cylinder; kind 1: (r*phi, r) of a disk."""
     return lib().orc_chi2(_dp(_f64(par, (6,))), _dp(_f64(C6, (36,))), _dp(_f64(hit, (3,))),
-                          sigma_rphi, sigma_z)
+                          int(kind), sigma_rphi, sigma_2)
 
 
-def update(par, C6, hit, sigma_rphi, sigma_z):
+def update(par, C6, hit, sigma_rphi, sigma_2, kind=0):
     out_p = np.zeros(6)
     out_C = np.zeros(36)
     c2 = lib().orc_update(_dp(_f64(par, (6,))), _dp(_f64(C6, (36,))), _dp(_f64(hit, (3,))),
-                          sigma_rphi, sigma_z, _dp(out_p), _dp(out_C))
+                          int(kind), sigma_rphi, sigma_2, _dp(out_p), _dp(out_C))
     return out_p, out_C.reshape(6, 6), c2
 
 

@@ -1,4 +1,5 @@
-/* FP64 CPU oracle of the barrel Kalman-filter track builder and fitter.
+/* FP64 CPU oracle of the Kalman-filter track builder and fitter (barrel
+ * cylinders and endcap disks).
  *
  * TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
  * benchmark's CPU-baseline leg call it; the GPU library never does, and the
@@ -13,7 +14,8 @@
  *    candidates per seed; fitting repeats the KF over a fixed hit set.
  *  - Section 2.2: ideal barrel, uniform longitudinal field, hybrid state
  *    (global Cartesian position, polar momentum), KF update on the plane
- *    tangent to the hit radius.
+ *    tangent to the hit radius; the simplified geometry's endcap disks are
+ *    planes at fixed z, reached by propagation to that z.
  *  - Section 3.2.1: a variable number of hit candidates per layer, so the
  *    beam is re-ranked and pruned after every layer.
  * Where the paper gives no formula, the readings used are: helix in a uniform
@@ -114,6 +116,63 @@ static void sinc_terms(double a, double *S1, double *C1, double *S2, double *C2)
     }
 }
 
+/* State after transverse path s along the helix, and (F != NULL) its
+ * derivative with respect to the input state once the path is tied to the
+ * surface: kind 0 the cylinder of radius r (x^2 + y^2 = r^2 at the end),
+ * kind 1 the plane z = const. */
+static int helix_to(const double p[6], double s, double bz, int kind, double r, double out[6],
+                    double F[36], double *path)
+{
+    const double x = p[0], y = p[1], z = p[2], qpt = p[3], phi = p[4], th = p[5];
+    const double w = -KAPPA * bz * qpt;
+    double a = w * s, S1, C1, S2, C2;
+    sinc_terms(a, &S1, &C1, &S2, &C2);
+    const double cph = cos(phi), sph = sin(phi);
+    const double A = cph * S1 - sph * C1;        /* (sin(phi+a) - sin phi)/a */
+    const double B = cph * C1 + sph * S1;        /* (cos phi - cos(phi+a))/a */
+    const double gx = cph * S2 - sph * C2;       /* d A / d a */
+    const double gy = sph * S2 + cph * C2;       /* d B / d a */
+    const double cot = cos(th) / sin(th);
+    const double nx = x + s * A, ny = y + s * B;
+    const double nphi = phi + a;
+    (void)r;
+
+    out[0] = nx;
+    out[1] = ny;
+    out[2] = z + s * cot;
+    out[3] = qpt;
+    out[4] = wrap_angle(nphi);
+    out[5] = th;
+    if (path) *path = s;
+    if (!F) return 0;
+
+    /* d(out)/d(in) at fixed path s */
+    double P[36];
+    memset(P, 0, sizeof(P));
+    for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
+    const double dw = -KAPPA * bz;                /* dw / d(q/pT) */
+    P[0 * 6 + 3] = s * s * gx * dw;
+    P[0 * 6 + 4] = -s * B;
+    P[1 * 6 + 3] = s * s * gy * dw;
+    P[1 * 6 + 4] = s * A;
+    P[2 * 6 + 5] = -s / (sin(th) * sin(th));
+    P[4 * 6 + 3] = s * dw;
+    /* the path itself depends on the inputs through the surface equation;
+     * t is d(out)/ds */
+    const double cn = cos(nphi), sn = sin(nphi);
+    const double t[6] = {cn, sn, cot, 0.0, w, 0.0};
+    double ds[6];
+    if (kind == 0) {           /* x(s)^2 + y(s)^2 = r^2 */
+        const double den = nx * cn + ny * sn;
+        for (int j = 0; j < 6; ++j) ds[j] = -(nx * P[0 * 6 + j] + ny * P[1 * 6 + j]) / den;
+    } else {                   /* z(s) = const */
+        for (int j = 0; j < 6; ++j) ds[j] = -P[2 * 6 + j] / cot;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) F[i * 6 + j] = P[i * 6 + j] + t[i] * ds[j];
+    return 0;
+}
+
 int orc_propagate(const double p[6], double r, double bz, double out[6], double F[36],
                   double *path, double *margin)
 {
@@ -163,45 +222,22 @@ int orc_propagate(const double p[6], double r, double bz, double out[6], double 
     if (margin) *margin = mrg;
     if (!(s > 0.0)) return 1;
 
-    double a = w * s, S1, C1, S2, C2;
-    sinc_terms(a, &S1, &C1, &S2, &C2);
-    const double cph = cos(phi), sph = sin(phi);
-    const double A = cph * S1 - sph * C1;        /* (sin(phi+a) - sin phi)/a */
-    const double B = cph * C1 + sph * S1;        /* (cos phi - cos(phi+a))/a */
-    const double gx = cph * S2 - sph * C2;       /* d A / d a */
-    const double gy = sph * S2 + cph * C2;       /* d B / d a */
-    const double cot = cos(th) / sin(th);
-    const double nx = x + s * A, ny = y + s * B;
-    const double nphi = phi + a;
+    return helix_to(p, s, bz, 0, r, out, F, path);
+}
 
-    out[0] = nx;
-    out[1] = ny;
-    out[2] = z + s * cot;
-    out[3] = qpt;
-    out[4] = wrap_angle(nphi);
-    out[5] = th;
-    if (path) *path = s;
-    if (!F) return 0;
-
-    /* d(out)/d(in) at fixed path s */
-    double P[36];
-    memset(P, 0, sizeof(P));
-    for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
-    const double dw = -KAPPA * bz;                /* dw / d(q/pT) */
-    P[0 * 6 + 3] = s * s * gx * dw;
-    P[0 * 6 + 4] = -s * B;
-    P[1 * 6 + 3] = s * s * gy * dw;
-    P[1 * 6 + 4] = s * A;
-    P[2 * 6 + 5] = -s / (sin(th) * sin(th));
-    P[4 * 6 + 3] = s * dw;
-    /* the path depends on the inputs through x(s)^2 + y(s)^2 = r^2 */
-    const double cn = cos(nphi), sn = sin(nphi);
-    const double den = nx * cn + ny * sn;
-    const double t[6] = {cn, sn, cot, 0.0, w, 0.0};
-    double ds[6];
-    for (int j = 0; j < 6; ++j) ds[j] = -(nx * P[0 * 6 + j] + ny * P[1 * 6 + j]) / den;
-    for (int i = 0; i < 6; ++i)
-        for (int j = 0; j < 6; ++j) F[i * 6 + j] = P[i * 6 + j] + t[i] * ds[j];
+/* Propagation to the plane z = zd (an endcap disk of the simplified
+ * geometry, Section 2.2): the longitudinal
+ * motion is linear in the transverse path, z(s) = z + s cot(theta), so
+ * s = (zd - z) tan(theta), valid when positive (the helix moves towards the
+ * plane).  *margin receives s. */
+int orc_propagate_plane(const double p[6], double zd, double bz, double out[6], double F[36],
+                        double *path, double *margin)
+{
+    const double s = (zd - p[2]) * tan(p[5]);
+    if (margin) *margin = s;
+    if (!(s > 0.0) || !isfinite(s)) return 1;
+    helix_to(p, s, bz, 1, 0.0, out, F, path);
+    out[2] = zd;                 /* on the plane by definition, not up to rounding */
     return 0;
 }
 
@@ -217,15 +253,16 @@ void orc_transport(const double F[36], double C[36])
 /* ------------------------------------------------------------ material */
 
 /* Highland scattering angle for a layer of x0 radiation lengths crossed at
- * incidence alpha to its normal; the two projected angles add noise to the
- * momentum direction: Var phi += th0^2/sin^2 theta, Var theta += th0^2, and
- * q/pT = q/(p sin theta) picks up the theta part at fixed |p|. */
-void orc_add_ms(const double p[6], double x0, double mass, double C[36])
+ * incidence alpha to its normal (the radial direction on a cylinder, z on a
+ * disk); the two projected angles add noise to the momentum direction:
+ * Var phi += th0^2/sin^2 theta, Var theta += th0^2, and q/pT = q/(p sin theta)
+ * picks up the theta part at fixed |p|. */
+void orc_add_ms(const double p[6], int kind, double x0, double mass, double C[36])
 {
     if (x0 <= 0.0) return;
     const double qpt = p[3], phi = p[4], th = p[5];
     const double phipos = atan2(p[1], p[0]);
-    double cosa = fabs(sin(th) * cos(phi - phipos));
+    double cosa = kind == 0 ? fabs(sin(th) * cos(phi - phipos)) : fabs(cos(th));
     if (cosa < 1e-6) cosa = 1e-6;
     const double t = x0 / cosa;
     const double k = fabs(qpt) * sin(th);                 /* 1 / |p| */
@@ -248,10 +285,13 @@ void orc_add_ms(const double p[6], double x0, double mass, double C[36])
 
 /* ------------------------------------------------------------ measurement */
 
-/* The measurement is the hit position in the plane tangent to the layer at
- * the hit: u along (-sin phi_h, cos phi_h, 0) and z.  H is the 2x6 matrix of
- * that projection, V = diag(sigma_rphi^2, sigma_z^2). */
-static void measurement(const double p[6], const double hit[3], double srphi, double sz,
+/* The measurement is the hit position in a plane through the hit: on a
+ * cylinder (kind 0) the tangent plane, coordinates u along
+ * (-sin phi_h, cos phi_h, 0) and z; on a disk (kind 1) the disk's own plane,
+ * coordinates u and v along (cos phi_h, sin phi_h, 0), the radial direction.
+ * H is the 2x6 matrix of that projection, V = diag(sigma_rphi^2, s2^2) with
+ * s2 the resolution of the second coordinate. */
+static void measurement(const double p[6], const double hit[3], int kind, double srphi, double s2,
                         double H[12], double res[2], double V[4])
 {
     const double phih = atan2(hit[1], hit[0]);
@@ -259,13 +299,19 @@ static void measurement(const double p[6], const double hit[3], double srphi, do
     memset(H, 0, 12 * sizeof(double));
     H[0 * 6 + 0] = -sh;
     H[0 * 6 + 1] = ch;
-    H[1 * 6 + 2] = 1.0;
     res[0] = (hit[0] - p[0]) * (-sh) + (hit[1] - p[1]) * ch;
-    res[1] = hit[2] - p[2];
+    if (kind == 0) {
+        H[1 * 6 + 2] = 1.0;
+        res[1] = hit[2] - p[2];
+    } else {
+        H[1 * 6 + 0] = ch;
+        H[1 * 6 + 1] = sh;
+        res[1] = (hit[0] - p[0]) * ch + (hit[1] - p[1]) * sh;
+    }
     V[0] = srphi * srphi;
     V[1] = 0.0;
     V[2] = 0.0;
-    V[3] = sz * sz;
+    V[3] = s2 * s2;
 }
 
 static void innovation(const double C[36], const double H[12], const double V[4], double HC[12],
@@ -283,20 +329,21 @@ static void innovation(const double C[36], const double H[12], const double V[4]
     Sinv[3] = S[0] / det;
 }
 
-double orc_chi2(const double p[6], const double C[36], const double hit[3], double srphi, double sz)
+double orc_chi2(const double p[6], const double C[36], const double hit[3], int kind, double srphi,
+                double s2)
 {
     double H[12], r[2], V[4], HC[12], S[4], Si[4], Sr[2];
-    measurement(p, hit, srphi, sz, H, r, V);
+    measurement(p, hit, kind, srphi, s2, H, r, V);
     innovation(C, H, V, HC, S, Si);
     matmul(Si, r, Sr, 2, 2, 1);
     return r[0] * Sr[0] + r[1] * Sr[1];
 }
 
-double orc_update(const double p[6], const double C[36], const double hit[3], double srphi,
-                  double sz, double out_p[6], double out_C[36])
+double orc_update(const double p[6], const double C[36], const double hit[3], int kind, double srphi,
+                  double s2, double out_p[6], double out_C[36])
 {
     double H[12], r[2], V[4], HC[12], S[4], Si[4], Sr[2];
-    measurement(p, hit, srphi, sz, H, r, V);
+    measurement(p, hit, kind, srphi, s2, H, r, V);
     innovation(C, H, V, HC, S, Si);
     matmul(Si, r, Sr, 2, 2, 1);
     const double chi2 = r[0] * Sr[0] + r[1] * Sr[1];
@@ -314,6 +361,39 @@ double orc_update(const double p[6], const double C[36], const double hit[3], do
     memcpy(out_p, np, sizeof(np));
     memcpy(out_C, nC, sizeof(nC));
     return chi2;
+}
+
+/* ------------------------------------------------------------ layers */
+
+/* Propagation to layer L: its cylinder, or its disk's plane. */
+static int to_layer(const orc_config *cfg, int L, const double p[6], double out[6], double F[36],
+                    double *margin)
+{
+    if (cfg->kind[L] == 0) return orc_propagate(p, cfg->radius[L], cfg->bz, out, F, NULL, margin);
+    return orc_propagate_plane(p, cfg->zplane[L], cfg->bz, out, F, NULL, margin);
+}
+
+/* resolution of a layer's second measured coordinate: z or r */
+static double second_sigma(const orc_config *cfg, int L)
+{
+    return cfg->kind[L] == 0 ? cfg->sigma_z : cfg->sigma_r;
+}
+
+static double layer_chi2(const orc_config *cfg, int L, const double p[6], const double C[36],
+                         const double hit[3])
+{
+    return orc_chi2(p, C, hit, cfg->kind[L], cfg->sigma_rphi, second_sigma(cfg, L));
+}
+
+static double layer_update(const orc_config *cfg, int L, const double p[6], const double C[36],
+                           const double hit[3], double out_p[6], double out_C[36])
+{
+    return orc_update(p, C, hit, cfg->kind[L], cfg->sigma_rphi, second_sigma(cfg, L), out_p, out_C);
+}
+
+static void leave_layer(const orc_config *cfg, int L, const double p[6], double C[36])
+{
+    orc_add_ms(p, cfg->kind[L], cfg->x0[L], cfg->mass, C);
 }
 
 /* ------------------------------------------------------------ threading */
@@ -385,8 +465,8 @@ static void fit_one(void *vctx, int64_t i)
     for (int L = 0; L < nl; ++L) {
         if (L > 0) {
             double np[6], F[36];
-            orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
-            if (orc_propagate(p, cfg->radius[L], cfg->bz, np, F, NULL, NULL)) {
+            leave_layer(cfg, L - 1, p, C);
+            if (to_layer(cfg, L, p, np, F, NULL)) {
                 status = 2;
                 break;
             }
@@ -396,7 +476,7 @@ static void fit_one(void *vctx, int64_t i)
         const int32_t h = c->track_hits[i * nl + L];
         if (h >= 0) {
             const double *hit = c->hits->xyz[L] + 3 * (int64_t)h;
-            double c2 = orc_update(p, C, hit, cfg->sigma_rphi, cfg->sigma_z, p, C);
+            double c2 = layer_update(cfg, L, p, C, hit, p, C);
             chi2 += c2;
             ++nupd;
             memcpy(op, p, sizeof(p));
@@ -463,16 +543,24 @@ void orc_circle_prior(const orc_config *cfg, const orc_hits *hits, int32_t n_tra
         par[3] = -w / (KAPPA * cfg->bz);
         par[4] = phi;
         par[5] = 0.5 * PI - atan(cot);
-        /* covariance: local diagonal rotated to (x, y) by the hit's azimuth */
+        /* covariance: local diagonal rotated to (x, y) by the hit's azimuth;
+         * the second coordinate is z on a cylinder, r on a disk (where the
+         * plane fixes z) */
         const double a = atan2(p[0][1], p[0][0]);
         const double s = sin(a), c = cos(a);
         double C[36];
         memset(C, 0, sizeof(C));
-        const double vu = sig[0] * sig[0];
-        C[0] = s * s * vu;
-        C[1] = C[6] = -s * c * vu;
-        C[7] = c * c * vu;
-        C[14] = sig[1] * sig[1];
+        const double vu = sig[0] * sig[0], v2 = sig[1] * sig[1];
+        if (cfg->kind[0] == 0) {
+            C[0] = s * s * vu;
+            C[1] = C[6] = -s * c * vu;
+            C[7] = c * c * vu;
+            C[14] = v2;
+        } else {
+            C[0] = s * s * vu + c * c * v2;
+            C[1] = C[6] = -s * c * vu + s * c * v2;
+            C[7] = c * c * vu + s * s * v2;
+        }
         C[21] = sig[2] * sig[2];
         C[28] = sig[3] * sig[3];
         C[35] = sig[4] * sig[4];
@@ -556,9 +644,9 @@ static void build_one(void *vctx, int64_t row)
                 double p[6], C[36], F[36], mrg;
                 memcpy(p, cd->par, sizeof(p));
                 memcpy(C, cd->C, sizeof(C));
-                orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
+                leave_layer(cfg, L - 1, p, C);
                 ++n_prop;
-                int fail = orc_propagate(p, r, cfg->bz, pred_par[c], F, NULL, &mrg);
+                int fail = to_layer(cfg, L, p, pred_par[c], F, &mrg);
                 if (fabs(mrg) / r < m_prop) m_prop = fabs(mrg) / r;
                 if (fail) {
                     cd->stopped = 1;
@@ -572,7 +660,7 @@ static void build_one(void *vctx, int64_t row)
                     for (int32_t j = 0; j < bc->hits->n_hits[L]; ++j) {
                         const double *h = xyz + 3 * (int64_t)j;
                         if (h[0] * pp[0] + h[1] * pp[1] <= 0.0) continue;   /* other side */
-                        double c2 = orc_chi2(pp, pred_C[c], h, cfg->sigma_rphi, cfg->sigma_z);
+                        double c2 = layer_chi2(cfg, L, pp, pred_C[c], h);
                         double dm = fabs(c2 - cfg->chi2_cut);
                         if (dm < m_cut) m_cut = dm;
                         if (c2 < cfg->chi2_cut) {
@@ -641,8 +729,7 @@ static void build_one(void *vctx, int64_t row)
             *nc = *par;
             if (e->kind == KIND_HIT) {
                 const double *h = bc->hits->xyz[L] + 3 * (int64_t)e->hit;
-                orc_update(pred_par[e->parent], pred_C[e->parent], h, cfg->sigma_rphi, cfg->sigma_z,
-                           nc->par, nc->C);
+                layer_update(cfg, L, pred_par[e->parent], pred_C[e->parent], h, nc->par, nc->C);
                 nc->chi2 = e->chi2;
                 nc->hits[L] = e->hit;
                 nc->n_hits = e->n_hits;
@@ -699,8 +786,8 @@ double orc_replay(const orc_config *cfg, const orc_hits *hits, const double seed
     for (int L = 0; L < cfg->n_layers; ++L) layer_chi2[L] = -1.0;
     for (int L = cfg->n_seed_layers; L < cfg->n_layers; ++L) {
         double np[6], F[36];
-        orc_add_ms(p, cfg->x0[L - 1], cfg->mass, C);
-        if (orc_propagate(p, cfg->radius[L], cfg->bz, np, F, NULL, NULL)) {
+        leave_layer(cfg, L - 1, p, C);
+        if (to_layer(cfg, L, p, np, F, NULL)) {
             *ok = 0;
             break;
         }
@@ -709,7 +796,7 @@ double orc_replay(const orc_config *cfg, const orc_hits *hits, const double seed
         const int32_t h = layer_hits[L];
         if (h >= 0) {
             const double *hit = hits->xyz[L] + 3 * (int64_t)h;
-            double c2 = orc_update(p, C, hit, cfg->sigma_rphi, cfg->sigma_z, p, C);
+            double c2 = layer_update(cfg, L, p, C, hit, p, C);
             layer_chi2[L] = c2;
             total += c2;
             if (!(c2 < cfg->chi2_cut)) *ok = 0;

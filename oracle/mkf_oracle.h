@@ -1,4 +1,5 @@
-/* FP64 CPU oracle of the barrel Kalman-filter track builder and fitter.
+/* FP64 CPU oracle of the Kalman-filter track builder and fitter (barrel
+ * cylinders and endcap disks).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the tests, the package's smoke check and
  * the benchmark's CPU-baseline leg may call it.  It shares no source, header,
@@ -35,6 +36,9 @@ typedef struct {
     double sigma_z;
     double chi2_cut;
     double mass;                /* mass hypothesis for the scattering angle */
+    int32_t kind[ORC_MAX_LAYERS];   /* 0 cylinder of radius radius[L], 1 disk: plane z = zplane[L] */
+    double zplane[ORC_MAX_LAYERS];
+    double sigma_r;             /* disk hit resolution along r */
 } orc_config;
 
 typedef struct {
@@ -71,18 +75,26 @@ typedef struct {
 int orc_propagate(const double par[6], double r, double bz, double out[6],
                   double F[36], double *path, double *margin);
 
-/* Add multiple-scattering noise for crossing a layer of thickness x0 at the
- * state's position (full 6x6 row-major covariance, in place). */
-void orc_add_ms(const double par[6], double x0, double mass, double C[36]);
+/* Propagate a state to the plane z = zd.  Returns 1 if the helix moves away
+ * from it; *margin receives the signed transverse path. */
+int orc_propagate_plane(const double par[6], double zd, double bz, double out[6],
+                        double F[36], double *path, double *margin);
 
-/* chi2 of a hit against a predicted state (full 6x6 covariance). */
-double orc_chi2(const double par[6], const double C[36], const double hit[3],
-                double sigma_rphi, double sigma_z);
+/* Add multiple-scattering noise for crossing a layer (kind 0 cylinder, 1
+ * disk) of thickness x0 at the state's position (full 6x6 row-major
+ * covariance, in place). */
+void orc_add_ms(const double par[6], int kind, double x0, double mass, double C[36]);
+
+/* chi2 of a hit against a predicted state (full 6x6 covariance); kind 0
+ * measures (r*phi, z), kind 1 (r*phi, r); s2 is the second coordinate's
+ * resolution. */
+double orc_chi2(const double par[6], const double C[36], const double hit[3], int kind,
+                double sigma_rphi, double s2);
 
 /* KF update with one hit; writes the filtered state and covariance and
  * returns the hit's chi2. */
-double orc_update(const double par[6], const double C[36], const double hit[3],
-                  double sigma_rphi, double sigma_z, double out_par[6], double out_C[36]);
+double orc_update(const double par[6], const double C[36], const double hit[3], int kind,
+                  double sigma_rphi, double s2, double out_par[6], double out_C[36]);
 
 /* Transport C <- F C F^T (full 6x6). */
 void orc_transport(const double F[36], double C[36]);
@@ -101,7 +113,7 @@ void orc_fit(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
  * them - the circle through the three transverse points, z linear in the arc
  * length - evaluated at the first hit, with the covariance
  * diag(sig[0..4])^2 in the frame (u, z, q/pT, phi, theta), u along the layer
- * tangent at the hit's azimuth.  out_ok[i] = 0 when a hit is missing or the
+ * tangent at the hit's azimuth (on a disk: (u, r, q/pT, phi, theta)).  out_ok[i] = 0 when a hit is missing or the
  * three points are collinear (then out_par/out_cov are zero). */
 void orc_circle_prior(const orc_config *cfg, const orc_hits *hits, int32_t n_tracks,
                       const int32_t *track_hits, const double sig[5], double *out_par, double *out_cov,

@@ -37,13 +37,33 @@ KAPPA = 0.00299792458  # GeV / (T cm): transverse momentum = KAPPA * B * radius
 # (u and z: the third hit itself; q/pT: sagitta over an 8 cm chord, sigma_rphi
 # = 100 um; phi and theta: chord directions), so the seed is conservative.
 SEED_SIGMA = (0.012, 0.12, 0.20, 0.009, 0.020)
-# loose prior for a fit that starts from the innermost hit
+# the same for disks, frame (u along r*phi, v along r, q/pT, phi, theta): the
+# three seed hits span only a few cm of transverse path, so the curvature is
+# nearly unknown (measured spreads on generated endcap events: 0.010, 0.10,
+# 0.48, 0.011, 0.0066)
+SEED_SIGMA_DISK = (0.012, 0.12, 0.58, 0.014, 0.008)
+# and their correlations, measured on the same events: the short arc ties the
+# curvature to the direction
+SEED_CORR_DISK = np.array([
+    [1.00, 0.00, -0.34, 0.55, 0.00],
+    [0.00, 1.00, 0.00, 0.00, 0.70],
+    [-0.34, 0.00, 1.00, -0.93, 0.00],
+    [0.55, 0.00, -0.93, 1.00, 0.00],
+    [0.00, 0.70, 0.00, 0.00, 1.00],
+])
+# loose prior for a fit that starts from the innermost hit (second
+# coordinate: z on a cylinder, r on a disk)
 PRIOR_SIGMA = (1.0, 10.0, 1.0, 0.1, 0.1)
 
 
 @dataclasses.dataclass
 class Geometry:
-    """Ideal barrel: n_layers cylinders at radius r_L, each 0.2 % X0 thick."""
+    """Ideal barrel: n_layers cylinders at radius r_L, each 0.2 % X0 thick.
+
+    With disk_z set the layers are instead endcap disks (Section 2.2: the
+    CMS geometry's endcaps, here ideal planes): disk L lies in the plane
+    z = disk_z[L] between radii disk_rmin and radii[L]; its hits are measured
+    along r*phi (sigma_rphi) and r (sigma_r)."""
     n_layers: int = 10
     radii: Sequence[float] = tuple(4.0 * (i + 1) for i in range(10))
     x0: Sequence[float] = tuple(0.002 for _ in range(10))
@@ -51,10 +71,27 @@ class Geometry:
     sigma_rphi: float = 0.01
     sigma_z: float = 0.1
     mass: float = 0.13957
+    disk_z: Optional[Sequence[float]] = None
+    disk_rmin: float = 2.0
+    sigma_r: float = 0.1
+
+    @property
+    def is_disk(self) -> bool:
+        return self.disk_z is not None
+
+    @staticmethod
+    def endcap(n_layers: int = 10) -> "Geometry":
+        """Forward tracker of n_layers disks at z = 30, 40, ... cm, radii 2-60 cm."""
+        return Geometry(n_layers=n_layers, radii=tuple(60.0 for _ in range(n_layers)),
+                        x0=tuple(0.002 for _ in range(n_layers)),
+                        disk_z=tuple(30.0 + 10.0 * i for i in range(n_layers)))
 
     def half_z(self) -> np.ndarray:
-        """Half length that bounds noise hits and the bin grid (|eta| < 1 plus margin)."""
+        """Half length that bounds noise hits and the bin grid (|eta| < 1 plus
+        margin); for disks, the outer radius."""
         r = np.asarray(self.radii, dtype=np.float64)
+        if self.is_disk:
+            return r.copy()
         return 1.05 * r * math.sinh(1.0) + 3.0
 
 
@@ -127,6 +164,23 @@ def _cross_cylinder(x, y, z, qpt, phi, theta, r, bz):
     return nx, ny, nz, nphi, s
 
 
+def _cross_plane(x, y, z, qpt, phi, theta, zd, bz):
+    """Crossing of the plane z = zd by a helix: the transverse path is fixed by
+    the dip angle, s = (zd - z) tan(theta), and the turning-angle form gives
+    the point.  Returns the new (x, y, z, phi) and s (negative: plane behind)."""
+    w = -KAPPA * bz * qpt
+    straight = np.abs(w) < 1e-12
+    ws = np.where(straight, 1.0, w)
+    s = (zd - z) * np.tan(theta)
+    nphi = phi + np.where(straight, 0.0, w * s)
+    cx = x - np.sin(phi) / ws
+    cy = y + np.cos(phi) / ws
+    nx = np.where(straight, x + s * np.cos(phi), cx + np.sin(nphi) / ws)
+    ny = np.where(straight, y + s * np.sin(phi), cy - np.cos(nphi) / ws)
+    nphi = np.mod(nphi + np.pi, 2.0 * np.pi) - np.pi
+    return nx, ny, np.full(np.shape(x), float(zd)), nphi, s
+
+
 def _highland(p, beta, t):
     return 0.0136 / (beta * p) * np.sqrt(t) * (1.0 + 0.038 * np.log(t))
 
@@ -159,6 +213,26 @@ def _circle_seed(p1, p2, p3, z1, z3, bz, at_first: bool):
     theta = 0.5 * np.pi - np.arctan(cot)
     phi = np.mod(phi + np.pi, 2 * np.pi) - np.pi
     return qpt, phi, theta
+
+
+def local_cov_to_packed_disk(phi_pos: np.ndarray, sig: Sequence[float],
+                             corr: Optional[np.ndarray] = None) -> np.ndarray:
+    """As local_cov_to_packed for a disk: the local covariance
+    diag(sig) corr diag(sig) (corr = identity by default) in the frame
+    (u along r*phi, v along r, q/pT, phi, theta), rotated to global
+    coordinates (x = -sin(phi_pos) u + cos(phi_pos) v, y = cos u + sin v);
+    z is fixed by the plane and carries no variance."""
+    sg = np.asarray(sig, dtype=np.float64)
+    R = np.eye(5) if corr is None else np.asarray(corr, dtype=np.float64)
+    local = sg[:, None] * R * sg[None, :]
+    s = np.sin(phi_pos)
+    c = np.cos(phi_pos)
+    G = np.zeros((phi_pos.shape[0], 6, 5))
+    G[:, 0, 0], G[:, 1, 0] = -s, c
+    G[:, 0, 1], G[:, 1, 1] = c, s
+    G[:, 3, 2] = G[:, 4, 3] = G[:, 5, 4] = 1.0
+    full = G @ local @ np.swapaxes(G, 1, 2)
+    return pack_sym(full)
 
 
 def local_cov_to_packed(phi_pos: np.ndarray, sig: Sequence[float]) -> np.ndarray:
@@ -200,18 +274,22 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
                smear: bool = True, scatter: bool = True,
                smear_scale: float = 1.0,
                pt_range=(0.5, 10.0), eta_max: float = 1.0,
-               vertex_sigma=(0.01, 1.0)) -> Event:
+               vertex_sigma=(0.01, 1.0), eta_range: Optional[Sequence[float]] = None) -> Event:
     """Generate one event of n_tracks particles plus uniform noise hits.
 
     noise: fraction of the true-hit count added per layer as uniform noise
-    (a scalar, or one value per layer).
+    (a scalar, or one value per layer).  Pseudo-rapidity: uniform in
+    eta_range, by default (-eta_max, eta_max) for a barrel and (1.6, 2.6) for
+    the endcap geometry (every track crosses every disk).
     """
     g = geometry or Geometry()
     nl = g.n_layers
     rk, rv, rms, rsm, rno, rsh = _streams(cfg, event, 6)
     n = int(n_tracks)
     pt = rk.uniform(pt_range[0], pt_range[1], n)
-    eta = rk.uniform(-eta_max, eta_max, n)
+    if eta_range is None:
+        eta_range = (1.6, 2.6) if g.is_disk else (-eta_max, eta_max)
+    eta = rk.uniform(eta_range[0], eta_range[1], n)
     phi = rk.uniform(-np.pi, np.pi, n)
     q = np.where(rk.uniform(0.0, 1.0, n) < 0.5, -1.0, 1.0)
     theta = 2.0 * np.arctan(np.exp(-eta))
@@ -226,19 +304,36 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
     true_xyz = np.zeros((n, nl, 3))
     for L in range(nl):
         r = float(g.radii[L])
-        x, y, z, phi, _ = _cross_cylinder(x, y, z, qpt, phi, theta, r, g.bz)
+        if g.is_disk:
+            x, y, z, phi, _ = _cross_plane(x, y, z, qpt, phi, theta, float(g.disk_z[L]), g.bz)
+        else:
+            x, y, z, phi, _ = _cross_cylinder(x, y, z, qpt, phi, theta, r, g.bz)
         truth[:, L] = np.stack([x, y, z, qpt, phi, theta], axis=1)
         phi_pos = np.arctan2(y, x)
-        if smear:
-            phi_h = phi_pos + rsm.normal(0.0, g.sigma_rphi * smear_scale, n) / r
-            z_h = z + rsm.normal(0.0, g.sigma_z * smear_scale, n)
+        if g.is_disk:
+            # r*phi and r measured on the plane
+            r_pos = np.hypot(x, y)
+            if smear:
+                phi_h = phi_pos + rsm.normal(0.0, g.sigma_rphi * smear_scale, n) / r_pos
+                r_h = r_pos + rsm.normal(0.0, g.sigma_r * smear_scale, n)
+            else:
+                phi_h, r_h = phi_pos, r_pos
+            true_xyz[:, L] = np.stack([r_h * np.cos(phi_h), r_h * np.sin(phi_h), z], axis=1)
         else:
-            phi_h = phi_pos
-            z_h = z.copy()
-        true_xyz[:, L] = np.stack([r * np.cos(phi_h), r * np.sin(phi_h), z_h], axis=1)
+            if smear:
+                phi_h = phi_pos + rsm.normal(0.0, g.sigma_rphi * smear_scale, n) / r
+                z_h = z + rsm.normal(0.0, g.sigma_z * smear_scale, n)
+            else:
+                phi_h = phi_pos
+                z_h = z.copy()
+            true_xyz[:, L] = np.stack([r * np.cos(phi_h), r * np.sin(phi_h), z_h], axis=1)
         if scatter and g.x0[L] > 0:
-            # two independent Gaussian angles in the planes orthogonal to p
-            cos_a = np.abs(np.sin(theta) * np.cos(phi - phi_pos))
+            # two independent Gaussian angles in the planes orthogonal to p;
+            # path factor 1/|cos| of the angle to the surface normal
+            if g.is_disk:
+                cos_a = np.abs(np.cos(theta))
+            else:
+                cos_a = np.abs(np.sin(theta) * np.cos(phi - phi_pos))
             t = g.x0[L] / np.maximum(cos_a, 1e-6)
             beta = p / np.sqrt(p * p + g.mass * g.mass)
             th0 = _highland(p, beta, t)
@@ -264,8 +359,12 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
         nn = int(round(frac[L] * n))
         n_noise[L] = nn
         ph = rno.uniform(-np.pi, np.pi, nn)
-        zz = rno.uniform(-hz[L], hz[L], nn)
-        noise_xyz = np.stack([r * np.cos(ph), r * np.sin(ph), zz], axis=1)
+        if g.is_disk:   # uniform over the annulus
+            rr = np.sqrt(rno.uniform(g.disk_rmin ** 2, r * r, nn))
+            noise_xyz = np.stack([rr * np.cos(ph), rr * np.sin(ph), np.full(nn, float(g.disk_z[L]))], axis=1)
+        else:
+            zz = rno.uniform(-hz[L], hz[L], nn)
+            noise_xyz = np.stack([r * np.cos(ph), r * np.sin(ph), zz], axis=1)
         allh = np.concatenate([true_xyz[:, L], noise_xyz], axis=0)
         perm = rsh.permutation(allh.shape[0])
         inv = np.empty_like(perm)
@@ -277,11 +376,15 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
     h0, h1, h2 = true_xyz[:, 0], true_xyz[:, 1], true_xyz[:, 2]
     sq, sphi, sth = _circle_seed(h0[:, :2], h1[:, :2], h2[:, :2], h0[:, 2], h2[:, 2], g.bz, False)
     seed_par = np.stack([h2[:, 0], h2[:, 1], h2[:, 2], sq, sphi, sth], axis=1)
-    seed_cov = local_cov_to_packed(np.arctan2(h2[:, 1], h2[:, 0]), SEED_SIGMA)
+    to_packed = local_cov_to_packed_disk if g.is_disk else local_cov_to_packed
+    if g.is_disk:
+        seed_cov = local_cov_to_packed_disk(np.arctan2(h2[:, 1], h2[:, 0]), SEED_SIGMA_DISK, SEED_CORR_DISK)
+    else:
+        seed_cov = local_cov_to_packed(np.arctan2(h2[:, 1], h2[:, 0]), SEED_SIGMA)
     seed_hits = np.ascontiguousarray(truth_hit[:, :3])
     pq, pphi, pth = _circle_seed(h0[:, :2], h1[:, :2], h2[:, :2], h0[:, 2], h2[:, 2], g.bz, True)
     prior_par = np.stack([h0[:, 0], h0[:, 1], h0[:, 2], pq, pphi, pth], axis=1)
-    prior_cov = local_cov_to_packed(np.arctan2(h0[:, 1], h0[:, 0]), PRIOR_SIGMA)
+    prior_cov = to_packed(np.arctan2(h0[:, 1], h0[:, 0]), PRIOR_SIGMA)
     return Event(geometry=g, hits=hits, seed_par=np.ascontiguousarray(seed_par),
                  seed_cov=seed_cov, seed_hits=seed_hits, truth_hit=truth_hit,
                  truth_par=truth, vertex_par=vertex, prior_par=np.ascontiguousarray(prior_par),
