@@ -53,10 +53,18 @@ typedef enum {
 #define MKF_HOLE_ALWAYS 0x1u   /* offer a hole child even when hits were accepted */
 
 /* Detector, field and building parameters (Section 2.2: ideal barrel of
- * cylinders in a uniform longitudinal field, Gaussian hit resolution).
- * layer_half_z bounds the hit index grid only (hits beyond it go to the edge
- * bins); layer_x0 is the material of each layer in radiation lengths at
- * normal incidence (0 = none). */
+ * cylinders in a uniform longitudinal field, Gaussian hit resolution; the
+ * simplified geometry's endcap disks as planes at fixed z).
+ * Layer L is a cylinder of radius layer_r[L] (layer_kind 0) or a disk
+ * (layer_kind 1) in the plane z = layer_z[L] between radii layer_rmin[L] and
+ * layer_r[L].  A cylinder's hits are measured along r*phi (sigma_rphi) and z
+ * (sigma_z), a disk's along r*phi and r (sigma_r).  layer_half_z (cylinders)
+ * and the disk radii bound the hit index grid only: hits beyond them go to
+ * the edge bins, a track may cross a layer anywhere.  layer_x0 is the
+ * material of each layer in radiation lengths at normal incidence (0 = none);
+ * the path through it grows as 1 / cos of the angle to the layer normal
+ * (radial for a cylinder, z for a disk).  Layers are crossed in index order;
+ * consecutive cylinders need increasing radii. */
 typedef struct {
     int32_t n_layers;        /* 4 .. MKF_MAX_LAYERS */
     int32_t n_seed_layers;   /* seeds carry one hit on each of layers 0 .. n_seed_layers-1 */
@@ -72,6 +80,10 @@ typedef struct {
     double sigma_z;          /* hit resolution along z, cm */
     double chi2_cut;         /* a hit is compatible when its chi2 < chi2_cut */
     double mass;             /* mass hypothesis for the scattering angle, GeV */
+    int32_t layer_kind[MKF_MAX_LAYERS];   /* 0 cylinder (all zero: a barrel), 1 disk */
+    double layer_z[MKF_MAX_LAYERS];       /* disk plane, cm (nonzero) */
+    double layer_rmin[MKF_MAX_LAYERS];    /* disk inner radius, 0 <= rmin < layer_r */
+    double sigma_r;          /* disk hit resolution along r, cm (> 0 when a disk exists) */
 } mkf_config;
 
 /* Device memory hooks.  alloc returns device memory usable on `stream`

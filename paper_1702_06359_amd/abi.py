@@ -45,6 +45,8 @@ class Config(C.Structure):
         ("layer_x0", C.c_double * MAX_LAYERS),
         ("bz", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double),
         ("chi2_cut", C.c_double), ("mass", C.c_double),
+        ("layer_kind", C.c_int32 * MAX_LAYERS), ("layer_z", C.c_double * MAX_LAYERS),
+        ("layer_rmin", C.c_double * MAX_LAYERS), ("sigma_r", C.c_double),
     ]
 
 
@@ -179,9 +181,14 @@ def config_from_geometry(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n
         c.layer_r[i] = geometry.radii[i]
         c.layer_half_z[i] = hz[i]
         c.layer_x0[i] = geometry.x0[i]
+        if geometry.is_disk:
+            c.layer_kind[i] = 1
+            c.layer_z[i] = geometry.disk_z[i]
+            c.layer_rmin[i] = geometry.disk_rmin
     c.bz = geometry.bz
     c.sigma_rphi = geometry.sigma_rphi
     c.sigma_z = geometry.sigma_z
+    c.sigma_r = geometry.sigma_r
     c.chi2_cut = chi2_cut
     c.mass = geometry.mass
     return c

@@ -125,7 +125,9 @@ __device__ __forceinline__ void rotate(float &s, float &c, float d)
 // 0 = known zero, 2 = known one, 1 = computed.  The transport below is
 // unrolled against this pattern so known zeros and ones cost nothing (the
 // paper's Matriplex generator does the same for its CPU kernels, Section 2.1).
-constexpr signed char kFpat[6][6] = {
+// To a cylinder the path depends on the transverse inputs; to a plane of
+// fixed z it depends on z and theta only, and z leaves with no variance.
+constexpr signed char kFpatCyl[6][6] = {
     {1, 1, 0, 1, 1, 0},
     {1, 1, 0, 1, 1, 0},
     {1, 1, 2, 1, 1, 1},
@@ -133,10 +135,21 @@ constexpr signed char kFpat[6][6] = {
     {1, 1, 0, 1, 1, 0},
     {0, 0, 0, 0, 0, 2},
 };
+constexpr signed char kFpatDisk[6][6] = {
+    {2, 0, 1, 1, 1, 1},
+    {0, 2, 1, 1, 1, 1},
+    {0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 2, 0, 0},
+    {0, 0, 1, 1, 2, 1},
+    {0, 0, 0, 0, 0, 2},
+};
 
-// C <- F C F^T on the packed covariance.
+// C <- F C F^T on the packed covariance, F of a cylinder (kDisk false) or a
+// disk crossing.
+template <bool kDisk>
 __device__ __forceinline__ void transport(const float (&F)[6][6], float (&c)[21])
 {
+    constexpr const signed char(&kFpat)[6][6] = kDisk ? kFpatDisk : kFpatCyl;
     float M[6][6];   // F C
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -326,16 +339,82 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
     return true;
 }
 
+// Propagate state p to the plane z = zd (an endcap disk): the transverse
+// path is fixed by the dip angle, s = (zd - z) tan(theta), and must be
+// positive (the helix heads towards the plane).  Same helix and outputs as
+// propagate(); the Jacobian's path term keeps z on the plane, so it depends
+// on z and theta only and the z row vanishes.
+__device__ __forceinline__ bool propagate_plane(const float (&p)[6], const Trig &tg, float zd, float w_per_qpt,
+                                                float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+{
+    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
+    const float sph = tg.sph, cph = tg.cph;
+    const float w = w_per_qpt * q;
+    const float ict = fast_rcp(tg.cth);
+    const float tanth = tg.sth * ict;
+    const float s = (zd - z) * tanth;
+    if (!(s > 0.f) || !(s < kInf)) return false;
+
+    const float a = w * s;
+    float S1, C1, S2, C2;
+    turn_terms(a, S1, C1, S2, C2);
+    const float A = fmaf(cph, S1, -sph * C1);
+    const float B = fmaf(cph, C1, sph * S1);
+    const float gx = fmaf(cph, S2, -sph * C2);
+    const float gy = fmaf(sph, S2, cph * C2);
+    const float ca = fmaf(-a, C1, 1.f), sa = a * S1;
+    const float cn = fmaf(cph, ca, -sph * sa), sn = fmaf(sph, ca, cph * sa);
+    o[0] = fmaf(s, A, x);
+    o[1] = fmaf(s, B, y);
+    o[2] = zd;
+    o[3] = q;
+    o[4] = wrap_pi(phi + a);
+    o[5] = p[5];
+    sn_out = sn;
+    cn_out = cn;
+
+    // derivatives at fixed path, plus d s / d(z, theta) = (-tan theta,
+    // s / (sin theta cos theta)) from z + s cot(theta) = zd
+    const float Pxq = s * s * gx * w_per_qpt, Pxp = -s * B;
+    const float Pyq = s * s * gy * w_per_qpt, Pyp = s * A;
+    const float Ppq = s * w_per_qpt;
+    const float dsz = -tanth;
+    const float dst = s * ict * fast_rcp(tg.sth);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) F[i][j] = 0.f;
+    F[0][0] = 1.f;
+    F[0][2] = cn * dsz;
+    F[0][3] = Pxq;
+    F[0][4] = Pxp;
+    F[0][5] = cn * dst;
+    F[1][1] = 1.f;
+    F[1][2] = sn * dsz;
+    F[1][3] = Pyq;
+    F[1][4] = Pyp;
+    F[1][5] = sn * dst;
+    F[3][3] = 1.f;
+    F[4][2] = w * dsz;
+    F[4][3] = Ppq;
+    F[4][4] = 1.f;
+    F[4][5] = w * dst;
+    F[5][5] = 1.f;
+    return true;
+}
+
 // Multiple scattering in a layer of x0 radiation lengths, crossed at the
-// state's position: Highland angle th0 with the path factor 1/|cos alpha|,
-// added to (q/pT, phi, theta) at fixed |p|.
-__device__ __forceinline__ void add_scattering(const float (&p)[6], const Trig &tg, float x0, float mass2,
-                                               float (&c)[21])
+// state's position: Highland angle th0 with the path factor 1/|cos alpha|
+// (alpha to the layer normal: radial on a cylinder, z on a disk), added to
+// (q/pT, phi, theta) at fixed |p|.
+__device__ __forceinline__ void add_scattering(const float (&p)[6], const Trig &tg, float x0, bool disk,
+                                               float mass2, float (&c)[21])
 {
     if (!(x0 > 0.f)) return;
     const float x = p[0], y = p[1], q = p[3];
     const float ir0 = __builtin_amdgcn_rsqf(fmaf(x, x, y * y));
-    const float cosa = fmaxf(fabsf(tg.sth * fmaf(tg.cph, x * ir0, tg.sph * y * ir0)), 1e-6f);
+    const float cosa = disk ? fmaxf(fabsf(tg.cth), 1e-6f)
+                            : fmaxf(fabsf(tg.sth * fmaf(tg.cph, x * ir0, tg.sph * y * ir0)), 1e-6f);
     const float t = x0 * fast_rcp(cosa);
     const float k = fabsf(q) * tg.sth;                                          // 1/|p|
     const float inv_bp = k * __builtin_amdgcn_sqrtf(fmaf(mass2 * k, k, 1.f));    // 1/(beta p)
@@ -365,22 +444,43 @@ __device__ __forceinline__ float hit_chi2(float x, float y, float z, float cxx, 
     return fmaf(szz * ru, ru, fmaf(-2.f * suz * ru, rz, suu * rz * rz)) * idet;
 }
 
+// chi2 of a disk hit (cos phi_h, sin phi_h, r_h) against a predicted state
+// on the disk's plane: residuals u along (-sin phi_h, cos phi_h) and v along
+// (cos phi_h, sin phi_h), S = H C H^T + diag(var_u, var_r).
+__device__ __forceinline__ float hit_chi2_disk(float x, float y, float cxx, float cxy, float cyy, float ch, float sh,
+                                               float rh, float var_u, float var_r)
+{
+    const float ru = fmaf(x, sh, -y * ch);
+    const float rv = rh - fmaf(x, ch, y * sh);
+    const float sc2 = 2.f * sh * ch;
+    const float ss = sh * sh, cc = ch * ch;
+    const float suu = fmaf(ss, cxx, fmaf(-sc2, cxy, fmaf(cc, cyy, var_u)));
+    const float svv = fmaf(cc, cxx, fmaf(sc2, cxy, fmaf(ss, cyy, var_r)));
+    const float suv = fmaf(0.5f * sc2, cyy - cxx, (cc - ss) * cxy);
+    const float idet = fast_rcp(fmaf(suu, svv, -suv * suv));
+    return fmaf(svv * ru, ru, fmaf(-2.f * suv * ru, rv, suu * rv * rv)) * idet;
+}
+
 // Kalman update with one hit.  K = C H^T S^-1, p += K r, C -= K (H C) on the
 // upper triangle (so C stays exactly symmetric).  Returns the hit's chi2.
+// The first measured coordinate is u along (-sin phi_h, cos phi_h, 0); the
+// second (value zh) is z on a cylinder, r along (cos phi_h, sin phi_h, 0) on
+// a disk (kDisk), with variance var_z.
+template <bool kDisk>
 __device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], Trig &tg, float ch, float sh, float zh,
                                            float var_u, float var_z)
 {
     const float ru = fmaf(p[0], sh, -p[1] * ch);
-    const float rz = zh - p[2];
+    const float rz = kDisk ? zh - fmaf(p[0], ch, p[1] * sh) : zh - p[2];
     float Mu[6], Mz[6];   // rows of H C
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         Mu[j] = fmaf(-sh, c[sym(0, j)], ch * c[sym(1, j)]);
-        Mz[j] = c[sym(2, j)];
+        Mz[j] = kDisk ? fmaf(ch, c[sym(0, j)], sh * c[sym(1, j)]) : c[sym(2, j)];
     }
     const float suu = fmaf(-sh, Mu[0], fmaf(ch, Mu[1], var_u));
-    const float suz = Mu[2];
-    const float szz = Mz[2] + var_z;
+    const float suz = kDisk ? fmaf(ch, Mu[0], sh * Mu[1]) : Mu[2];
+    const float szz = kDisk ? fmaf(ch, Mz[0], fmaf(sh, Mz[1], var_z)) : Mz[2] + var_z;
     const float idet = fast_rcp(fmaf(suu, szz, -suz * suz));
     const float i00 = szz * idet, i01 = -suz * idet, i11 = suu * idet;
     const float chi2 = fmaf(ru, fmaf(i00, ru, i01 * rz), rz * fmaf(i01, ru, i11 * rz));
@@ -410,20 +510,22 @@ __device__ __forceinline__ float kf_update(float (&p)[6], float (&c)[21], Trig &
 // Used where the prediction is much looser than the hit (a fit starting
 // from a wide prior): there C - K H C subtracts two nearly equal numbers and
 // loses FP32 digits, while the Joseph form only scales them by (I - K H).
+// Measured coordinates as in kf_update.
+template <bool kDisk>
 __device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21], Trig &tg, float ch, float sh,
                                                   float zh, float var_u, float var_z)
 {
     const float ru = fmaf(p[0], sh, -p[1] * ch);
-    const float rz = zh - p[2];
+    const float rz = kDisk ? zh - fmaf(p[0], ch, p[1] * sh) : zh - p[2];
     float Mu[6], Mz[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         Mu[j] = fmaf(-sh, c[sym(0, j)], ch * c[sym(1, j)]);
-        Mz[j] = c[sym(2, j)];
+        Mz[j] = kDisk ? fmaf(ch, c[sym(0, j)], sh * c[sym(1, j)]) : c[sym(2, j)];
     }
     const float suu = fmaf(-sh, Mu[0], fmaf(ch, Mu[1], var_u));
-    const float suz = Mu[2];
-    const float szz = Mz[2] + var_z;
+    const float suz = kDisk ? fmaf(ch, Mu[0], sh * Mu[1]) : Mu[2];
+    const float szz = kDisk ? fmaf(ch, Mz[0], fmaf(sh, Mz[1], var_z)) : Mz[2] + var_z;
     const float idet = 1.f / fmaf(suu, szz, -suz * suz);
     const float i00 = szz * idet, i01 = -suz * idet, i11 = suu * idet;
     const float chi2 = fmaf(ru, fmaf(i00, ru, i01 * rz), rz * fmaf(i01, ru, i11 * rz));
@@ -450,8 +552,8 @@ __device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21],
         float D[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) D[j] = c[sym(i, j)] - fmaf(K0[i], Mu[j], K1[i] * Mz[j]);
-        const float du = fmaf(-sh, D[0], ch * D[1]);   // (D H^T)_iu
-        const float dz = D[2];                         // (D H^T)_iz
+        const float du = fmaf(-sh, D[0], ch * D[1]);                    // (D H^T)_iu
+        const float dz = kDisk ? fmaf(ch, D[0], sh * D[1]) : D[2];      // (D H^T)_i2
 #pragma unroll
         for (int j = i; j < 6; ++j) {
             const float kvk = fmaf(var_u * K0[i], K0[j], var_z * K1[i] * K1[j]);

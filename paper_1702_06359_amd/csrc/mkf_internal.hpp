@@ -15,14 +15,18 @@ constexpr uint32_t kHoleId = 0xFFFFFFu;   // hit-id field of a hole or stopped e
 constexpr int kMaxHitsPerLayer = 0xFFFFFE;
 
 // Per-layer geometry and the hit-index grid, in FP32 as the kernels use it.
+// The grid's second coordinate is z on a cylinder and r on a disk.
 struct LayerParam {
-    float r;
+    float r;           // cylinder radius; disk outer radius
     float half_z;
     float x0;
     float inv_dphi;    // bins_phi / (2 pi)
-    float inv_dz;      // bins_z / (2 half_z)
+    float inv_dz;      // bins_z / extent of the second coordinate
     float inv_r;
-    float pad1, pad2;
+    float grid_lo;     // lower edge of the second coordinate: -half_z, or the disk's r_min
+    float zplane;      // disk plane
+    int kind;          // 0 cylinder, 1 disk
+    int pad[3];
 };
 
 // Building and fitting parameters for one launch.
@@ -35,14 +39,15 @@ struct Params {
     int hole_always;
     int bins_phi;
     int bins_z;
-    int pad;
+    int disks;           // 1: every layer is a disk, 0: every layer a cylinder
     float w_per_qpt;     // -kappa * B: curvature w = w_per_qpt * q/pT
     float var_u;         // sigma_rphi^2
     float var_z;         // sigma_z^2
     float chi2_cut;
     float mass2;         // scattering mass hypothesis squared
     float win_scale;     // (1 + window margin)
-    float pad1, pad2;
+    float var_r;         // sigma_r^2 (disks)
+    float pad2;
 };
 
 // Device view of one loaded event.  All pointers are device pointers.
@@ -53,8 +58,8 @@ struct DevEvent {
     int n_hits;                          // all layers
     int layer_off[kMaxLayers + 1];       // first hit of each layer in the flat hit arrays
     const double *raw_xyz;               // [n_hits][3] caller order
-    float4 *hits;                        // [n_hits] caller order: (cos phi_h, sin phi_h, z, 0)
-    float4 *binned;                      // [n_hits] grouped by layer then bin: (c, s, z, id bits)
+    float4 *hits;                        // [n_hits] caller order: (cos phi_h, sin phi_h, z or r, 0)
+    float4 *binned;                      // [n_hits] grouped by layer then bin: (c, s, z or r, id bits)
     int *bin_of;                         // [n_hits] bin of each caller-order hit
     int *bin_rank;                       // [n_hits] position of the hit inside its bin
     int *bin_count;                      // [n_layers][n_bins] counts (zero between index builds)

@@ -96,22 +96,24 @@ __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_sta
 
 // ---------------------------------------------------------------------------
 // Hit index: per layer, hits are grouped by an (eta, phi) grid.  On a cylinder
-// eta is a function of z, so the grid is (z, phi): bin = iz * bins_phi + iphi.
-// A counting sort over all events of a batch at once.
+// eta is a function of z, on a disk a function of r, so the grid is (z, phi)
+// or (r, phi): bin = iz * bins_phi + iphi.  A counting sort over all events
+// of a batch at once.
 
-// A caller-order hit as (cos phi, sin phi, z, 0) and its (z row, phi) bin.
+// A caller-order hit as (cos phi, sin phi, z or r, 0) and its (row, phi) bin.
 __device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const double *xyz, float4 *out)
 {
     const double x = xyz[0], y = xyz[1];
-    const double ir = 1.0 / sqrt(x * x + y * y);
+    const double rr = sqrt(x * x + y * y);
+    const double ir = 1.0 / rr;
     const float c = (float)(x * ir), s = (float)(y * ir);
-    const float z = (float)xyz[2];
+    const float g2 = lp.kind ? (float)rr : (float)xyz[2];
     const float phi = atan2f(s, c);
     int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
-    int iz = (int)floorf((z + lp.half_z) * lp.inv_dz);
+    int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
     ip = min(max(ip, 0), P.bins_phi - 1);
     iz = min(max(iz, 0), P.bins_z - 1);
-    *out = make_float4(c, s, z, 0.f);
+    *out = make_float4(c, s, g2, 0.f);
     return iz * P.bins_phi + ip;
 }
 
@@ -456,7 +458,7 @@ __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
     return s - x;
 }
 
-template <int K, bool kStats>
+template <int K, bool kStats, bool kDisk>
 struct WaveSearch {
     SearchLds &W;
     const float4 *bh;
@@ -534,8 +536,9 @@ struct WaveSearch {
                     cnt.scan++;
                     if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd) cnt.chi2++;
                 }
-                const float c2 = hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z, P.var_u,
-                                          P.var_z);
+                const float c2 = kDisk ? hit_chi2_disk(a.x, a.y, b.x, b.y, b.z, hv.x, hv.y, hv.z, P.var_u, P.var_r)
+                                       : hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z,
+                                                  P.var_u, P.var_z);
                 ok = fwd & (c2 < P.chi2_cut);
                 tot = a.w + c2;
                 hid = (unsigned)__float_as_int(hv.w);
@@ -574,31 +577,42 @@ struct WaveSearch {
 // with `predicted` set: the best K accepted hits of the lane in (lc, lid),
 // sorted by accumulated chi2 then hit id; returns the lane's accepted count.
 // All lanes of the wavefront must call it together.
-template <int K, bool kStats>
+template <int K, bool kStats, bool kDisk>
 __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], float chi2, bool predicted,
                                             int L, const LayerParam &lp, const Params &P, const DevEvent &E,
                                             int lane, SearchLds &W, unsigned long long (&lk)[K], Count &cnt)
 {
     int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
-    float du = 0.f, dz = 0.f;
+    float du = 0.f, dz = 0.f, g2 = pp[2];
     if (predicted) {
-        // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
-        // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
         const float cxx = pc[sym(0, 0)], cxy = pc[sym(0, 1)], cyy = pc[sym(1, 1)];
         const float hd = 0.5f * (cxx - cyy);
         const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
-        du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
-        dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
+        float xr;
+        if (!kDisk) {
+            // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
+            // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
+            du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
+            dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
+            xr = du * lp.inv_r;
+        } else {
+            // on a disk the hit lies within distance du of the predicted
+            // point: S <= lambda_max(C_xy) + max(V_u, V_r) in every direction;
+            // the grid's second coordinate is the predicted radius +- du
+            du = sqrtf(P.chi2_cut * (lmax + fmaxf(P.var_u, P.var_r))) * P.win_scale;
+            dz = du;
+            g2 = sqrtf(fmaf(pp[0], pp[0], pp[1] * pp[1]));
+            xr = du * fast_rcp(g2);
+        }
         const float phipos = fast_atan2(pp[1], pp[0]);
         // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
-        const float xr = du * lp.inv_r;
-        const float dphi = (xr >= 0.7f ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
+        const float dphi = (xr >= 0.7f || !(xr >= 0.f) ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
         const int nphi = P.bins_phi;
-        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(pp[2])) {
+        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(g2)) {
             const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
             const int ihi = (int)floorf((phipos + dphi + kPi) * lp.inv_dphi);
-            izlo = min(max((int)floorf((pp[2] - dz - 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
-            const int izhi = min(max((int)floorf((pp[2] + dz + 1e-4f + lp.half_z) * lp.inv_dz), 0), P.bins_z - 1);
+            izlo = min(max((int)floorf((g2 - dz - 1e-4f - lp.grid_lo) * lp.inv_dz), 0), P.bins_z - 1);
+            const int izhi = min(max((int)floorf((g2 + dz + 1e-4f - lp.grid_lo) * lp.inv_dz), 0), P.bins_z - 1);
             n_rows = izhi - izlo + 1;
             if (ihi - ilo + 1 >= nphi) {
                 s0lo = 0;
@@ -621,12 +635,12 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
             }
         }
     }
-    W.own[0][lane] = make_float4(pp[0], pp[1], pp[2], chi2);
+    W.own[0][lane] = make_float4(pp[0], pp[1], g2, chi2);
     W.own[1][lane] = make_float4(pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(0, 2)]);
     W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
     W.head[lane] = kEnd;
 
-    WaveSearch<K, kStats> ws{W, E.binned, P, lane, lk, cnt};
+    WaveSearch<K, kStats, kDisk> ws{W, E.binned, P, lane, lk, cnt};
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * (P.bins_phi * P.bins_z + 1);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
@@ -674,7 +688,7 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
 // One building layer for every lane of a wavefront (Section 2: propagate the
 // candidate to the next layer, collect compatible hits, branch; Section
 // 3.2.1: re-rank and prune to max_cands per seed).
-template <int G, bool kStats>
+template <int G, bool kStats, bool kDisk>
 __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
                                            const int lane, const Hist &H, SearchLds &W, Count &cnt)
 {
@@ -690,11 +704,12 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     bool predicted = false;
     if (active) {
         float np[6], F[6][6], sn, cn;
-        const bool ok = propagate(S.p, S.tg, lp.r, P.w_per_qpt, np, F, sn, cn);
+        const bool ok = kDisk ? propagate_plane(S.p, S.tg, lp.zplane, P.w_per_qpt, np, F, sn, cn)
+                              : propagate(S.p, S.tg, lp.r, P.w_per_qpt, np, F, sn, cn);
         if (kStats) cnt.prop++;
         if (ok) {
-            add_scattering(S.p, S.tg, P.layer[L - 1].x0, P.mass2, S.c);
-            transport(F, S.c);
+            add_scattering(S.p, S.tg, P.layer[L - 1].x0, kDisk, P.mass2, S.c);
+            transport<kDisk>(F, S.c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) S.p[i] = np[i];
             S.tg.sph = sn;
@@ -712,7 +727,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     unsigned long long lk[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) lk[i] = ~0ull;
-    const int nacc = search_layer<K, kStats>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
+    const int nacc = search_layer<K, kStats, kDisk>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
     if (kStats) cnt.acc += nacc;
 
     // 3. hole child, or stop on this surface (with the prediction as state)
@@ -773,7 +788,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     S.stopped = p_stopped;
     S.status = p_status;
     if (with_hit) {
-        kf_update(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+        kf_update<kDisk>(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
         if (kStats) cnt.upd++;
         H.put(L, lane, (int)hid, parent);
     } else {
@@ -834,7 +849,7 @@ __host__ __device__ constexpr int search_lds_offset(int waves, int n_layers)
 // Batched builder.  Each wavefront takes work items (event, group of 64/G
 // seeds) - from a device counter when persistent, else from its block index -
 // and runs every building layer of its seeds with the state in registers.
-template <int G, bool kStats>
+template <int G, bool kStats, bool kDisk>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_batch(const Params P, const BatchArgs B, int persistent)
 {
     extern __shared__ int s_dyn[];
@@ -861,7 +876,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         Lane S;
         init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
         Count cnt;
-        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats>(S, L, P, E, lane, H, SL, cnt);
+        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats, kDisk>(S, L, P, E, lane, H, SL, cnt);
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
         flush_counts<kStats>(cnt, E, lane);
         if (!persistent) break;
@@ -870,7 +885,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // Per-layer builder: one event, one layer per launch, candidate state in
 // device memory (structure of arrays, slot = seed * G + rank) between layers.
-template <int G, bool kStats>
+template <int G, bool kStats, bool kDisk>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
 {
     const DevEvent &E = *Ep;
@@ -906,7 +921,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     extern __shared__ int s_dyn[];
     SearchLds &SL = reinterpret_cast<SearchLds *>(s_dyn)[threadIdx.x >> 6];
     Count cnt;
-    layer_step<G, kStats>(S, L, P, E, lane, H, SL, cnt);
+    layer_step<G, kStats, kDisk>(S, L, P, E, lane, H, SL, cnt);
     if (L == P.n_layers - 1) {
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
     } else {
@@ -931,7 +946,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // layer the scattering of the previous one, propagation, transport, and the
 // update with that layer's hit if it has one (hit_of(L) >= 0).  (op, oc) is
 // the state after the last update.
-template <class HitOf>
+template <bool kDisk, class HitOf>
 __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, float (&p)[6], float (&c)[21],
                                           HitOf hit_of, float (&op)[6], float (&oc)[21], float &chi2, int &nupd,
                                           int &status)
@@ -947,14 +962,15 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
     for (int L = 0; L < P.n_layers; ++L) {
         if (L > 0) {
             float np[6], F[6][6], sn, cn;
-            if (!propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn)) {
+            if (!(kDisk ? propagate_plane(p, tg, P.layer[L].zplane, P.w_per_qpt, np, F, sn, cn)
+                        : propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn))) {
                 status = 2;
                 break;
             }
-            add_scattering(p, tg, P.layer[L - 1].x0, P.mass2, c);
+            add_scattering(p, tg, P.layer[L - 1].x0, kDisk, P.mass2, c);
             tg.sph = sn;
             tg.cph = cn;
-            transport(F, c);
+            transport<kDisk>(F, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
@@ -963,7 +979,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
             const float4 hv = load_global(E.hits + E.layer_off[L] + h);
             // Joseph form: a fit starts from a wide prior, where the plain
             // form C - K H C would lose FP32 digits
-            chi2 += kf_update_joseph(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_z);
+            chi2 += kf_update_joseph<kDisk>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
             ++nupd;
 #pragma unroll
             for (int i = 0; i < 6; ++i) op[i] = p[i];
@@ -974,6 +990,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
 }
 
 // Fit with known hits: one lane per track, no branching beyond skipped layers.
+template <bool kDisk>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -987,8 +1004,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int i = 0; i < 6; ++i) p[i] = (float)load_global(E.track_par + 6 * t + i);
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = (float)load_global(E.track_cov + 21 * t + i);
-    fit_track(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc, chi2,
-              nupd, status);
+    fit_track<kDisk>(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc,
+                     chi2, nupd, status);
 #pragma unroll
     for (int i = 0; i < 6; ++i) store_global(E.fit_par + 6 * t + i, (double)op[i]);
 #pragma unroll
@@ -1002,8 +1019,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // layers 0, 1 and 2 (the transverse circle through the three points; z
 // linear in the arc length), at the first hit, with a loose diagonal
 // covariance in the frame (u, z, q/pT, phi, theta) of the layer tangent at
-// that hit: sigma = (1 cm, 10 cm, 1 / GeV, 0.1, 0.1).  Computed in double
-// from the caller's coordinates; false without three usable points.
+// that hit, (u, r, q/pT, phi, theta) on a disk: sigma = (1 cm, 10 cm,
+// 1 / GeV, 0.1, 0.1).  Computed in double from the caller's coordinates;
+// false without three usable points.
+template <bool kDisk>
 __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params &P, const int *hits, float (&p)[6],
                                                 float (&c)[21])
 {
@@ -1042,10 +1061,16 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
     const double sa = sin(a), ca = cos(a);
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = 0.f;
-    c[sym(0, 0)] = (float)(sa * sa);
-    c[sym(0, 1)] = (float)(-sa * ca);
-    c[sym(1, 1)] = (float)(ca * ca);
-    c[sym(2, 2)] = 100.f;
+    if (!kDisk) {
+        c[sym(0, 0)] = (float)(sa * sa);
+        c[sym(0, 1)] = (float)(-sa * ca);
+        c[sym(1, 1)] = (float)(ca * ca);
+        c[sym(2, 2)] = 100.f;
+    } else {
+        c[sym(0, 0)] = (float)(sa * sa + 100.0 * ca * ca);
+        c[sym(0, 1)] = (float)(99.0 * sa * ca);
+        c[sym(1, 1)] = (float)(ca * ca + 100.0 * sa * sa);
+    }
     c[sym(3, 3)] = 1.f;
     c[sym(4, 4)] = 0.01f;
     c[sym(5, 5)] = 0.01f;
@@ -1054,6 +1079,7 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
 
 // Final fit of every built track of a batch (after the build): one lane per
 // seed, hits from the build's output.
+template <bool kDisk>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_refit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1064,8 +1090,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int *hits = E.out_hits + t * P.n_layers;
     float p[6], c[21], op[6], oc[21], chi2 = 0.f;
     int nupd = 0, status = 3;
-    if (final_fit_prior(E, P, hits, p, c))
-        fit_track(P, E, p, c, [&](int L) { return load_global(hits + L); }, op, oc, chi2, nupd, status);
+    if (final_fit_prior<kDisk>(E, P, hits, p, c))
+        fit_track<kDisk>(P, E, p, c, [&](int L) { return load_global(hits + L); }, op, oc, chi2, nupd, status);
     else {
 #pragma unroll
         for (int i = 0; i < 6; ++i) op[i] = 0.f;
@@ -1182,7 +1208,8 @@ static hipError_t launch_batch_t(const Params &p, const BatchArgs &b, int wpb, i
     const size_t lds = sizeof(int) * (size_t)search_lds_offset(wpb, p.n_layers) + wpb * sizeof(SearchLds);
     const unsigned grid = persistent ? (unsigned)n_blocks : blocks_for(b.total_items, wpb);
     if (grid == 0) return hipSuccess;
-    k_build_batch<G, kStats><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
+    if (p.disks) k_build_batch<G, kStats, true><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
+    else k_build_batch<G, kStats, false><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
     return hipGetLastError();
 }
 
@@ -1210,7 +1237,8 @@ static hipError_t launch_layer_t(const Params &p, const DevEvent *ev_dev, int n_
     const int items = (n_seeds + kWave / G - 1) / (kWave / G);
     const unsigned grid = blocks_for(items, wpb);
     if (grid == 0) return hipSuccess;
-    k_build_layer<G, kStats><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
+    if (p.disks) k_build_layer<G, kStats, true><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
+    else k_build_layer<G, kStats, false><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
     return hipGetLastError();
 }
 
@@ -1235,14 +1263,16 @@ hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const Dev
 hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_seeds <= 0) return hipSuccess;
-    k_refit<<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
+    if (p.disks) k_refit<true><<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
+    else k_refit<false><<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
     return hipGetLastError();
 }
 
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_tracks <= 0) return hipSuccess;
-    k_fit<<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
+    if (p.disks) k_fit<true><<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
+    else k_fit<false><<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
     return hipGetLastError();
 }
 

@@ -183,23 +183,34 @@ void derive_params(mkf_ctx *ctx)
     const mkf_tuning &t = ctx->tuning;
     std::memset(&P, 0, sizeof(P));
     for (int L = 0; L < c.n_layers; ++L) {
-        P.layer[L].r = (float)c.layer_r[L];
-        P.layer[L].half_z = (float)c.layer_half_z[L];
-        P.layer[L].x0 = (float)c.layer_x0[L];
-        P.layer[L].inv_dphi = (float)(t.bins_phi / (2.0 * M_PI));
-        P.layer[L].inv_dz = (float)(t.bins_z / (2.0 * c.layer_half_z[L]));
-        P.layer[L].inv_r = (float)(1.0 / c.layer_r[L]);
+        LayerParam &lp = P.layer[L];
+        lp.r = (float)c.layer_r[L];
+        lp.x0 = (float)c.layer_x0[L];
+        lp.inv_dphi = (float)(t.bins_phi / (2.0 * M_PI));
+        lp.inv_r = (float)(1.0 / c.layer_r[L]);
+        lp.kind = c.layer_kind[L];
+        if (lp.kind == 0) {
+            lp.half_z = (float)c.layer_half_z[L];
+            lp.inv_dz = (float)(t.bins_z / (2.0 * c.layer_half_z[L]));
+            lp.grid_lo = -lp.half_z;
+        } else {
+            lp.zplane = (float)c.layer_z[L];
+            lp.inv_dz = (float)(t.bins_z / (c.layer_r[L] - c.layer_rmin[L]));
+            lp.grid_lo = (float)c.layer_rmin[L];
+        }
     }
     P.n_layers = c.n_layers;
     P.n_seed_layers = c.n_seed_layers;
     P.max_cands = c.max_cands;
     P.max_holes = c.max_holes;
     P.hole_always = (c.flags & MKF_HOLE_ALWAYS) ? 1 : 0;
+    P.disks = c.layer_kind[0] == 1 ? 1 : 0;
     P.bins_phi = t.bins_phi;
     P.bins_z = t.bins_z;
     P.w_per_qpt = (float)(-0.00299792458 * c.bz);
     P.var_u = (float)(c.sigma_rphi * c.sigma_rphi);
     P.var_z = (float)(c.sigma_z * c.sigma_z);
+    P.var_r = (float)(c.sigma_r * c.sigma_r);
     P.chi2_cut = (float)c.chi2_cut;
     P.mass2 = (float)(c.mass * c.mass);
     P.win_scale = 1.05f;
@@ -213,13 +224,30 @@ mkf_status check_config(const mkf_config *c)
     if (c->max_cands < 1 || c->max_cands > kMaxCands) return fail(MKF_E_INVALID, "max_cands must be 1..%d", kMaxCands);
     if (c->max_holes < 0 || c->max_holes > 7) return fail(MKF_E_INVALID, "max_holes must be 0..7");
     if (c->flags & ~MKF_HOLE_ALWAYS) return fail(MKF_E_INVALID, "unknown config flags");
+    bool any_disk = false;
     for (int L = 0; L < c->n_layers; ++L) {
-        if (!(c->layer_r[L] > 0) || !std::isfinite(c->layer_r[L]) || (L > 0 && !(c->layer_r[L] > c->layer_r[L - 1])))
-            return fail(MKF_E_INVALID, "layer radii must be positive and increasing");
-        if (!(c->layer_half_z[L] > 0) || !std::isfinite(c->layer_half_z[L]))
-            return fail(MKF_E_INVALID, "layer_half_z must be positive");
+        const int kind = c->layer_kind[L];
+        if (kind != 0 && kind != 1) return fail(MKF_E_INVALID, "layer_kind must be 0 (cylinder) or 1 (disk)");
+        if (!(c->layer_r[L] > 0) || !std::isfinite(c->layer_r[L])) return fail(MKF_E_INVALID, "layer_r must be positive");
+        if (kind == 0) {
+            if (L > 0 && c->layer_kind[L - 1] == 0 && !(c->layer_r[L] > c->layer_r[L - 1]))
+                return fail(MKF_E_INVALID, "consecutive cylinder radii must increase");
+            if (!(c->layer_half_z[L] > 0) || !std::isfinite(c->layer_half_z[L]))
+                return fail(MKF_E_INVALID, "layer_half_z must be positive");
+        } else {
+            any_disk = true;
+            if (!std::isfinite(c->layer_z[L]) || c->layer_z[L] == 0.0)
+                return fail(MKF_E_INVALID, "a disk needs a finite nonzero layer_z");
+            if (!(c->layer_rmin[L] >= 0) || !(c->layer_rmin[L] < c->layer_r[L]))
+                return fail(MKF_E_INVALID, "a disk needs 0 <= layer_rmin < layer_r");
+        }
         if (!(c->layer_x0[L] >= 0) || !std::isfinite(c->layer_x0[L])) return fail(MKF_E_INVALID, "layer_x0 must be >= 0");
     }
+    if (any_disk && (!(c->sigma_r > 0) || !std::isfinite(c->sigma_r)))
+        return fail(MKF_E_INVALID, "sigma_r must be positive when a disk exists");
+    for (int L = 1; L < c->n_layers; ++L)
+        if (c->layer_kind[L] != c->layer_kind[0])
+            return fail(MKF_E_INVALID, "layers must be all cylinders or all disks (mixed lists are not supported)");
     if (!std::isfinite(c->bz)) return fail(MKF_E_INVALID, "bz must be finite");
     if (!(c->sigma_rphi > 0) || !(c->sigma_z > 0) || !std::isfinite(c->sigma_rphi) || !std::isfinite(c->sigma_z))
         return fail(MKF_E_INVALID, "hit resolutions must be positive");

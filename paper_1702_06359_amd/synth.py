@@ -403,6 +403,14 @@ def ckf_events(n_events: int = 10, n_tracks: int = 20000, noise: float = 0.10, f
     return [make_event(n_tracks, cfg=1, event=first + e, noise=noise) for e in range(n_events)]
 
 
+def endcap_events(n_events: int = 10, n_tracks: int = 10000, noise: float = 0.10, first: int = 0):
+    """Events of the endcap workload: ten disks, 1.6 < eta < 2.6, 10 % noise
+    hits per disk.  10,000 tracks per event carry the particle density per
+    unit of eta of the 20,000-track barrel workload (|eta| < 1)."""
+    g = Geometry.endcap()
+    return [make_event(n_tracks, cfg=3, event=first + e, noise=noise, geometry=g) for e in range(n_events)]
+
+
 def fit_batch_sizes(n_batches: int = 64, total: int = 1_000_000, lo: int = 2000, hi: int = 30000,
                     seed: int = 0) -> np.ndarray:
     """Uneven batch sizes in [lo, hi] summing exactly to total."""

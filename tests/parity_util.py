@@ -22,14 +22,20 @@ with open(os.path.join(HERE, "tolerances.json")) as _f:
     TOL = json.load(_f)
 
 
-def local_frame(phi_pos):
+def local_frame(phi_pos, disk=False):
+    """Columns: u along the layer at azimuth phi_pos, then z (cylinder) or r
+    (disk, whose plane fixes z), q/pT, phi, theta."""
     G = np.zeros((6, 5))
     G[0, 0], G[1, 0] = -math.sin(phi_pos), math.cos(phi_pos)
-    G[2, 1] = G[3, 2] = G[4, 3] = G[5, 4] = 1.0
+    if disk:
+        G[0, 1], G[1, 1] = math.cos(phi_pos), math.sin(phi_pos)
+    else:
+        G[2, 1] = 1.0
+    G[3, 2] = G[4, 3] = G[5, 4] = 1.0
     return G
 
 
-def state_errors(par_g, cov_g, par_o, cov_o):
+def state_errors(par_g, cov_g, par_o, cov_o, disk=False):
     """Per-track max |dp|/sigma on the 5-D local frame and max relative
     difference of the local covariance diagonal (oracle as reference)."""
     n = par_o.shape[0]
@@ -38,7 +44,7 @@ def state_errors(par_g, cov_g, par_o, cov_o):
     Cg = synth.unpack_sym(cov_g)
     Co = synth.unpack_sym(cov_o)
     for i in range(n):
-        G = local_frame(math.atan2(par_o[i, 1], par_o[i, 0]))
+        G = local_frame(math.atan2(par_o[i, 1], par_o[i, 0]), disk)
         d = par_g[i] - par_o[i]
         d[4] = (d[4] + np.pi) % (2 * np.pi) - np.pi
         so = np.diag(G.T @ Co[i] @ G)
@@ -66,7 +72,8 @@ def compare_build(gpu, orc, cfg, hits, seed_par, seed_cov, rows=None, tol=None):
     rep["status_mismatch"] = int((gpu["status"][rows][s] != orc["status"][s]).sum())
     rep["nhits_mismatch"] = int((gpu["n_hits"][rows][s] != orc["n_hits"][s]).sum())
     rep["nholes_mismatch"] = int((gpu["n_holes"][rows][s] != orc["n_holes"][s]).sum())
-    dpar, dcov = state_errors(gpu["par"][rows][s], gpu["cov"][rows][s], orc["par"][s], orc["cov"][s])
+    dpar, dcov = state_errors(gpu["par"][rows][s], gpu["cov"][rows][s], orc["par"][s], orc["cov"][s],
+                              disk=bool(cfg.kind[0]))
     dchi = np.abs(gpu["chi2"][rows][s] - orc["chi2"][s]) / (1.0 + orc["chi2"][s])
     rep["max_dpar_sigma"] = float(dpar.max()) if dpar.size else 0.0
     rep["max_dcov_rel"] = float(dcov.max()) if dcov.size else 0.0

@@ -29,7 +29,7 @@ def _fit_both(ctx, ev, hits_assign, prior_par=None, prior_cov=None):
     return g, o
 
 
-def _check(name, g, o, tol=None, prior_cov=None):
+def _check(name, g, o, tol=None, prior_cov=None, disk=False):
     """Element-wise parity.  With prior_cov, each covariance component's
     tolerance is max(tau_cov_rel, f R 2^-24), R = prior variance / final
     variance in the local frame (the conditioning of that track's fit)."""
@@ -37,13 +37,13 @@ def _check(name, g, o, tol=None, prior_cov=None):
     assert (g["status"] == o["status"]).all()
     ok = o["status"] == 0
     assert (g["ndof"][ok] == o["ndof"][ok]).all()
-    dpar, dcov = state_errors(g["par"][ok], g["cov"][ok], o["par"][ok], o["cov"][ok])
+    dpar, dcov = state_errors(g["par"][ok], g["cov"][ok], o["par"][ok], o["cov"][ok], disk)
     dchi = np.abs(g["chi2"][ok] - o["chi2"][ok]) / (1.0 + o["chi2"][ok])
     cov_tol = np.full(int(ok.sum()), tol["tau_cov_rel"])
     chi_tol = np.full(int(ok.sum()), tol["eps_chi2_rel"])
     if prior_cov is not None:
         # each chi2 term is r^2/S with S built from that covariance
-        R = conditioning(prior_cov[ok], o["par"][ok], o["cov"][ok])
+        R = conditioning(prior_cov[ok], o["par"][ok], o["cov"][ok], disk)
         cov_tol = np.maximum(cov_tol, tol["cov_conditioning_factor"] * R * 2.0 ** -24)
         chi_tol = np.maximum(chi_tol, tol["cov_conditioning_factor"] * R * 2.0 ** -24)
     rep = dict(n=int(ok.sum()), max_dpar_sigma=dpar.max(), p9999_dpar_sigma=np.quantile(dpar, 0.9999),
@@ -57,13 +57,13 @@ def _check(name, g, o, tol=None, prior_cov=None):
     assert rep["max_dchi2_over_tol"] <= 1.0, rep
 
 
-def conditioning(prior_cov, par, cov):
+def conditioning(prior_cov, par, cov, disk=False):
     """Per track, max over the local components of prior variance / final variance."""
     Cp = synth.unpack_sym(prior_cov)
     Cf = synth.unpack_sym(cov)
     R = np.zeros(par.shape[0])
     for i in range(par.shape[0]):
-        G = local_frame(np.arctan2(par[i, 1], par[i, 0]))
+        G = local_frame(np.arctan2(par[i, 1], par[i, 0]), disk)
         R[i] = np.max(np.diag(G.T @ Cp[i] @ G) / np.diag(G.T @ Cf[i] @ G))
     return R
 
