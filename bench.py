@@ -7,9 +7,9 @@ A step = hit-index build for every event + the batched build.  Prints one
 JSON line with throughput, the roofline of the build kernel, the CPU oracle
 baseline and serving latencies.
 
-Other workloads (--workload): fit (1,000,000 tracks in 64 uneven batches),
-batched (256 uneven events, batched vs plain builder), serve (Poisson
-arrivals, p50/p99 latency).
+Other workloads (--workload): endcap (10 events x 10,000 tracks on ten
+disks), fit (1,000,000 tracks in 64 uneven batches), batched (256 uneven
+events, batched vs plain builder), serve (Poisson arrivals, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -76,9 +76,9 @@ def gpu_count_guard(n):
         sys.exit(2)
 
 
-def make_ctx(k, tuning=None):
+def make_ctx(k, tuning=None, geometry=None):
     from paper_1702_06359_amd import abi, synth
-    ctx = abi.Context(abi.config_from_geometry(synth.Geometry(), max_cands=k))
+    ctx = abi.Context(abi.config_from_geometry(geometry or synth.Geometry(), max_cands=k))
     if tuning:
         ctx.set_tuning(**tuning)
     return ctx
@@ -223,6 +223,8 @@ def workload_ckf(args):
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:
+        log("endcap workload")
+        result["endcap"] = endcap_leg(args)
         log("serving latency run")
         pool_sizes = synth.loguniform_sizes(16, 500, 50000, cfg=4)
         pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(pool_sizes)]
@@ -242,6 +244,44 @@ def workload_ckf(args):
         result["cpu_baseline"] = cpu_baseline_build(evs[0], k, args.cpu_seconds)
     ctx.close()
     return result
+
+
+def endcap_leg(args, steps=None):
+    """The same step on the endcap workload: 10 events x 10,000 tracks on ten
+    disks (1.6 < eta < 2.6), 10 % noise, k = 6."""
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    evs = synth.endcap_events(10, 10000, 0.10)
+    ctx = make_ctx(6, args.tuning, geometry=synth.Geometry.endcap())
+    handles = [ctx.load_event(e) for e in evs]
+
+    def step():
+        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC)
+
+    def sync():
+        ctx.sync()
+        torch.cuda.synchronize()
+    n = steps or args.steps
+    step()
+    sync()
+    ctx.timer_reset()
+    elapsed = time_steps(step, n, 0, sync)
+    build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
+    ctx.close()
+    tracks = sum(e.n_seeds for e in evs)
+    return {"workload": "combinatorial KF building, 10 events x 10,000 tracks, 10-disk endcap "
+                        "(z = 30..120 cm, 1.6 < eta < 2.6), 10% noise hits, k=6, chi2<30, 1 hole",
+            "tracks_per_s": round(tracks * n / elapsed, 1), "ms_per_step": round(elapsed / n * 1e3, 4),
+            "build_kernel_ms": round(build_ms / max(build_n, 1), 4)}
+
+
+def workload_endcap(args):
+    r = endcap_leg(args)
+    return {"metric": "tracks built/sec (endcap disks, combinatorial KF)", "value": r["tracks_per_s"],
+            "unit": "tracks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic", "config": {"workload": r["workload"]},
+            "build_kernel_ms": r["build_kernel_ms"]}
 
 
 def workload_fit(args):
@@ -408,7 +448,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ckf", choices=["ckf", "fit", "batched", "serve", "calib"])
+    ap.add_argument("--workload", default="ckf", choices=["ckf", "endcap", "fit", "batched", "serve", "calib"])
     ap.add_argument("--serve-events", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--quick", action="store_true", help="headline number only (profiling runs)")
@@ -417,8 +457,8 @@ def main():
     args = ap.parse_args()
     gpu_count_guard(args.gpus)
     args.tuning = None
-    res = {"ckf": workload_ckf, "fit": workload_fit, "batched": workload_batched, "serve": workload_serve,
-           "calib": workload_calib}[args.workload](args)
+    res = {"ckf": workload_ckf, "endcap": workload_endcap, "fit": workload_fit, "batched": workload_batched,
+           "serve": workload_serve, "calib": workload_calib}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

@@ -596,13 +596,28 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
             dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
             xr = du * lp.inv_r;
         } else {
-            // on a disk the hit lies within distance du of the predicted
-            // point: S <= lambda_max(C_xy) + max(V_u, V_r) in every direction;
-            // the grid's second coordinate is the predicted radius +- du
-            du = sqrtf(P.chi2_cut * (lmax + fmaxf(P.var_u, P.var_r))) * P.win_scale;
-            dz = du;
+            // On a disk the position covariance has a radial part too.  Any
+            // hit with chi2 < cut lies within d0 = sqrt(cut (lmax + max V))
+            // of the predicted point, so its azimuth is within a0 = asin(d0 /
+            // rp) of the prediction's.  The hit frame is the prediction's
+            // (u_p, r_p) turned by that angle a, so sqrt(u_h^T C u_h) <=
+            // sqrt(C_uu) + |a| sqrt(lmax) (likewise for r), which bounds
+            // each residual separately: |rp sin a| <= du and
+            // |r_h - rp cos a| <= dr.
             g2 = sqrtf(fmaf(pp[0], pp[0], pp[1] * pp[1]));
-            xr = du * fast_rcp(g2);
+            const float irp = fast_rcp(g2);
+            const float cp = pp[0] * irp, sp = pp[1] * irp;
+            const float cuu = fmaf(sp * sp, cxx, fmaf(-2.f * sp * cp, cxy, cp * cp * cyy));
+            const float crr = fmaf(cp * cp, cxx, fmaf(2.f * sp * cp, cxy, sp * sp * cyy));
+            const float d0 = sqrtf(P.chi2_cut * (lmax + fmaxf(P.var_u, P.var_r))) * P.win_scale;
+            const float x0 = d0 * irp;
+            const float a0 = x0 >= 0.7f ? 0.5f * kPi : x0 * __builtin_amdgcn_rsqf(1.f - x0 * x0);
+            const float sl = a0 * sqrtf(lmax);
+            const float su = sqrtf(fmaxf(cuu, 0.f)) + sl, sr = sqrtf(fmaxf(crr, 0.f)) + sl;
+            du = sqrtf(P.chi2_cut * fmaf(su, su, P.var_u)) * P.win_scale;
+            // rp (1 - cos a) <= du^2 / rp for the low edge of the radius range
+            dz = fmaf(du * du, irp, sqrtf(P.chi2_cut * fmaf(sr, sr, P.var_r)) * P.win_scale);
+            xr = du * irp;
         }
         const float phipos = fast_atan2(pp[1], pp[0]);
         // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
