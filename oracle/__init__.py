@@ -30,6 +30,7 @@ class OrcConfig(C.Structure):
         ("bz", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double),
         ("chi2_cut", C.c_double), ("mass", C.c_double),
         ("kind", C.c_int32 * MAX_LAYERS), ("zplane", C.c_double * MAX_LAYERS), ("sigma_r", C.c_double),
+        ("thick", C.c_double * MAX_LAYERS),
     ]
 
 
@@ -84,6 +85,8 @@ def lib():
         L.orc_propagate.restype = C.c_int
         L.orc_propagate_plane.argtypes = [dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_propagate_plane.restype = C.c_int
+        L.orc_step_near.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_step_near.restype = C.c_int
         L.orc_add_ms.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp]
         L.orc_chi2.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double]
         L.orc_chi2.restype = C.c_double
@@ -131,6 +134,7 @@ def config(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n_seed_layers=3
         if geometry.is_disk:
             c.kind[i] = 1
             c.zplane[i] = geometry.disk_z[i]
+        c.thick[i] = geometry.thick(i)
     c.bz = geometry.bz
     c.sigma_rphi = geometry.sigma_rphi
     c.sigma_z = geometry.sigma_z
@@ -175,6 +179,18 @@ def propagate_plane(par, zd, bz, jacobian=True):
     rc = lib().orc_propagate_plane(_dp(p), float(zd), float(bz), _dp(out),
                                    _dp(F) if F is not None else None, C.byref(s), C.byref(m))
     return rc == 0, out, (F.reshape(6, 6) if F is not None else None), s.value, m.value
+
+
+def step_near(par, kind, where, bz, jacobian=True):
+    """Nearest crossing (either direction) of r = where (kind 0) or z = where
+    (kind 1); returns (ok, new_par, F or None, signed path)."""
+    p = _f64(par, (6,))
+    out = np.zeros(6)
+    F = np.zeros(36) if jacobian else None
+    s = C.c_double(0.0)
+    rc = lib().orc_step_near(_dp(p), int(kind), float(where), float(bz), _dp(out),
+                             _dp(F) if F is not None else None, C.byref(s))
+    return rc == 0, out, (F.reshape(6, 6) if F is not None else None), s.value
 
 
 def add_ms(par, C6, x0, mass, kind=0):

@@ -241,6 +241,52 @@ int orc_propagate_plane(const double p[6], double zd, double bz, double out[6], 
     return 0;
 }
 
+/* Second step of the two-step propagation (Section 2.2: from the layer's
+ * average radius or z to the exact surface of a hit): the crossing of the
+ * cylinder of radius `where` (kind 0) or of the plane z = `where` (kind 1)
+ * nearest along the helix, ahead of the state or behind it.  On a cylinder,
+ * of the two roots of the path quadratic (principal branch, |w s| < pi) the
+ * one of smaller |s|.  Returns 1 when the helix never reaches the surface. */
+int orc_step_near(const double p[6], int kind, double where, double bz, double out[6], double F[36],
+                  double *path)
+{
+    double s;
+    if (kind == 1) {
+        s = (where - p[2]) * tan(p[5]);
+        if (!isfinite(s)) return 1;
+        helix_to(p, s, bz, 1, 0.0, out, F, path);
+        out[2] = where;
+        return 0;
+    }
+    const double x = p[0], y = p[1], qpt = p[3], phi = p[4];
+    const double w = -KAPPA * bz * qpt;
+    const double b = x * cos(phi) + y * sin(phi);
+    const double e = -x * sin(phi) + y * cos(phi);
+    const double D = where * where - (x * x + y * y);
+    const double alpha = 1.0 + w * e - 0.25 * w * w * D;
+    const double disc = b * b + alpha * D;
+    if (!(disc >= 0.0)) return 1;
+    /* roots T = (-b -+ q) / (2 alpha), written without cancellation */
+    const double q = sqrt(disc);
+    const double bq = b >= 0.0 ? b + q : b - q;
+    double roots[2];
+    int nr = 0;
+    if (bq != 0.0) roots[nr++] = 0.5 * D / bq;
+    if (alpha != 0.0 && bq != 0.0) roots[nr++] = -0.5 * bq / alpha;
+    if (nr == 0 && D == 0.0) roots[nr++] = 0.0;
+    int found = 0;
+    s = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        const double u = w * roots[i];
+        const double atanc = fabs(u) < 1e-4 ? 1.0 - u * u / 3.0 + u * u * u * u / 5.0 : atan(u) / u;
+        const double si = 2.0 * roots[i] * atanc;
+        if (!found || fabs(si) < fabs(s)) s = si;
+        found = 1;
+    }
+    if (!found) return 1;
+    return helix_to(p, s, bz, 0, where, out, F, path);
+}
+
 void orc_transport(const double F[36], double C[36])
 {
     double FC[36], Ft[36];
@@ -396,6 +442,39 @@ static void leave_layer(const orc_config *cfg, int L, const double p[6], double 
     orc_add_ms(p, cfg->kind[L], cfg->x0[L], cfg->mass, C);
 }
 
+/* The surface of a hit on layer L: its radius on a cylinder, its z on a disk. */
+static double hit_surface(const orc_config *cfg, int L, const double hit[3])
+{
+    return cfg->kind[L] == 0 ? hypot(hit[0], hit[1]) : hit[2];
+}
+
+/* Second step on a layer of finite thickness: the state (p, C) on the
+ * layer's average surface carried to the hit's own surface.  Returns 1 when
+ * the helix does not reach it. */
+static int step_to_hit(const orc_config *cfg, int L, const double p[6], const double C[36],
+                       const double hit[3], double out_p[6], double out_C[36])
+{
+    double F[36], np[6], nC[36];
+    if (orc_step_near(p, cfg->kind[L], hit_surface(cfg, L, hit), cfg->bz, np, F, NULL)) return 1;
+    memcpy(nC, C, sizeof(nC));
+    orc_transport(F, nC);
+    memcpy(out_p, np, sizeof(np));
+    memcpy(out_C, nC, sizeof(nC));
+    return 0;
+}
+
+/* Fit: straight to the surface of the layer's hit (h != NULL) on a thick
+ * layer - the composition of the two steps - else to the average surface. */
+static int fit_to_layer(const orc_config *cfg, int L, const double p[6], const double *hit, double out[6],
+                        double F[36])
+{
+    if (hit && cfg->thick[L] > 0.0) {
+        if (cfg->kind[L] == 0) return orc_propagate(p, hypot(hit[0], hit[1]), cfg->bz, out, F, NULL, NULL);
+        return orc_propagate_plane(p, hit[2], cfg->bz, out, F, NULL, NULL);
+    }
+    return to_layer(cfg, L, p, out, F, NULL);
+}
+
 /* ------------------------------------------------------------ threading */
 
 typedef struct {
@@ -463,19 +542,19 @@ static void fit_one(void *vctx, int64_t i)
         if (c->hit_chi2) c->hit_chi2[i * nl + L] = -1.0;
     }
     for (int L = 0; L < nl; ++L) {
+        const int32_t h = c->track_hits[i * nl + L];
+        const double *hit = h >= 0 ? c->hits->xyz[L] + 3 * (int64_t)h : NULL;
         if (L > 0) {
             double np[6], F[36];
             leave_layer(cfg, L - 1, p, C);
-            if (to_layer(cfg, L, p, np, F, NULL)) {
+            if (fit_to_layer(cfg, L, p, hit, np, F)) {
                 status = 2;
                 break;
             }
             memcpy(p, np, sizeof(p));
             orc_transport(F, C);
         }
-        const int32_t h = c->track_hits[i * nl + L];
         if (h >= 0) {
-            const double *hit = c->hits->xyz[L] + 3 * (int64_t)h;
             double c2 = layer_update(cfg, L, p, C, hit, p, C);
             chi2 += c2;
             ++nupd;
@@ -660,7 +739,15 @@ static void build_one(void *vctx, int64_t row)
                     for (int32_t j = 0; j < bc->hits->n_hits[L]; ++j) {
                         const double *h = xyz + 3 * (int64_t)j;
                         if (h[0] * pp[0] + h[1] * pp[1] <= 0.0) continue;   /* other side */
-                        double c2 = layer_chi2(cfg, L, pp, pred_C[c], h);
+                        double c2;
+                        if (cfg->thick[L] > 0.0) {
+                            /* two-step: from the average surface to the hit's */
+                            double hp[6], hC[36];
+                            if (step_to_hit(cfg, L, pp, pred_C[c], h, hp, hC)) continue;
+                            c2 = layer_chi2(cfg, L, hp, hC, h);
+                        } else {
+                            c2 = layer_chi2(cfg, L, pp, pred_C[c], h);
+                        }
                         double dm = fabs(c2 - cfg->chi2_cut);
                         if (dm < m_cut) m_cut = dm;
                         if (c2 < cfg->chi2_cut) {
@@ -729,7 +816,13 @@ static void build_one(void *vctx, int64_t row)
             *nc = *par;
             if (e->kind == KIND_HIT) {
                 const double *h = bc->hits->xyz[L] + 3 * (int64_t)e->hit;
-                layer_update(cfg, L, pred_par[e->parent], pred_C[e->parent], h, nc->par, nc->C);
+                if (cfg->thick[L] > 0.0) {
+                    double hp[6], hC[36];
+                    step_to_hit(cfg, L, pred_par[e->parent], pred_C[e->parent], h, hp, hC);
+                    layer_update(cfg, L, hp, hC, h, nc->par, nc->C);
+                } else {
+                    layer_update(cfg, L, pred_par[e->parent], pred_C[e->parent], h, nc->par, nc->C);
+                }
                 nc->chi2 = e->chi2;
                 nc->hits[L] = e->hit;
                 nc->n_hits = e->n_hits;
@@ -796,6 +889,10 @@ double orc_replay(const orc_config *cfg, const orc_hits *hits, const double seed
         const int32_t h = layer_hits[L];
         if (h >= 0) {
             const double *hit = hits->xyz[L] + 3 * (int64_t)h;
+            if (cfg->thick[L] > 0.0 && step_to_hit(cfg, L, p, C, hit, p, C)) {
+                *ok = 0;
+                break;
+            }
             double c2 = layer_update(cfg, L, p, C, hit, p, C);
             layer_chi2[L] = c2;
             total += c2;

@@ -39,6 +39,8 @@ typedef struct {
     int32_t kind[ORC_MAX_LAYERS];   /* 0 cylinder of radius radius[L], 1 disk: plane z = zplane[L] */
     double zplane[ORC_MAX_LAYERS];
     double sigma_r;             /* disk hit resolution along r */
+    double thick[ORC_MAX_LAYERS];   /* > 0: hits spread over this radial (cylinder) or z (disk) depth
+                                       around the average surface; two-step propagation */
 } orc_config;
 
 typedef struct {
@@ -79,6 +81,12 @@ int orc_propagate(const double par[6], double r, double bz, double out[6],
  * from it; *margin receives the signed transverse path. */
 int orc_propagate_plane(const double par[6], double zd, double bz, double out[6],
                         double F[36], double *path, double *margin);
+
+/* The nearest crossing (either direction) of the cylinder r = where (kind
+ * 0) or the plane z = where (kind 1): the second, short step of the two-step
+ * propagation.  Returns 1 when the helix never reaches it. */
+int orc_step_near(const double par[6], int kind, double where, double bz, double out[6], double F[36],
+                  double *path);
 
 /* Add multiple-scattering noise for crossing a layer (kind 0 cylinder, 1
  * disk) of thickness x0 at the state's position (full 6x6 row-major

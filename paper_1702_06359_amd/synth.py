@@ -74,10 +74,17 @@ class Geometry:
     disk_z: Optional[Sequence[float]] = None
     disk_rmin: float = 2.0
     sigma_r: float = 0.1
+    # finite thickness (Section 2.2's simplified geometry: modules of a layer
+    # sit at different radii, or z on a disk): a track's hit on layer L lies
+    # on the surface r_L + d (z_L + d), d uniform in [-t/2, t/2] per crossing
+    thickness: Optional[Sequence[float]] = None
 
     @property
     def is_disk(self) -> bool:
         return self.disk_z is not None
+
+    def thick(self, L: int) -> float:
+        return 0.0 if self.thickness is None else float(self.thickness[L])
 
     @staticmethod
     def endcap(n_layers: int = 10) -> "Geometry":
@@ -178,7 +185,7 @@ def _cross_plane(x, y, z, qpt, phi, theta, zd, bz):
     nx = np.where(straight, x + s * np.cos(phi), cx + np.sin(nphi) / ws)
     ny = np.where(straight, y + s * np.sin(phi), cy - np.cos(nphi) / ws)
     nphi = np.mod(nphi + np.pi, 2.0 * np.pi) - np.pi
-    return nx, ny, np.full(np.shape(x), float(zd)), nphi, s
+    return nx, ny, np.broadcast_to(np.asarray(zd, dtype=np.float64), np.shape(x)).copy(), nphi, s
 
 
 def _highland(p, beta, t):
@@ -284,7 +291,7 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
     """
     g = geometry or Geometry()
     nl = g.n_layers
-    rk, rv, rms, rsm, rno, rsh = _streams(cfg, event, 6)
+    rk, rv, rms, rsm, rno, rsh, rth = _streams(cfg, event, 7)
     n = int(n_tracks)
     pt = rk.uniform(pt_range[0], pt_range[1], n)
     if eta_range is None:
@@ -304,9 +311,12 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
     true_xyz = np.zeros((n, nl, 3))
     for L in range(nl):
         r = float(g.radii[L])
+        t = g.thick(L)
+        d = rth.uniform(-0.5 * t, 0.5 * t, n) if t > 0 else 0.0
         if g.is_disk:
-            x, y, z, phi, _ = _cross_plane(x, y, z, qpt, phi, theta, float(g.disk_z[L]), g.bz)
+            x, y, z, phi, _ = _cross_plane(x, y, z, qpt, phi, theta, float(g.disk_z[L]) + d, g.bz)
         else:
+            r = r + d
             x, y, z, phi, _ = _cross_cylinder(x, y, z, qpt, phi, theta, r, g.bz)
         truth[:, L] = np.stack([x, y, z, qpt, phi, theta], axis=1)
         phi_pos = np.arctan2(y, x)
@@ -334,9 +344,9 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
                 cos_a = np.abs(np.cos(theta))
             else:
                 cos_a = np.abs(np.sin(theta) * np.cos(phi - phi_pos))
-            t = g.x0[L] / np.maximum(cos_a, 1e-6)
+            tx = g.x0[L] / np.maximum(cos_a, 1e-6)
             beta = p / np.sqrt(p * p + g.mass * g.mass)
-            th0 = _highland(p, beta, t)
+            th0 = _highland(p, beta, tx)
             a1 = rms.normal(0.0, 1.0, n) * th0
             a2 = rms.normal(0.0, 1.0, n) * th0
             d = np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)], 1)
@@ -359,12 +369,15 @@ def make_event(n_tracks: int, *, cfg: int = 0, event: int = 0,
         nn = int(round(frac[L] * n))
         n_noise[L] = nn
         ph = rno.uniform(-np.pi, np.pi, nn)
+        t = g.thick(L)
         if g.is_disk:   # uniform over the annulus
             rr = np.sqrt(rno.uniform(g.disk_rmin ** 2, r * r, nn))
-            noise_xyz = np.stack([rr * np.cos(ph), rr * np.sin(ph), np.full(nn, float(g.disk_z[L]))], axis=1)
+            zd = float(g.disk_z[L]) + (rno.uniform(-0.5 * t, 0.5 * t, nn) if t > 0 else 0.0)
+            noise_xyz = np.stack([rr * np.cos(ph), rr * np.sin(ph), np.broadcast_to(zd, (nn,))], axis=1)
         else:
             zz = rno.uniform(-hz[L], hz[L], nn)
-            noise_xyz = np.stack([r * np.cos(ph), r * np.sin(ph), zz], axis=1)
+            rr = r + (rno.uniform(-0.5 * t, 0.5 * t, nn) if t > 0 else 0.0)
+            noise_xyz = np.stack([rr * np.cos(ph), rr * np.sin(ph), zz], axis=1)
         allh = np.concatenate([true_xyz[:, L], noise_xyz], axis=0)
         perm = rsh.permutation(allh.shape[0])
         inv = np.empty_like(perm)
