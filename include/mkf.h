@@ -64,7 +64,13 @@ typedef enum {
  * material of each layer in radiation lengths at normal incidence (0 = none);
  * the path through it grows as 1 / cos of the angle to the layer normal
  * (radial for a cylinder, z for a disk).  Layers are crossed in index order;
- * consecutive cylinders need increasing radii. */
+ * consecutive cylinders need increasing radii.
+ * A layer of thickness t > 0 (Section 2.2's simplified geometry: modules at
+ * different radii) holds hits anywhere within t/2 of its average radius (z
+ * for a disk).  Building then propagates in two steps: to the average
+ * surface, then, for each hit in the window, to the hit's own radius (z),
+ * ahead or behind, where its chi2 and the update are taken; the fit goes
+ * straight to the hit's surface.  The GPU takes all-thin or all-thick lists. */
 typedef struct {
     int32_t n_layers;        /* 4 .. MKF_MAX_LAYERS */
     int32_t n_seed_layers;   /* seeds carry one hit on each of layers 0 .. n_seed_layers-1 */
@@ -84,6 +90,7 @@ typedef struct {
     double layer_z[MKF_MAX_LAYERS];       /* disk plane, cm (nonzero) */
     double layer_rmin[MKF_MAX_LAYERS];    /* disk inner radius, 0 <= rmin < layer_r */
     double sigma_r;          /* disk hit resolution along r, cm (> 0 when a disk exists) */
+    double layer_thickness[MKF_MAX_LAYERS];   /* depth of a layer, cm (0: hits on the surface) */
 } mkf_config;
 
 /* Device memory hooks.  alloc returns device memory usable on `stream`

@@ -47,6 +47,7 @@ class Config(C.Structure):
         ("chi2_cut", C.c_double), ("mass", C.c_double),
         ("layer_kind", C.c_int32 * MAX_LAYERS), ("layer_z", C.c_double * MAX_LAYERS),
         ("layer_rmin", C.c_double * MAX_LAYERS), ("sigma_r", C.c_double),
+        ("layer_thickness", C.c_double * MAX_LAYERS),
     ]
 
 
@@ -185,6 +186,7 @@ def config_from_geometry(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n
             c.layer_kind[i] = 1
             c.layer_z[i] = geometry.disk_z[i]
             c.layer_rmin[i] = geometry.disk_rmin
+        c.layer_thickness[i] = geometry.thick(i)
     c.bz = geometry.bz
     c.sigma_rphi = geometry.sigma_rphi
     c.sigma_z = geometry.sigma_z

@@ -187,6 +187,48 @@ __device__ __forceinline__ void transport(const float (&F)[6][6], float (&c)[21]
     }
 }
 
+// Position block of F C F^T only (xx, xy, yy, xz, yz, zz): what the chi2 of
+// a hit needs after the second step of a thick layer.
+template <bool kDisk>
+__device__ __forceinline__ void transport_pos(const float (&F)[6][6], const float (&c)[21], float (&cp)[6])
+{
+    constexpr const signed char(&kFpat)[6][6] = kDisk ? kFpatDisk : kFpatCyl;
+    float M[3][6];   // rows 0..2 of F C
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            float acc = 0.f;
+            bool first = true;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                if (kFpat[i][t] == 0) continue;
+                const float v = c[sym(t, j)];
+                if (first) acc = (kFpat[i][t] == 2) ? v : F[i][t] * v;
+                else acc = (kFpat[i][t] == 2) ? acc + v : fmaf(F[i][t], v, acc);
+                first = false;
+            }
+            M[i][j] = acc;
+        }
+    }
+    constexpr int kI[6] = {0, 0, 1, 0, 1, 2}, kK[6] = {0, 1, 1, 2, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const int i = kI[e], k = kK[e];
+        float acc = 0.f;
+        bool first = true;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            if (kFpat[k][t] == 0) continue;
+            const float v = M[i][t];
+            if (first) acc = (kFpat[k][t] == 2) ? v : v * F[k][t];
+            else acc = (kFpat[k][t] == 2) ? acc + v : fmaf(v, F[k][t], acc);
+            first = false;
+        }
+        cp[e] = acc;
+    }
+}
+
 // sin(a)/a, (1-cos a)/a and their derivatives (a cos a - sin a)/a^2,
 // (a sin a - 1 + cos a)/a^2: series below |a| = 0.5, where the direct forms
 // lose FP32 digits to cancellation.
@@ -238,6 +280,9 @@ __device__ __forceinline__ Trig trig_of(const float (&p)[6])
     return t;
 }
 
+__device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, float s, float w_per_qpt,
+                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out);
+
 // Propagate state p (with the sines and cosines of its angles in tg) to the
 // cylinder of radius r along the helix of the
 // uniform field (curvature w = w_per_qpt * q/pT, w > 0 turning
@@ -251,7 +296,7 @@ __device__ __forceinline__ Trig trig_of(const float (&p)[6])
 __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
                                           float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
 {
-    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
+    const float x = p[0], y = p[1], q = p[3];
     const float sph = tg.sph, cph = tg.cph;
     const float w = w_per_qpt * q;
     const float b = fmaf(x, cph, y * sph);
@@ -283,7 +328,18 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
         }
         if (!(s < kInf)) return false;
     }
+    helix_cyl(p, tg, s, w_per_qpt, o, F, sn_out, cn_out);
+    return true;
+}
 
+// The helix step of transverse path s (either sign) from state p, and the
+// Jacobian on the cylinder through the end point (see propagate).
+__device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, float s, float w_per_qpt,
+                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+{
+    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
+    const float sph = tg.sph, cph = tg.cph;
+    const float w = w_per_qpt * q;
     const float a = w * s;
     float S1, C1, S2, C2;
     turn_terms(a, S1, C1, S2, C2);
@@ -336,8 +392,46 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
     F[4][1] = w * dsy;
     F[4][3] = fmaf(w, dsq, Ppq);
     F[4][4] = fmaf(w, dsp, 1.f);
+}
+
+// Second step of the two-step propagation on a layer of finite thickness:
+// from the layer's average cylinder to the nearby cylinder of radius r
+// through a hit, ahead or behind.  Of the two roots of the path quadratic
+// (principal branch) the one of smaller |s|.  False when r is never reached.
+__device__ __forceinline__ bool step_near_cyl(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
+                                              float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+{
+    const float x = p[0], y = p[1];
+    const float w = w_per_qpt * p[3];
+    const float b = fmaf(x, tg.cph, y * tg.sph);
+    const float e = fmaf(y, tg.cph, -x * tg.sph);
+    const float D = fmaf(r, r, -fmaf(x, x, y * y));
+    const float alpha = fmaf(w, e, 1.f) - 0.25f * w * w * D;
+    const float disc = fmaf(b, b, alpha * D);
+    if (!(disc >= 0.f)) return false;
+    const float qd = __builtin_amdgcn_sqrtf(disc);
+    const float bq = b >= 0.f ? b + qd : b - qd;
+    float s;
+    if (bq != 0.f) {
+        const float T1 = 0.5f * D / bq;
+        s = 2.f * T1 * atanc(w * T1);
+        if (alpha != 0.f) {
+            const float T2 = -0.5f * bq / alpha;
+            const float s2 = 2.f * T2 * atanc(w * T2);
+            if (fabsf(s2) < fabsf(s)) s = s2;
+        }
+    } else if (D == 0.f) {
+        s = 0.f;
+    } else {
+        return false;
+    }
+    if (!(fabsf(s) < kInf)) return false;
+    helix_cyl(p, tg, s, w_per_qpt, o, F, sn_out, cn_out);
     return true;
 }
+
+__device__ __forceinline__ void helix_plane(const float (&p)[6], const Trig &tg, float s, float zd, float w_per_qpt,
+                                            float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out);
 
 // Propagate state p to the plane z = zd (an endcap disk): the transverse
 // path is fixed by the dip angle, s = (zd - z) tan(theta), and must be
@@ -347,14 +441,22 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
 __device__ __forceinline__ bool propagate_plane(const float (&p)[6], const Trig &tg, float zd, float w_per_qpt,
                                                 float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
 {
-    const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
+    const float s = (zd - p[2]) * (tg.sth * fast_rcp(tg.cth));
+    if (!(s > 0.f) || !(s < kInf)) return false;
+    helix_plane(p, tg, s, zd, w_per_qpt, o, F, sn_out, cn_out);
+    return true;
+}
+
+// The helix step of transverse path s (either sign) from state p onto the
+// plane z = zd, and the Jacobian on that plane (see propagate_plane).
+__device__ __forceinline__ void helix_plane(const float (&p)[6], const Trig &tg, float s, float zd, float w_per_qpt,
+                                            float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+{
+    const float x = p[0], y = p[1], q = p[3], phi = p[4];
     const float sph = tg.sph, cph = tg.cph;
     const float w = w_per_qpt * q;
     const float ict = fast_rcp(tg.cth);
     const float tanth = tg.sth * ict;
-    const float s = (zd - z) * tanth;
-    if (!(s > 0.f) || !(s < kInf)) return false;
-
     const float a = w * s;
     float S1, C1, S2, C2;
     turn_terms(a, S1, C1, S2, C2);
@@ -400,6 +502,16 @@ __device__ __forceinline__ bool propagate_plane(const float (&p)[6], const Trig 
     F[4][4] = 1.f;
     F[4][5] = w * dst;
     F[5][5] = 1.f;
+}
+
+// Second step onto the plane z = zd through a hit of a thick disk, ahead or
+// behind: s = (zd - z) tan(theta) of either sign.
+__device__ __forceinline__ bool step_near_plane(const float (&p)[6], const Trig &tg, float zd, float w_per_qpt,
+                                                float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+{
+    const float s = (zd - p[2]) * (tg.sth * fast_rcp(tg.cth));
+    if (!(fabsf(s) < kInf)) return false;
+    helix_plane(p, tg, s, zd, w_per_qpt, o, F, sn_out, cn_out);
     return true;
 }
 

@@ -26,7 +26,8 @@ struct LayerParam {
     float grid_lo;     // lower edge of the second coordinate: -half_z, or the disk's r_min
     float zplane;      // disk plane
     int kind;          // 0 cylinder, 1 disk
-    int pad[3];
+    float half_thick;  // half the layer's depth (radial or along z); 0: hits on the surface
+    int pad[2];
 };
 
 // Building and fitting parameters for one launch.
@@ -39,7 +40,7 @@ struct Params {
     int hole_always;
     int bins_phi;
     int bins_z;
-    int disks;           // 1: every layer is a disk, 0: every layer a cylinder
+    int geo;             // bit 0: every layer a disk (else a cylinder); bit 1: every layer thick
     float w_per_qpt;     // -kappa * B: curvature w = w_per_qpt * q/pT
     float var_u;         // sigma_rphi^2
     float var_z;         // sigma_z^2
@@ -120,6 +121,7 @@ struct BatchArgs {
 };
 
 // Launch helpers implemented in mkf_kernels.hip.
+size_t build_lds_bytes(int geo, int n_layers, int waves_per_block);   // dynamic LDS of a batched build block
 hipError_t launch_fill_i32(int *ptr, int value, int n, hipStream_t s);
 hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s);
 hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s);

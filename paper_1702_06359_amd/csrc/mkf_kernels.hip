@@ -100,7 +100,9 @@ __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_sta
 // or (r, phi): bin = iz * bins_phi + iphi.  A counting sort over all events
 // of a batch at once.
 
-// A caller-order hit as (cos phi, sin phi, z or r, 0) and its (row, phi) bin.
+// A caller-order hit as (cos phi, sin phi, z or r, 0) - on a layer of finite
+// thickness (x, y, z, 0), whose own surface the second propagation step
+// needs - and its (row, phi) bin.
 __device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const double *xyz, float4 *out)
 {
     const double x = xyz[0], y = xyz[1];
@@ -113,7 +115,7 @@ __device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, co
     int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
     ip = min(max(ip, 0), P.bins_phi - 1);
     iz = min(max(iz, 0), P.bins_z - 1);
-    *out = make_float4(c, s, g2, 0.f);
+    *out = lp.half_thick > 0.f ? make_float4((float)x, (float)y, (float)xyz[2], 0.f) : make_float4(c, s, g2, 0.f);
     return iz * P.bins_phi + ip;
 }
 
@@ -424,13 +426,26 @@ constexpr int kRuns = 128;   // run records held before their pairs are evaluate
 constexpr int kAcc = 128;    // accepted entries held before the owners merge them
 constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
 
-struct SearchLds {
-    float4 own[3][kWave];    // owner state {x, y, z, chi2}, {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}
+// Surface kinds the kernels are specialised for: bit 0 disks (else
+// cylinders), bit 1 finite thickness (two-step propagation).
+constexpr bool geo_disk(int geo) { return (geo & 1) != 0; }
+constexpr bool geo_thick(int geo) { return (geo & 2) != 0; }
+
+// kOwn rows of owner data per lane: 3 on thin layers ({x, y, z or r, chi2},
+// {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}); 8 on thick ones, where every
+// pair carries its candidate to the hit's own surface and so needs the whole
+// predicted state ({x, y, z, chi2}, {q/pT, sin phi, cos phi, sin theta},
+// {cos theta, -, -, C0}, then C1..C20).
+template <int kOwn>
+struct SearchLdsT {
+    float4 own[kOwn][kWave];
     int4 run[kRuns];         // {first binned index, first pair index, owner lane, -}
     int2 acc[kAcc];          // {accumulated chi2 bits, hit id << 8 | next entry}
     int head[kWave];         // first accepted entry of each owner
     int mark[kWave];         // run starting at each pair slot of the current round
 };
+template <int kGeo>
+using SearchLds = SearchLdsT<geo_thick(kGeo) ? 8 : 3>;
 
 // LDS written by some lanes of a wavefront and read by others: the wavefront's
 // LDS operations are executed in order, so it only takes a compiler barrier
@@ -458,9 +473,11 @@ __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
     return s - x;
 }
 
-template <int K, bool kStats, bool kDisk>
+template <int K, bool kStats, int kGeo>
 struct WaveSearch {
-    SearchLds &W;
+    static constexpr bool kDisk = geo_disk(kGeo);
+    static constexpr bool kThick = geo_thick(kGeo);
+    SearchLds<kGeo> &W;
     const float4 *bh;
     const Params &P;
     const int lane;
@@ -530,17 +547,54 @@ struct WaveSearch {
             float tot = 0.f;
             unsigned hid = 0;
             if (valid) {
-                const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
-                const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
-                if (kStats) {
-                    cnt.scan++;
-                    if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd) cnt.chi2++;
+                if constexpr (!kThick) {
+                    const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
+                    const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
+                    if (kStats) {
+                        cnt.scan++;
+                        if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd)
+                            cnt.chi2++;
+                    }
+                    const float c2 = kDisk ? hit_chi2_disk(a.x, a.y, b.x, b.y, b.z, hv.x, hv.y, hv.z, P.var_u, P.var_r)
+                                           : hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z,
+                                                      P.var_u, P.var_z);
+                    ok = fwd & (c2 < P.chi2_cut);
+                    tot = a.w + c2;
+                } else {
+                    // two-step: the owner's prediction on the layer's average
+                    // surface, carried to this hit's own surface
+                    const float4 r0 = W.own[0][o], r1 = W.own[1][o], r2 = W.own[2][o];
+                    const bool fwd = fmaf(r0.x, hv.x, r0.y * hv.y) > 0.f;
+                    float c[21];
+                    c[0] = r2.w;
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) {
+                        const float4 v = W.own[3 + i][o];
+                        c[1 + 4 * i] = v.x;
+                        c[2 + 4 * i] = v.y;
+                        c[3 + 4 * i] = v.z;
+                        c[4 + 4 * i] = v.w;
+                    }
+                    const float p[6] = {r0.x, r0.y, r0.z, r1.x, 0.f, 0.f};
+                    const Trig tg{r1.y, r1.z, r1.w, r2.x};
+                    const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
+                    const float irh = fast_rcp(rh);
+                    float np[6], F[6][6], sn, cn, cp[6];
+                    const bool reach = kDisk ? step_near_plane(p, tg, hv.z, P.w_per_qpt, np, F, sn, cn)
+                                             : step_near_cyl(p, tg, rh, P.w_per_qpt, np, F, sn, cn);
+                    transport_pos<kDisk>(F, c, cp);
+                    const float ch = hv.x * irh, sh = hv.y * irh;
+                    const float c2 = kDisk ? hit_chi2_disk(np[0], np[1], cp[0], cp[1], cp[2], ch, sh, rh, P.var_u,
+                                                           P.var_r)
+                                           : hit_chi2(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], ch,
+                                                      sh, hv.z, P.var_u, P.var_z);
+                    if (kStats) {
+                        cnt.scan++;
+                        if (fwd && reach) cnt.chi2++;
+                    }
+                    ok = fwd & reach & (c2 < P.chi2_cut);
+                    tot = r0.w + c2;
                 }
-                const float c2 = kDisk ? hit_chi2_disk(a.x, a.y, b.x, b.y, b.z, hv.x, hv.y, hv.z, P.var_u, P.var_r)
-                                       : hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z,
-                                                  P.var_u, P.var_z);
-                ok = fwd & (c2 < P.chi2_cut);
-                tot = a.w + c2;
                 hid = (unsigned)__float_as_int(hv.w);
             }
             const unsigned long long am = __ballot(ok);
@@ -577,24 +631,26 @@ struct WaveSearch {
 // with `predicted` set: the best K accepted hits of the lane in (lc, lid),
 // sorted by accumulated chi2 then hit id; returns the lane's accepted count.
 // All lanes of the wavefront must call it together.
-template <int K, bool kStats, bool kDisk>
-__device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], float chi2, bool predicted,
-                                            int L, const LayerParam &lp, const Params &P, const DevEvent &E,
-                                            int lane, SearchLds &W, unsigned long long (&lk)[K], Count &cnt)
+// Half-widths of the window that holds every chi2 < cut hit of a surface,
+// for a predicted position (x, y, z) with position covariance (cxx, cxy,
+// cyy, czz): du along the layer, dz along the grid's second coordinate g2 (z,
+// or r on a disk), and the bound x = du / r on the azimuth (inv_r: 1 / the
+// cylinder's radius).
+template <bool kDisk>
+__device__ __forceinline__ void window_at(const Params &P, float x, float y, float z, float cxx, float cxy, float cyy,
+                                          float czz, float inv_r, float scale, float &du, float &dz, float &g2,
+                                          float &xr)
 {
-    int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
-    float du = 0.f, dz = 0.f, g2 = pp[2];
-    if (predicted) {
-        const float cxx = pc[sym(0, 0)], cxy = pc[sym(0, 1)], cyy = pc[sym(1, 1)];
+    {
         const float hd = 0.5f * (cxx - cyy);
         const float lmax = 0.5f * (cxx + cyy) + sqrtf(fmaf(hd, hd, cxy * cxy));
-        float xr;
         if (!kDisk) {
             // the chi2 < cut ellipse lies inside |u| <= du, |dz| <= dz, since
             // S_uu(phi_h) <= lambda_max(C_xy) + V_u for every hit direction
-            du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * P.win_scale;
-            dz = sqrtf(P.chi2_cut * (pc[sym(2, 2)] + P.var_z)) * P.win_scale;
-            xr = du * lp.inv_r;
+            g2 = z;
+            du = sqrtf(P.chi2_cut * (lmax + P.var_u)) * scale;
+            dz = sqrtf(P.chi2_cut * (czz + P.var_z)) * scale;
+            xr = du * inv_r;
         } else {
             // On a disk the position covariance has a radial part too.  Any
             // hit with chi2 < cut lies within d0 = sqrt(cut (lmax + max V))
@@ -604,30 +660,98 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
             // sqrt(C_uu) + |a| sqrt(lmax) (likewise for r), which bounds
             // each residual separately: |rp sin a| <= du and
             // |r_h - rp cos a| <= dr.
-            g2 = sqrtf(fmaf(pp[0], pp[0], pp[1] * pp[1]));
+            g2 = sqrtf(fmaf(x, x, y * y));
             const float irp = fast_rcp(g2);
-            const float cp = pp[0] * irp, sp = pp[1] * irp;
+            const float cp = x * irp, sp = y * irp;
             const float cuu = fmaf(sp * sp, cxx, fmaf(-2.f * sp * cp, cxy, cp * cp * cyy));
             const float crr = fmaf(cp * cp, cxx, fmaf(2.f * sp * cp, cxy, sp * sp * cyy));
-            const float d0 = sqrtf(P.chi2_cut * (lmax + fmaxf(P.var_u, P.var_r))) * P.win_scale;
+            const float d0 = sqrtf(P.chi2_cut * (lmax + fmaxf(P.var_u, P.var_r))) * scale;
             const float x0 = d0 * irp;
             const float a0 = x0 >= 0.7f ? 0.5f * kPi : x0 * __builtin_amdgcn_rsqf(1.f - x0 * x0);
             const float sl = a0 * sqrtf(lmax);
             const float su = sqrtf(fmaxf(cuu, 0.f)) + sl, sr = sqrtf(fmaxf(crr, 0.f)) + sl;
-            du = sqrtf(P.chi2_cut * fmaf(su, su, P.var_u)) * P.win_scale;
+            du = sqrtf(P.chi2_cut * fmaf(su, su, P.var_u)) * scale;
             // rp (1 - cos a) <= du^2 / rp for the low edge of the radius range
-            dz = fmaf(du * du, irp, sqrtf(P.chi2_cut * fmaf(sr, sr, P.var_r)) * P.win_scale);
+            dz = fmaf(du * du, irp, sqrtf(P.chi2_cut * fmaf(sr, sr, P.var_r)) * scale);
             xr = du * irp;
         }
+    }
+}
+
+// |phi_h - phi| <= asin(x) <= x / sqrt(1 - x^2) for x = du / r
+__device__ __forceinline__ float dphi_of(float xr)
+{
+    return (xr >= 0.7f || !(xr >= 0.f) ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
+}
+
+// Windowed search of layer L for the predicted state (pp, pc) of every lane
+// with `predicted` set: the best K accepted hits of the lane in (lc, lid),
+// sorted by accumulated chi2 then hit id; returns the lane's accepted count.
+// All lanes of the wavefront must call it together.
+template <int K, bool kStats, int kGeo>
+__device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], const Trig &tg, float chi2,
+                                            bool predicted, int L, const LayerParam &lp, const Params &P,
+                                            const DevEvent &E, int lane, SearchLds<kGeo> &W,
+                                            unsigned long long (&lk)[K], Count &cnt)
+{
+    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
+    int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
+    float du = 0.f, dz = 0.f, g2 = pp[2];
+    if (predicted) {
         const float phipos = fast_atan2(pp[1], pp[0]);
-        // |phi_h - phi| <= asin(du / r) <= x / sqrt(1 - x^2), x = du / r
-        const float dphi = (xr >= 0.7f || !(xr >= 0.f) ? 0.5f * kPi : xr * __builtin_amdgcn_rsqf(1.f - xr * xr)) + 1e-5f;
+        float lo, hi, g2lo, g2hi;   // azimuth offsets from phipos, second-coordinate range
+        bool finite = isfinite(phipos);
+        if constexpr (!kThick) {
+            float xr;
+            window_at<kDisk>(P, pp[0], pp[1], pp[2], pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(2, 2)],
+                             lp.inv_r, P.win_scale, du, dz, g2, xr);
+            hi = dphi_of(xr);
+            lo = -hi;
+            g2lo = g2 - dz;
+            g2hi = g2 + dz;
+        } else {
+            // A thick layer's hits lie between two bounding surfaces: the
+            // window is the union of the chi2 < cut windows at both (the
+            // predicted point moves along the short arc between them and its
+            // covariance changes quadratically with the step), widened by 10 %.
+            lo = kInf;
+            hi = -kInf;
+            g2lo = kInf;
+            g2hi = -kInf;
+#pragma unroll
+            for (int end = -1; end <= 1; end += 2) {
+                const float where = (kDisk ? lp.zplane : lp.r) + (float)end * lp.half_thick;
+                float np[6], F[6][6], sn, cn, cp[6];
+                const bool reach = kDisk ? step_near_plane(pp, tg, where, P.w_per_qpt, np, F, sn, cn)
+                                         : step_near_cyl(pp, tg, where, P.w_per_qpt, np, F, sn, cn);
+                transport_pos<kDisk>(F, pc, cp);
+                float due, dze, g2e, xre;
+                window_at<kDisk>(P, np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[5], fast_rcp(where),
+                                 P.win_scale * 1.1f, due, dze, g2e, xre);
+                const float off = wrap_pi(fast_atan2(np[1], np[0]) - phipos);
+                const float dph = dphi_of(xre);
+                lo = fminf(lo, off - dph);
+                hi = fmaxf(hi, off + dph);
+                g2lo = fminf(g2lo, g2e - dze);
+                g2hi = fmaxf(g2hi, g2e + dze);
+                finite = finite && reach;
+            }
+            if (!finite) {   // an edge out of reach: the whole layer
+                finite = isfinite(phipos);
+                lo = -kPi;
+                hi = kPi;
+                g2lo = -1e30f;
+                g2hi = 1e30f;
+            }
+        }
         const int nphi = P.bins_phi;
-        if (isfinite(phipos) && isfinite(dphi) && isfinite(dz) && isfinite(g2)) {
-            const int ilo = (int)floorf((phipos - dphi + kPi) * lp.inv_dphi);
-            const int ihi = (int)floorf((phipos + dphi + kPi) * lp.inv_dphi);
-            izlo = min(max((int)floorf((g2 - dz - 1e-4f - lp.grid_lo) * lp.inv_dz), 0), P.bins_z - 1);
-            const int izhi = min(max((int)floorf((g2 + dz + 1e-4f - lp.grid_lo) * lp.inv_dz), 0), P.bins_z - 1);
+        if (finite && isfinite(lo) && isfinite(hi) && !isnan(g2lo) && !isnan(g2hi)) {
+            const int ilo = (int)floorf((phipos + lo + kPi) * lp.inv_dphi);
+            const int ihi = (int)floorf((phipos + hi + kPi) * lp.inv_dphi);
+            const float zlo = fmaxf((g2lo - 1e-4f - lp.grid_lo) * lp.inv_dz, -1.f);
+            const float zhi = fminf((g2hi + 1e-4f - lp.grid_lo) * lp.inv_dz, (float)P.bins_z);
+            izlo = min(max((int)floorf(zlo), 0), P.bins_z - 1);
+            const int izhi = min(max((int)floorf(zhi), 0), P.bins_z - 1);
             n_rows = izhi - izlo + 1;
             if (ihi - ilo + 1 >= nphi) {
                 s0lo = 0;
@@ -650,12 +774,21 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
             }
         }
     }
-    W.own[0][lane] = make_float4(pp[0], pp[1], g2, chi2);
-    W.own[1][lane] = make_float4(pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(0, 2)]);
-    W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
+    if constexpr (!kThick) {
+        W.own[0][lane] = make_float4(pp[0], pp[1], g2, chi2);
+        W.own[1][lane] = make_float4(pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(0, 2)]);
+        W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
+    } else {
+        W.own[0][lane] = make_float4(pp[0], pp[1], pp[2], chi2);
+        W.own[1][lane] = make_float4(pp[3], tg.sph, tg.cph, tg.sth);
+        W.own[2][lane] = make_float4(tg.cth, 0.f, 0.f, pc[0]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            W.own[3 + i][lane] = make_float4(pc[1 + 4 * i], pc[2 + 4 * i], pc[3 + 4 * i], pc[4 + 4 * i]);
+    }
     W.head[lane] = kEnd;
 
-    WaveSearch<K, kStats, kDisk> ws{W, E.binned, P, lane, lk, cnt};
+    WaveSearch<K, kStats, kGeo> ws{W, E.binned, P, lane, lk, cnt};
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * (P.bins_phi * P.bins_z + 1);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
@@ -703,10 +836,11 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
 // One building layer for every lane of a wavefront (Section 2: propagate the
 // candidate to the next layer, collect compatible hits, branch; Section
 // 3.2.1: re-rank and prune to max_cands per seed).
-template <int G, bool kStats, bool kDisk>
+template <int G, bool kStats, int kGeo>
 __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
-                                           const int lane, const Hist &H, SearchLds &W, Count &cnt)
+                                           const int lane, const Hist &H, SearchLds<kGeo> &W, Count &cnt)
 {
+    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
     constexpr int K = G;     // a parent contributes at most max_cands <= G children
     const int gbase = (lane / G) * G;
     const int slot = lane - gbase;
@@ -742,7 +876,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     unsigned long long lk[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) lk[i] = ~0ull;
-    const int nacc = search_layer<K, kStats, kDisk>(pp, pc, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
+    const int nacc = search_layer<K, kStats, kGeo>(pp, pc, S.tg, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
     if (kStats) cnt.acc += nacc;
 
     // 3. hole child, or stop on this surface (with the prediction as state)
@@ -803,7 +937,23 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     S.stopped = p_stopped;
     S.status = p_status;
     if (with_hit) {
-        kf_update<kDisk>(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
+        if constexpr (!kThick) {
+            kf_update<kDisk>(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
+        } else {
+            // second step to the hit's own surface, then the update there
+            const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
+            const float irh = fast_rcp(rh);
+            float np[6], F[6][6], sn, cn;
+            if (kDisk) step_near_plane(S.p, S.tg, hv.z, P.w_per_qpt, np, F, sn, cn);
+            else step_near_cyl(S.p, S.tg, rh, P.w_per_qpt, np, F, sn, cn);
+            transport<kDisk>(F, S.c);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) S.p[i] = np[i];
+            S.tg.sph = sn;
+            S.tg.cph = cn;
+            kf_update<kDisk>(S.p, S.c, S.tg, hv.x * irh, hv.y * irh, kDisk ? rh : hv.z, P.var_u,
+                             kDisk ? P.var_r : P.var_z);
+        }
         if (kStats) cnt.upd++;
         H.put(L, lane, (int)hid, parent);
     } else {
@@ -864,7 +1014,7 @@ __host__ __device__ constexpr int search_lds_offset(int waves, int n_layers)
 // Batched builder.  Each wavefront takes work items (event, group of 64/G
 // seeds) - from a device counter when persistent, else from its block index -
 // and runs every building layer of its seeds with the state in registers.
-template <int G, bool kStats, bool kDisk>
+template <int G, bool kStats, int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_batch(const Params P, const BatchArgs B, int persistent)
 {
     extern __shared__ int s_dyn[];
@@ -874,7 +1024,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int per_wave = P.n_layers * kWave;
     Hist H{s_dyn + wave * per_wave, reinterpret_cast<unsigned char *>(s_dyn + W * per_wave) + wave * per_wave,
            kWave};
-    SearchLds &SL = reinterpret_cast<SearchLds *>(s_dyn + search_lds_offset(W, P.n_layers))[wave];
+    SearchLds<kGeo> &SL = reinterpret_cast<SearchLds<kGeo> *>(s_dyn + search_lds_offset(W, P.n_layers))[wave];
     int item = blockIdx.x * W + wave;
     for (;;) {
         if (persistent) {
@@ -891,7 +1041,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         Lane S;
         init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
         Count cnt;
-        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats, kDisk>(S, L, P, E, lane, H, SL, cnt);
+        for (int L = P.n_seed_layers; L < P.n_layers; ++L) layer_step<G, kStats, kGeo>(S, L, P, E, lane, H, SL, cnt);
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
         flush_counts<kStats>(cnt, E, lane);
         if (!persistent) break;
@@ -900,7 +1050,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // Per-layer builder: one event, one layer per launch, candidate state in
 // device memory (structure of arrays, slot = seed * G + rank) between layers.
-template <int G, bool kStats, bool kDisk>
+template <int G, bool kStats, int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
 {
     const DevEvent &E = *Ep;
@@ -934,9 +1084,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                       : Trig{0.f, 1.f, 1.f, 0.f};
     }
     extern __shared__ int s_dyn[];
-    SearchLds &SL = reinterpret_cast<SearchLds *>(s_dyn)[threadIdx.x >> 6];
+    SearchLds<kGeo> &SL = reinterpret_cast<SearchLds<kGeo> *>(s_dyn)[threadIdx.x >> 6];
     Count cnt;
-    layer_step<G, kStats, kDisk>(S, L, P, E, lane, H, SL, cnt);
+    layer_step<G, kStats, kGeo>(S, L, P, E, lane, H, SL, cnt);
     if (L == P.n_layers - 1) {
         finalize_lane<G>(S, P, E, lane, valid ? seed : E.n_seeds, H);
     } else {
@@ -961,7 +1111,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // layer the scattering of the previous one, propagation, transport, and the
 // update with that layer's hit if it has one (hit_of(L) >= 0).  (op, oc) is
 // the state after the last update.
-template <bool kDisk, class HitOf>
+template <int kGeo, class HitOf>
 __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, float (&p)[6], float (&c)[21],
                                           HitOf hit_of, float (&op)[6], float (&oc)[21], float &chi2, int &nupd,
                                           int &status)
@@ -973,12 +1123,24 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
     chi2 = 0.f;
     nupd = 0;
     status = 0;
+    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
     Trig tg = trig_of(p);
     for (int L = 0; L < P.n_layers; ++L) {
+        const int h = hit_of(L);
+        float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
+        float where = kDisk ? P.layer[L].zplane : P.layer[L].r;
+        if constexpr (kThick) {
+            // the hit carries (x, y, z): its own surface is the target (the
+            // two steps composed)
+            if (h >= 0) {
+                hv = load_global(E.hits + E.layer_off[L] + h);
+                where = kDisk ? hv.z : sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
+            }
+        }
         if (L > 0) {
             float np[6], F[6][6], sn, cn;
-            if (!(kDisk ? propagate_plane(p, tg, P.layer[L].zplane, P.w_per_qpt, np, F, sn, cn)
-                        : propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn))) {
+            if (!(kDisk ? propagate_plane(p, tg, where, P.w_per_qpt, np, F, sn, cn)
+                        : propagate(p, tg, where, P.w_per_qpt, np, F, sn, cn))) {
                 status = 2;
                 break;
             }
@@ -989,12 +1151,23 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
-        const int h = hit_of(L);
         if (h >= 0) {
-            const float4 hv = load_global(E.hits + E.layer_off[L] + h);
+            float ch, sh, g2h;
+            if constexpr (kThick) {
+                const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
+                const float irh = fast_rcp(rh);
+                ch = hv.x * irh;
+                sh = hv.y * irh;
+                g2h = kDisk ? rh : hv.z;
+            } else {
+                hv = load_global(E.hits + E.layer_off[L] + h);
+                ch = hv.x;
+                sh = hv.y;
+                g2h = hv.z;
+            }
             // Joseph form: a fit starts from a wide prior, where the plain
             // form C - K H C would lose FP32 digits
-            chi2 += kf_update_joseph<kDisk>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
+            chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
             ++nupd;
 #pragma unroll
             for (int i = 0; i < 6; ++i) op[i] = p[i];
@@ -1005,7 +1178,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
 }
 
 // Fit with known hits: one lane per track, no branching beyond skipped layers.
-template <bool kDisk>
+template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1019,8 +1192,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int i = 0; i < 6; ++i) p[i] = (float)load_global(E.track_par + 6 * t + i);
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = (float)load_global(E.track_cov + 21 * t + i);
-    fit_track<kDisk>(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc,
-                     chi2, nupd, status);
+    fit_track<kGeo>(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc,
+                    chi2, nupd, status);
 #pragma unroll
     for (int i = 0; i < 6; ++i) store_global(E.fit_par + 6 * t + i, (double)op[i]);
 #pragma unroll
@@ -1094,7 +1267,7 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
 
 // Final fit of every built track of a batch (after the build): one lane per
 // seed, hits from the build's output.
-template <bool kDisk>
+template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_refit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1105,8 +1278,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int *hits = E.out_hits + t * P.n_layers;
     float p[6], c[21], op[6], oc[21], chi2 = 0.f;
     int nupd = 0, status = 3;
-    if (final_fit_prior<kDisk>(E, P, hits, p, c))
-        fit_track<kDisk>(P, E, p, c, [&](int L) { return load_global(hits + L); }, op, oc, chi2, nupd, status);
+    if (final_fit_prior<geo_disk(kGeo)>(E, P, hits, p, c))
+        fit_track<kGeo>(P, E, p, c, [&](int L) { return load_global(hits + L); }, op, oc, chi2, nupd, status);
     else {
 #pragma unroll
         for (int i = 0; i < 6; ++i) op[i] = 0.f;
@@ -1216,15 +1389,26 @@ hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
     return hipGetLastError();
 }
 
+size_t build_lds_bytes(int geo, int n_layers, int wpb)
+{
+    const size_t search = geo_thick(geo) ? sizeof(SearchLds<2>) : sizeof(SearchLds<0>);
+    return sizeof(int) * (size_t)search_lds_offset(wpb, n_layers) + (size_t)wpb * search;
+}
+
 template <int G, bool kStats>
 static hipError_t launch_batch_t(const Params &p, const BatchArgs &b, int wpb, int persistent, int n_blocks,
                                  hipStream_t s)
 {
-    const size_t lds = sizeof(int) * (size_t)search_lds_offset(wpb, p.n_layers) + wpb * sizeof(SearchLds);
     const unsigned grid = persistent ? (unsigned)n_blocks : blocks_for(b.total_items, wpb);
     if (grid == 0) return hipSuccess;
-    if (p.disks) k_build_batch<G, kStats, true><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
-    else k_build_batch<G, kStats, false><<<grid, wpb * kWave, lds, s>>>(p, b, persistent);
+    const size_t hist = sizeof(int) * (size_t)search_lds_offset(wpb, p.n_layers);
+    switch (p.geo) {
+    case 0: k_build_batch<G, kStats, 0><<<grid, wpb * kWave, hist + wpb * sizeof(SearchLds<0>), s>>>(p, b, persistent); break;
+    case 1: k_build_batch<G, kStats, 1><<<grid, wpb * kWave, hist + wpb * sizeof(SearchLds<1>), s>>>(p, b, persistent); break;
+    case 2: k_build_batch<G, kStats, 2><<<grid, wpb * kWave, hist + wpb * sizeof(SearchLds<2>), s>>>(p, b, persistent); break;
+    case 3: k_build_batch<G, kStats, 3><<<grid, wpb * kWave, hist + wpb * sizeof(SearchLds<3>), s>>>(p, b, persistent); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1252,8 +1436,13 @@ static hipError_t launch_layer_t(const Params &p, const DevEvent *ev_dev, int n_
     const int items = (n_seeds + kWave / G - 1) / (kWave / G);
     const unsigned grid = blocks_for(items, wpb);
     if (grid == 0) return hipSuccess;
-    if (p.disks) k_build_layer<G, kStats, true><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
-    else k_build_layer<G, kStats, false><<<grid, wpb * kWave, wpb * sizeof(SearchLds), s>>>(p, ev_dev, L);
+    switch (p.geo) {
+    case 0: k_build_layer<G, kStats, 0><<<grid, wpb * kWave, wpb * sizeof(SearchLds<0>), s>>>(p, ev_dev, L); break;
+    case 1: k_build_layer<G, kStats, 1><<<grid, wpb * kWave, wpb * sizeof(SearchLds<1>), s>>>(p, ev_dev, L); break;
+    case 2: k_build_layer<G, kStats, 2><<<grid, wpb * kWave, wpb * sizeof(SearchLds<2>), s>>>(p, ev_dev, L); break;
+    case 3: k_build_layer<G, kStats, 3><<<grid, wpb * kWave, wpb * sizeof(SearchLds<3>), s>>>(p, ev_dev, L); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1278,16 +1467,28 @@ hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const Dev
 hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_seeds <= 0) return hipSuccess;
-    if (p.disks) k_refit<true><<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
-    else k_refit<false><<<blocks_for(b.total_seeds, 256), 256, 0, s>>>(p, b);
+    const unsigned grid = blocks_for(b.total_seeds, 256);
+    switch (p.geo) {
+    case 0: k_refit<0><<<grid, 256, 0, s>>>(p, b); break;
+    case 1: k_refit<1><<<grid, 256, 0, s>>>(p, b); break;
+    case 2: k_refit<2><<<grid, 256, 0, s>>>(p, b); break;
+    case 3: k_refit<3><<<grid, 256, 0, s>>>(p, b); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_tracks <= 0) return hipSuccess;
-    if (p.disks) k_fit<true><<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
-    else k_fit<false><<<blocks_for(b.total_tracks, 256), 256, 0, s>>>(p, b);
+    const unsigned grid = blocks_for(b.total_tracks, 256);
+    switch (p.geo) {
+    case 0: k_fit<0><<<grid, 256, 0, s>>>(p, b); break;
+    case 1: k_fit<1><<<grid, 256, 0, s>>>(p, b); break;
+    case 2: k_fit<2><<<grid, 256, 0, s>>>(p, b); break;
+    case 3: k_fit<3><<<grid, 256, 0, s>>>(p, b); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

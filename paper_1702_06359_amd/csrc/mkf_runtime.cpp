@@ -189,6 +189,7 @@ void derive_params(mkf_ctx *ctx)
         lp.inv_dphi = (float)(t.bins_phi / (2.0 * M_PI));
         lp.inv_r = (float)(1.0 / c.layer_r[L]);
         lp.kind = c.layer_kind[L];
+        lp.half_thick = (float)(0.5 * c.layer_thickness[L]);
         if (lp.kind == 0) {
             lp.half_z = (float)c.layer_half_z[L];
             lp.inv_dz = (float)(t.bins_z / (2.0 * c.layer_half_z[L]));
@@ -204,7 +205,7 @@ void derive_params(mkf_ctx *ctx)
     P.max_cands = c.max_cands;
     P.max_holes = c.max_holes;
     P.hole_always = (c.flags & MKF_HOLE_ALWAYS) ? 1 : 0;
-    P.disks = c.layer_kind[0] == 1 ? 1 : 0;
+    P.geo = (c.layer_kind[0] == 1 ? 1 : 0) | (c.layer_thickness[0] > 0.0 ? 2 : 0);
     P.bins_phi = t.bins_phi;
     P.bins_z = t.bins_z;
     P.w_per_qpt = (float)(-0.00299792458 * c.bz);
@@ -248,6 +249,14 @@ mkf_status check_config(const mkf_config *c)
     for (int L = 1; L < c->n_layers; ++L)
         if (c->layer_kind[L] != c->layer_kind[0])
             return fail(MKF_E_INVALID, "layers must be all cylinders or all disks (mixed lists are not supported)");
+    for (int L = 0; L < c->n_layers; ++L) {
+        const double t = c->layer_thickness[L];
+        if (!(t >= 0.0) || !std::isfinite(t)) return fail(MKF_E_INVALID, "layer_thickness must be >= 0");
+        if ((t > 0.0) != (c->layer_thickness[0] > 0.0))
+            return fail(MKF_E_INVALID, "layers must be all thin or all thick (mixed lists are not supported)");
+        const double ref = c->layer_kind[L] == 0 ? c->layer_r[L] : std::fabs(c->layer_z[L]);
+        if (!(0.5 * t < ref)) return fail(MKF_E_INVALID, "layer_thickness must be below twice the layer's r or |z|");
+    }
     if (!std::isfinite(c->bz)) return fail(MKF_E_INVALID, "bz must be finite");
     if (!(c->sigma_rphi > 0) || !(c->sigma_z > 0) || !std::isfinite(c->sigma_rphi) || !std::isfinite(c->sigma_z))
         return fail(MKF_E_INVALID, "hit resolutions must be positive");
@@ -800,8 +809,8 @@ mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t)
     mkf_tuning nt = *t;
     mkf_status st = check_tuning(ctx->cfg, &nt);
     if (st != MKF_OK) return st;
-    const size_t lds = (size_t)nt.waves_per_block * ctx->cfg.n_layers * kWave * 5;
-    if (lds > 65536) return fail(MKF_E_INVALID, "waves_per_block too large for %d layers", ctx->cfg.n_layers);
+    if (build_lds_bytes(ctx->params.geo, ctx->cfg.n_layers, nt.waves_per_block) > 65536)
+        return fail(MKF_E_INVALID, "waves_per_block too large for %d layers", ctx->cfg.n_layers);
     ctx->tuning = nt;
     derive_params(ctx);
     drop_graphs_with(ctx, -1);

@@ -40,7 +40,7 @@ def test_exported_symbols_are_unmangled_c(libpath):
 def test_binding_struct_layouts_match_the_header():
     structs = {
         "mkf_config": (abi.Config, ["n_layers", "flags", "layer_r", "layer_half_z", "layer_x0", "bz", "chi2_cut",
-                                    "mass", "layer_kind", "layer_z", "layer_rmin", "sigma_r"]),
+                                    "mass", "layer_kind", "layer_z", "layer_rmin", "sigma_r", "layer_thickness"]),
         "mkf_allocator": (abi.Allocator, ["alloc", "free", "user"]),
         "mkf_event": (abi.Event, ["n_layers", "n_seeds", "n_tracks", "n_hits", "hit_xyz", "seed_par", "seed_cov",
                                   "seed_hits", "track_par", "track_cov", "track_hits"]),
