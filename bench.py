@@ -8,7 +8,7 @@ JSON line with throughput, the roofline of the build kernel, the CPU oracle
 baseline and serving latencies.
 
 Other workloads (--workload): endcap (10 events x 10,000 tracks on ten
-disks), fit (1,000,000 tracks in 64 uneven batches), batched (256 uneven
+disks), two_step (the headline on 6 mm deep barrel layers), fit (1,000,000 tracks in 64 uneven batches), batched (256 uneven
 events, batched vs plain builder), serve (Poisson arrivals, p50/p99 latency).
 """
 from __future__ import annotations
@@ -225,6 +225,8 @@ def workload_ckf(args):
     if not args.quick:
         log("endcap workload")
         result["endcap"] = endcap_leg(args)
+        log("two-step workload")
+        result["two_step"] = two_step_leg(args)
         log("serving latency run")
         pool_sizes = synth.loguniform_sizes(16, 500, 50000, cfg=4)
         pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(pool_sizes)]
@@ -246,13 +248,11 @@ def workload_ckf(args):
     return result
 
 
-def endcap_leg(args, steps=None):
-    """The same step on the endcap workload: 10 events x 10,000 tracks on ten
-    disks (1.6 < eta < 2.6), 10 % noise, k = 6."""
+def geometry_leg(args, evs, geometry, workload, steps=None):
+    """The headline step (index + batched build, k = 6) on other events."""
     import torch
-    from paper_1702_06359_amd import abi, synth
-    evs = synth.endcap_events(10, 10000, 0.10)
-    ctx = make_ctx(6, args.tuning, geometry=synth.Geometry.endcap())
+    from paper_1702_06359_amd import abi
+    ctx = make_ctx(6, args.tuning, geometry=geometry)
     handles = [ctx.load_event(e) for e in evs]
 
     def step():
@@ -269,15 +269,31 @@ def endcap_leg(args, steps=None):
     build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
     ctx.close()
     tracks = sum(e.n_seeds for e in evs)
-    return {"workload": "combinatorial KF building, 10 events x 10,000 tracks, 10-disk endcap "
-                        "(z = 30..120 cm, 1.6 < eta < 2.6), 10% noise hits, k=6, chi2<30, 1 hole",
-            "tracks_per_s": round(tracks * n / elapsed, 1), "ms_per_step": round(elapsed / n * 1e3, 4),
-            "build_kernel_ms": round(build_ms / max(build_n, 1), 4)}
+    return {"workload": workload, "tracks_per_s": round(tracks * n / elapsed, 1),
+            "ms_per_step": round(elapsed / n * 1e3, 4), "build_kernel_ms": round(build_ms / max(build_n, 1), 4)}
+
+
+def endcap_leg(args, steps=None):
+    """10 events x 10,000 tracks on ten disks (1.6 < eta < 2.6), 10 % noise."""
+    from paper_1702_06359_amd import synth
+    return geometry_leg(args, synth.endcap_events(10, 10000, 0.10), synth.Geometry.endcap(),
+                        "combinatorial KF building, 10 events x 10,000 tracks, 10-disk endcap "
+                        "(z = 30..120 cm, 1.6 < eta < 2.6), 10% noise hits, k=6, chi2<30, 1 hole", steps)
+
+
+def two_step_leg(args, steps=None):
+    """The headline events' recipe on a barrel whose layers are 6 mm deep:
+    two-step propagation, every window hit carried to its own radius."""
+    from paper_1702_06359_amd import synth
+    g = synth.Geometry(thickness=tuple(0.6 for _ in range(10)))
+    evs = [synth.make_event(20000, cfg=5, event=e, noise=0.10, geometry=g) for e in range(10)]
+    return geometry_leg(args, evs, g, "combinatorial KF building, 10 events x 20,000 tracks, 10-layer barrel "
+                        "of 6 mm deep layers (two-step propagation), 10% noise hits, k=6, chi2<30, 1 hole", steps)
 
 
 def workload_endcap(args):
-    r = endcap_leg(args)
-    return {"metric": "tracks built/sec (endcap disks, combinatorial KF)", "value": r["tracks_per_s"],
+    r = endcap_leg(args) if args.workload == "endcap" else two_step_leg(args)
+    return {"metric": f"tracks built/sec ({args.workload}, combinatorial KF)", "value": r["tracks_per_s"],
             "unit": "tracks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32", "data": "synthetic", "config": {"workload": r["workload"]},
@@ -448,7 +464,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ckf", choices=["ckf", "endcap", "fit", "batched", "serve", "calib"])
+    ap.add_argument("--workload", default="ckf",
+                    choices=["ckf", "endcap", "two_step", "fit", "batched", "serve", "calib"])
     ap.add_argument("--serve-events", type=int, default=1024)
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--quick", action="store_true", help="headline number only (profiling runs)")
@@ -457,7 +474,8 @@ def main():
     args = ap.parse_args()
     gpu_count_guard(args.gpus)
     args.tuning = None
-    res = {"ckf": workload_ckf, "endcap": workload_endcap, "fit": workload_fit, "batched": workload_batched,
+    res = {"ckf": workload_ckf, "endcap": workload_endcap, "two_step": workload_endcap, "fit": workload_fit,
+           "batched": workload_batched,
            "serve": workload_serve, "calib": workload_calib}[args.workload](args)
     print(json.dumps(res), flush=True)
 

@@ -25,7 +25,7 @@ MAX_CANDS = 16
 class OrcConfig(C.Structure):
     _fields_ = [
         ("n_layers", C.c_int32), ("n_seed_layers", C.c_int32), ("max_cands", C.c_int32),
-        ("max_holes", C.c_int32), ("hole_always", C.c_int32), ("pad_", C.c_int32),
+        ("max_holes", C.c_int32), ("hole_always", C.c_int32), ("update3d", C.c_int32),
         ("radius", C.c_double * MAX_LAYERS), ("x0", C.c_double * MAX_LAYERS),
         ("bz", C.c_double), ("sigma_rphi", C.c_double), ("sigma_z", C.c_double),
         ("chi2_cut", C.c_double), ("mass", C.c_double),
@@ -93,6 +93,10 @@ def lib():
         L.orc_update.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_update.restype = C.c_double
         L.orc_transport.argtypes = [dp, dp]
+        L.orc_chi2_3d.argtypes = [dp, dp, dp, C.c_double, C.c_double, C.c_double]
+        L.orc_chi2_3d.restype = C.c_double
+        L.orc_update_3d.argtypes = [dp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_update_3d.restype = C.c_double
         L.orc_fit.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip,
                               dp, dp, dp, ip, ip, dp, C.c_int32]
         L.orc_build.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip, ip,
@@ -121,13 +125,14 @@ def _f64(a, shape=None):
 
 
 def config(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n_seed_layers=3,
-           hole_always=False) -> OrcConfig:
+           hole_always=False, update3d=False) -> OrcConfig:
     c = OrcConfig()
     c.n_layers = geometry.n_layers
     c.n_seed_layers = n_seed_layers
     c.max_cands = max_cands
     c.max_holes = max_holes
     c.hole_always = int(bool(hole_always))
+    c.update3d = int(bool(update3d))
     for i in range(geometry.n_layers):
         c.radius[i] = geometry.radii[i]
         c.x0[i] = geometry.x0[i]
@@ -218,6 +223,19 @@ def update(par, C6, hit, sigma_rphi, sigma_2, kind=0):
     out_C = np.zeros(36)
     c2 = lib().orc_update(_dp(_f64(par, (6,))), _dp(_f64(C6, (36,))), _dp(_f64(hit, (3,))),
                           int(kind), sigma_rphi, sigma_2, _dp(out_p), _dp(out_C))
+    return out_p, out_C.reshape(6, 6), c2
+
+
+def chi2_3d(par, C6, hit, sigma_rphi, sigma_r, sigma_z):
+    return lib().orc_chi2_3d(_dp(_f64(par, (6,))), _dp(_f64(C6, (36,))), _dp(_f64(hit, (3,))),
+                             sigma_rphi, sigma_r, sigma_z)
+
+
+def update_3d(par, C6, hit, sigma_rphi, sigma_r, sigma_z):
+    out_p = np.zeros(6)
+    out_C = np.zeros(36)
+    c2 = lib().orc_update_3d(_dp(_f64(par, (6,))), _dp(_f64(C6, (36,))), _dp(_f64(hit, (3,))),
+                             sigma_rphi, sigma_r, sigma_z, _dp(out_p), _dp(out_C))
     return out_p, out_C.reshape(6, 6), c2
 
 

@@ -428,12 +428,14 @@ static double second_sigma(const orc_config *cfg, int L)
 static double layer_chi2(const orc_config *cfg, int L, const double p[6], const double C[36],
                          const double hit[3])
 {
+    if (cfg->update3d) return orc_chi2_3d(p, C, hit, cfg->sigma_rphi, cfg->sigma_r, cfg->sigma_z);
     return orc_chi2(p, C, hit, cfg->kind[L], cfg->sigma_rphi, second_sigma(cfg, L));
 }
 
 static double layer_update(const orc_config *cfg, int L, const double p[6], const double C[36],
                            const double hit[3], double out_p[6], double out_C[36])
 {
+    if (cfg->update3d) return orc_update_3d(p, C, hit, cfg->sigma_rphi, cfg->sigma_r, cfg->sigma_z, out_p, out_C);
     return orc_update(p, C, hit, cfg->kind[L], cfg->sigma_rphi, second_sigma(cfg, L), out_p, out_C);
 }
 
@@ -473,6 +475,79 @@ static int fit_to_layer(const orc_config *cfg, int L, const double p[6], const d
         return orc_propagate_plane(p, hit[2], cfg->bz, out, F, NULL, NULL);
     }
     return to_layer(cfg, L, p, out, F, NULL);
+}
+
+/* The 3x3 global-Cartesian variant: the measurement is the hit's position
+ * (x, y, z) itself, H = [I3 0], with the hit's error ellipsoid
+ * V = sigma_rphi^2 u u^T + sigma_r^2 n n^T + sigma_z^2 e_z e_z^T, where
+ * u = (-sin phi_h, cos phi_h, 0) and n = (cos phi_h, sin phi_h, 0).  With
+ * sigma_r (cylinders) or sigma_z (disks) along the layer normal, it needs
+ * all three positive. */
+static void measurement3(const double p[6], const double hit[3], double su, double sr, double sz, double H[18],
+                         double res[3], double V[9])
+{
+    const double phih = atan2(hit[1], hit[0]);
+    const double u[3] = {-sin(phih), cos(phih), 0.0}, n[3] = {cos(phih), sin(phih), 0.0}, e[3] = {0.0, 0.0, 1.0};
+    memset(H, 0, 18 * sizeof(double));
+    for (int i = 0; i < 3; ++i) {
+        H[i * 6 + i] = 1.0;
+        res[i] = hit[i] - p[i];
+        for (int j = 0; j < 3; ++j) V[i * 3 + j] = su * su * u[i] * u[j] + sr * sr * n[i] * n[j] + sz * sz * e[i] * e[j];
+    }
+}
+
+/* inverse of a 3x3 matrix by its cofactors */
+static void inverse3(const double A[9], double B[9])
+{
+    B[0] = A[4] * A[8] - A[5] * A[7];
+    B[1] = A[2] * A[7] - A[1] * A[8];
+    B[2] = A[1] * A[5] - A[2] * A[4];
+    B[3] = A[5] * A[6] - A[3] * A[8];
+    B[4] = A[0] * A[8] - A[2] * A[6];
+    B[5] = A[2] * A[3] - A[0] * A[5];
+    B[6] = A[3] * A[7] - A[4] * A[6];
+    B[7] = A[1] * A[6] - A[0] * A[7];
+    B[8] = A[0] * A[4] - A[1] * A[3];
+    const double det = A[0] * B[0] + A[1] * B[3] + A[2] * B[6];
+    for (int i = 0; i < 9; ++i) B[i] /= det;
+}
+
+static double update3_impl(const double p[6], const double C[36], const double hit[3], double su, double sr,
+                           double sz, double *out_p, double *out_C)
+{
+    double H[18], r[3], V[9], HC[18], Ht[18], S[9], Si[9], Sr[3];
+    measurement3(p, hit, su, sr, sz, H, r, V);
+    matmul(H, C, HC, 3, 6, 6);
+    transpose(H, Ht, 3, 6);
+    matmul(HC, Ht, S, 3, 6, 3);
+    for (int i = 0; i < 9; ++i) S[i] += V[i];
+    inverse3(S, Si);
+    matmul(Si, r, Sr, 3, 3, 1);
+    const double chi2 = r[0] * Sr[0] + r[1] * Sr[1] + r[2] * Sr[2];
+    if (!out_p) return chi2;
+    double CHt[18], K[18], Kr[6], KHC[36], np[6], nC[36];
+    transpose(HC, CHt, 3, 6);
+    matmul(CHt, Si, K, 6, 3, 3);
+    matmul(K, r, Kr, 6, 3, 1);
+    matmul(K, HC, KHC, 6, 3, 6);
+    for (int i = 0; i < 6; ++i) np[i] = p[i] + Kr[i];
+    np[4] = wrap_angle(np[4]);
+    for (int i = 0; i < 36; ++i) nC[i] = C[i] - KHC[i];
+    symmetrize(nC);
+    memcpy(out_p, np, sizeof(np));
+    memcpy(out_C, nC, sizeof(nC));
+    return chi2;
+}
+
+double orc_chi2_3d(const double p[6], const double C[36], const double hit[3], double srphi, double sr, double sz)
+{
+    return update3_impl(p, C, hit, srphi, sr, sz, NULL, NULL);
+}
+
+double orc_update_3d(const double p[6], const double C[36], const double hit[3], double srphi, double sr, double sz,
+                     double out_p[6], double out_C[36])
+{
+    return update3_impl(p, C, hit, srphi, sr, sz, out_p, out_C);
 }
 
 /* ------------------------------------------------------------ threading */

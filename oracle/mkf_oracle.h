@@ -28,7 +28,7 @@ typedef struct {
     int32_t max_cands;          /* beam width k */
     int32_t max_holes;
     int32_t hole_always;        /* 1: a hole child even when hits were accepted */
-    int32_t pad_;
+    int32_t update3d;           /* 1: 3x3 global-Cartesian measurement (orc_update_3d) on every layer */
     double radius[ORC_MAX_LAYERS];
     double x0[ORC_MAX_LAYERS];  /* material per layer, radiation lengths at normal incidence */
     double bz;
@@ -103,6 +103,14 @@ double orc_chi2(const double par[6], const double C[36], const double hit[3], in
  * returns the hit's chi2. */
 double orc_update(const double par[6], const double C[36], const double hit[3], int kind,
                   double sigma_rphi, double s2, double out_par[6], double out_C[36]);
+
+/* The 3x3 global-Cartesian measurement: the hit's (x, y, z) with error
+ * ellipsoid sigma_rphi (along the layer), sigma_r (radial), sigma_z (along z),
+ * all positive.  chi2, and the update writing the filtered state. */
+double orc_chi2_3d(const double par[6], const double C[36], const double hit[3], double sigma_rphi,
+                   double sigma_r, double sigma_z);
+double orc_update_3d(const double par[6], const double C[36], const double hit[3], double sigma_rphi,
+                     double sigma_r, double sigma_z, double out_par[6], double out_C[36]);
 
 /* Transport C <- F C F^T (full 6x6). */
 void orc_transport(const double F[36], double C[36]);
