@@ -51,6 +51,10 @@ typedef enum {
 
 /* config.flags */
 #define MKF_HOLE_ALWAYS 0x1u   /* offer a hole child even when hits were accepted */
+#define MKF_UPDATE_3D 0x2u     /* 3x3 global-Cartesian measurement: the hit's (x, y, z) with the error
+                                  ellipsoid sigma_rphi along the layer, sigma_r radially and sigma_z along z
+                                  (the layer normal carries sigma_r on a cylinder, sigma_z on a disk), in
+                                  place of the two coordinates on the tangent plane; needs sigma_r > 0 */
 
 /* Detector, field and building parameters (Section 2.2: ideal barrel of
  * cylinders in a uniform longitudinal field, Gaussian hit resolution; the

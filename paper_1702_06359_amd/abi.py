@@ -24,6 +24,7 @@ MAX_CANDS = 8
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_AGAIN, E_NOTFOUND, E_STATE = 0, -1, -2, -3, -4, -5, -6
 HOLE_ALWAYS = 0x1
+UPDATE_3D = 0x2
 BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC, BATCH_FIT = 0x1, 0x2, 0x4, 0x8, 0x10
 TIMER_BUILD, TIMER_INDEX, TIMER_FIT = 0, 1, 2
 
@@ -170,13 +171,13 @@ def _ip(a):
 
 
 def config_from_geometry(geometry, *, max_cands=1, max_holes=1, chi2_cut=30.0, n_seed_layers=3,
-                         hole_always=False) -> Config:
+                         hole_always=False, update3d=False) -> Config:
     c = Config()
     c.n_layers = geometry.n_layers
     c.n_seed_layers = n_seed_layers
     c.max_cands = max_cands
     c.max_holes = max_holes
-    c.flags = HOLE_ALWAYS if hole_always else 0
+    c.flags = (HOLE_ALWAYS if hole_always else 0) | (UPDATE_3D if update3d else 0)
     hz = geometry.half_z()
     for i in range(geometry.n_layers):
         c.layer_r[i] = geometry.radii[i]

@@ -677,6 +677,146 @@ __device__ __forceinline__ float kf_update_joseph(float (&p)[6], float (&c)[21],
     return chi2;
 }
 
+// ---- 3x3 global-Cartesian measurement ----------------------------------------
+// The hit's position (x, y, z) measured with the error ellipsoid
+// V = var_u u u^T + var_r n n^T + var_z e_z e_z^T (u = (-sin, cos, 0) and
+// n = (cos, sin, 0) at the hit's azimuth); H = [I3 0].
+
+struct Sym3 {           // symmetric 3x3: xx, xy, yy, xz, yz, zz
+    float a[6];
+};
+
+__device__ __forceinline__ Sym3 hit_ellipsoid(float ch, float sh, float var_u, float var_r, float var_z)
+{
+    Sym3 v;
+    v.a[0] = fmaf(var_u * sh, sh, var_r * ch * ch);
+    v.a[1] = (var_r - var_u) * sh * ch;
+    v.a[2] = fmaf(var_u * ch, ch, var_r * sh * sh);
+    v.a[3] = 0.f;
+    v.a[4] = 0.f;
+    v.a[5] = var_z;
+    return v;
+}
+
+// inverse of a symmetric 3x3 by its cofactors
+__device__ __forceinline__ Sym3 inverse_sym3(const Sym3 &s)
+{
+    const float xx = s.a[0], xy = s.a[1], yy = s.a[2], xz = s.a[3], yz = s.a[4], zz = s.a[5];
+    Sym3 b;
+    b.a[0] = fmaf(yy, zz, -yz * yz);
+    b.a[1] = fmaf(xz, yz, -xy * zz);
+    b.a[2] = fmaf(xx, zz, -xz * xz);
+    b.a[3] = fmaf(xy, yz, -xz * yy);
+    b.a[4] = fmaf(xy, xz, -xx * yz);
+    b.a[5] = fmaf(xx, yy, -xy * xy);
+    const float idet = 1.f / fmaf(xx, b.a[0], fmaf(xy, b.a[1], xz * b.a[3]));
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b.a[i] *= idet;
+    return b;
+}
+
+__device__ __forceinline__ constexpr int s3(int i, int j)
+{
+    return i == j ? (i == 0 ? 0 : (i == 1 ? 2 : 5)) : ((i + j) == 1 ? 1 : ((i + j) == 2 ? 3 : 4));
+}
+
+// chi2 of a hit (hx, hy, hz) against a predicted position with covariance
+// (cxx, cxy, cyy, cxz, cyz, czz)
+__device__ __forceinline__ float hit_chi2_3d(float x, float y, float z, float cxx, float cxy, float cyy, float cxz,
+                                             float cyz, float czz, float hx, float hy, float hz, float var_u,
+                                             float var_r, float var_z)
+{
+    const float irh = __builtin_amdgcn_rsqf(fmaf(hx, hx, hy * hy));
+    const Sym3 v = hit_ellipsoid(hx * irh, hy * irh, var_u, var_r, var_z);
+    Sym3 S;
+    S.a[0] = cxx + v.a[0];
+    S.a[1] = cxy + v.a[1];
+    S.a[2] = cyy + v.a[2];
+    S.a[3] = cxz;
+    S.a[4] = cyz;
+    S.a[5] = czz + v.a[5];
+    const Sym3 Si = inverse_sym3(S);
+    const float r[3] = {hx - x, hy - y, hz - z};
+    float c2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c2 = fmaf(r[i] * Si.a[s3(i, j)], r[j], c2);
+    return c2;
+}
+
+// Kalman update with the 3x3 measurement; kJoseph selects the Joseph form of
+// the covariance (the fit).  Returns the hit's chi2.
+template <bool kJoseph>
+__device__ __forceinline__ float kf_update_3d(float (&p)[6], float (&c)[21], Trig &tg, float hx, float hy, float hz,
+                                              float var_u, float var_r, float var_z)
+{
+    const float irh = __builtin_amdgcn_rsqf(fmaf(hx, hx, hy * hy));
+    const Sym3 v = hit_ellipsoid(hx * irh, hy * irh, var_u, var_r, var_z);
+    float M[3][6];   // H C: rows 0..2 of C
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) M[k][j] = c[sym(k, j)];
+    Sym3 S;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        constexpr int kI[6] = {0, 0, 1, 0, 1, 2}, kJ[6] = {0, 1, 1, 2, 2, 2};
+        S.a[e] = M[kI[e]][kJ[e]] + v.a[e];
+    }
+    const Sym3 Si = inverse_sym3(S);
+    const float r[3] = {hx - p[0], hy - p[1], hz - p[2]};
+    float Sr[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Sr[i] = fmaf(Si.a[s3(i, 0)], r[0], fmaf(Si.a[s3(i, 1)], r[1], Si.a[s3(i, 2)] * r[2]));
+    const float chi2 = fmaf(r[0], Sr[0], fmaf(r[1], Sr[1], r[2] * Sr[2]));
+    float K[6][3];   // C H^T S^-1
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            K[i][k] = fmaf(M[0][i], Si.a[s3(0, k)], fmaf(M[1][i], Si.a[s3(1, k)], M[2][i] * Si.a[s3(2, k)]));
+    float dp[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        dp[i] = fmaf(K[i][0], r[0], fmaf(K[i][1], r[1], K[i][2] * r[2]));
+        p[i] += dp[i];
+    }
+    p[4] = wrap_pi(p[4]);
+    rotate(tg.sph, tg.cph, dp[4]);
+    rotate(tg.sth, tg.cth, dp[5]);
+    if (!kJoseph) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i; j < 6; ++j)
+                c[sym(i, j)] -= fmaf(K[i][0], M[0][j], fmaf(K[i][1], M[1][j], K[i][2] * M[2][j]));
+        return chi2;
+    }
+    // C' = D - (D H^T) K^T + K V K^T with D = (I - K H) C
+    float nc[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        float D[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            D[j] = c[sym(i, j)] - fmaf(K[i][0], M[0][j], fmaf(K[i][1], M[1][j], K[i][2] * M[2][j]));
+        float KV[3];   // row i of K V
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            KV[l] = fmaf(K[i][0], v.a[s3(0, l)], fmaf(K[i][1], v.a[s3(1, l)], K[i][2] * v.a[s3(2, l)]));
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            const float dk = fmaf(D[0], K[j][0], fmaf(D[1], K[j][1], D[2] * K[j][2]));
+            const float kvk = fmaf(KV[0], K[j][0], fmaf(KV[1], K[j][1], KV[2] * K[j][2]));
+            nc[sym(i, j)] = D[j] - dk + kvk;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = nc[i];
+    return chi2;
+}
+
 // ---- beam ordering ---------------------------------------------------------
 // A child's rank key packs, most significant first: (31 - n_hits), the
 // candidate's summed chi2 (non-negative float bits order like the floats),

@@ -40,15 +40,16 @@ struct Params {
     int hole_always;
     int bins_phi;
     int bins_z;
-    int geo;             // bit 0: every layer a disk (else a cylinder); bit 1: every layer thick
+    int geo;             // bit 0: every layer a disk (else a cylinder); bit 1: hits carry (x, y, z) and every
+                         // pair is carried to the hit's surface (thick layers, or the 3x3 measurement)
     float w_per_qpt;     // -kappa * B: curvature w = w_per_qpt * q/pT
     float var_u;         // sigma_rphi^2
     float var_z;         // sigma_z^2
     float chi2_cut;
     float mass2;         // scattering mass hypothesis squared
     float win_scale;     // (1 + window margin)
-    float var_r;         // sigma_r^2 (disks)
-    float pad2;
+    float var_r;         // sigma_r^2 (disks; the radial axis of the 3x3 measurement)
+    int update3d;        // 3x3 global-Cartesian measurement (needs the (x, y, z) hit layout)
 };
 
 // Device view of one loaded event.  All pointers are device pointers.

@@ -94,6 +94,13 @@ __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_sta
     }
 }
 
+// Geometries the kernels are specialised for: bit 0 disks (else cylinders);
+// bit 1 hits that carry their position (x, y, z), to whose own surface every
+// (candidate, hit) pair is carried before its chi2 - layers of finite
+// thickness (the two-step propagation) and the 3x3 measurement.
+constexpr bool geo_disk(int geo) { return (geo & 1) != 0; }
+constexpr bool geo_xyz(int geo) { return (geo & 2) != 0; }
+
 // ---------------------------------------------------------------------------
 // Hit index: per layer, hits are grouped by an (eta, phi) grid.  On a cylinder
 // eta is a function of z, on a disk a function of r, so the grid is (z, phi)
@@ -115,7 +122,7 @@ __device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, co
     int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
     ip = min(max(ip, 0), P.bins_phi - 1);
     iz = min(max(iz, 0), P.bins_z - 1);
-    *out = lp.half_thick > 0.f ? make_float4((float)x, (float)y, (float)xyz[2], 0.f) : make_float4(c, s, g2, 0.f);
+    *out = geo_xyz(P.geo) ? make_float4((float)x, (float)y, (float)xyz[2], 0.f) : make_float4(c, s, g2, 0.f);
     return iz * P.bins_phi + ip;
 }
 
@@ -426,10 +433,6 @@ constexpr int kRuns = 128;   // run records held before their pairs are evaluate
 constexpr int kAcc = 128;    // accepted entries held before the owners merge them
 constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
 
-// Surface kinds the kernels are specialised for: bit 0 disks (else
-// cylinders), bit 1 finite thickness (two-step propagation).
-constexpr bool geo_disk(int geo) { return (geo & 1) != 0; }
-constexpr bool geo_thick(int geo) { return (geo & 2) != 0; }
 
 // kOwn rows of owner data per lane: 3 on thin layers ({x, y, z or r, chi2},
 // {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}); 8 on thick ones, where every
@@ -445,7 +448,7 @@ struct SearchLdsT {
     int mark[kWave];         // run starting at each pair slot of the current round
 };
 template <int kGeo>
-using SearchLds = SearchLdsT<geo_thick(kGeo) ? 8 : 3>;
+using SearchLds = SearchLdsT<geo_xyz(kGeo) ? 8 : 3>;
 
 // LDS written by some lanes of a wavefront and read by others: the wavefront's
 // LDS operations are executed in order, so it only takes a compiler barrier
@@ -476,7 +479,7 @@ __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
 template <int K, bool kStats, int kGeo>
 struct WaveSearch {
     static constexpr bool kDisk = geo_disk(kGeo);
-    static constexpr bool kThick = geo_thick(kGeo);
+    static constexpr bool kXyz = geo_xyz(kGeo);
     SearchLds<kGeo> &W;
     const float4 *bh;
     const Params &P;
@@ -547,7 +550,7 @@ struct WaveSearch {
             float tot = 0.f;
             unsigned hid = 0;
             if (valid) {
-                if constexpr (!kThick) {
+                if constexpr (!kXyz) {
                     const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
                     const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
                     if (kStats) {
@@ -584,10 +587,12 @@ struct WaveSearch {
                                              : step_near_cyl(p, tg, rh, P.w_per_qpt, np, F, sn, cn);
                     transport_pos<kDisk>(F, c, cp);
                     const float ch = hv.x * irh, sh = hv.y * irh;
-                    const float c2 = kDisk ? hit_chi2_disk(np[0], np[1], cp[0], cp[1], cp[2], ch, sh, rh, P.var_u,
-                                                           P.var_r)
-                                           : hit_chi2(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], ch,
-                                                      sh, hv.z, P.var_u, P.var_z);
+                    const float c2 =
+                        P.update3d ? hit_chi2_3d(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], hv.x,
+                                                 hv.y, hv.z, P.var_u, P.var_r, P.var_z)
+                        : kDisk    ? hit_chi2_disk(np[0], np[1], cp[0], cp[1], cp[2], ch, sh, rh, P.var_u, P.var_r)
+                                   : hit_chi2(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], ch, sh,
+                                              hv.z, P.var_u, P.var_z);
                     if (kStats) {
                         cnt.scan++;
                         if (fwd && reach) cnt.chi2++;
@@ -694,14 +699,14 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
                                             const DevEvent &E, int lane, SearchLds<kGeo> &W,
                                             unsigned long long (&lk)[K], Count &cnt)
 {
-    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
+    constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
     int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
     float du = 0.f, dz = 0.f, g2 = pp[2];
     if (predicted) {
         const float phipos = fast_atan2(pp[1], pp[0]);
         float lo, hi, g2lo, g2hi;   // azimuth offsets from phipos, second-coordinate range
         bool finite = isfinite(phipos);
-        if constexpr (!kThick) {
+        if constexpr (!kXyz) {
             float xr;
             window_at<kDisk>(P, pp[0], pp[1], pp[2], pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(2, 2)],
                              lp.inv_r, P.win_scale, du, dz, g2, xr);
@@ -774,7 +779,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
             }
         }
     }
-    if constexpr (!kThick) {
+    if constexpr (!kXyz) {
         W.own[0][lane] = make_float4(pp[0], pp[1], g2, chi2);
         W.own[1][lane] = make_float4(pc[sym(0, 0)], pc[sym(0, 1)], pc[sym(1, 1)], pc[sym(0, 2)]);
         W.own[2][lane] = make_float4(pc[sym(1, 2)], pc[sym(2, 2)], du, dz);
@@ -840,7 +845,7 @@ template <int G, bool kStats, int kGeo>
 __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
                                            const int lane, const Hist &H, SearchLds<kGeo> &W, Count &cnt)
 {
-    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
+    constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
     constexpr int K = G;     // a parent contributes at most max_cands <= G children
     const int gbase = (lane / G) * G;
     const int slot = lane - gbase;
@@ -937,7 +942,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     S.stopped = p_stopped;
     S.status = p_status;
     if (with_hit) {
-        if constexpr (!kThick) {
+        if constexpr (!kXyz) {
             kf_update<kDisk>(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
         } else {
             // second step to the hit's own surface, then the update there
@@ -951,8 +956,9 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
             for (int i = 0; i < 6; ++i) S.p[i] = np[i];
             S.tg.sph = sn;
             S.tg.cph = cn;
-            kf_update<kDisk>(S.p, S.c, S.tg, hv.x * irh, hv.y * irh, kDisk ? rh : hv.z, P.var_u,
-                             kDisk ? P.var_r : P.var_z);
+            if (P.update3d) kf_update_3d<false>(S.p, S.c, S.tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+            else kf_update<kDisk>(S.p, S.c, S.tg, hv.x * irh, hv.y * irh, kDisk ? rh : hv.z, P.var_u,
+                                  kDisk ? P.var_r : P.var_z);
         }
         if (kStats) cnt.upd++;
         H.put(L, lane, (int)hid, parent);
@@ -1123,13 +1129,13 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
     chi2 = 0.f;
     nupd = 0;
     status = 0;
-    constexpr bool kDisk = geo_disk(kGeo), kThick = geo_thick(kGeo);
+    constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
     Trig tg = trig_of(p);
     for (int L = 0; L < P.n_layers; ++L) {
         const int h = hit_of(L);
         float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
         float where = kDisk ? P.layer[L].zplane : P.layer[L].r;
-        if constexpr (kThick) {
+        if constexpr (kXyz) {
             // the hit carries (x, y, z): its own surface is the target (the
             // two steps composed)
             if (h >= 0) {
@@ -1153,7 +1159,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
         }
         if (h >= 0) {
             float ch, sh, g2h;
-            if constexpr (kThick) {
+            if constexpr (kXyz) {
                 const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
                 const float irh = fast_rcp(rh);
                 ch = hv.x * irh;
@@ -1167,7 +1173,8 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
             }
             // Joseph form: a fit starts from a wide prior, where the plain
             // form C - K H C would lose FP32 digits
-            chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
+            if (kXyz && P.update3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+            else chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
             ++nupd;
 #pragma unroll
             for (int i = 0; i < 6; ++i) op[i] = p[i];
@@ -1391,7 +1398,7 @@ hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
 
 size_t build_lds_bytes(int geo, int n_layers, int wpb)
 {
-    const size_t search = geo_thick(geo) ? sizeof(SearchLds<2>) : sizeof(SearchLds<0>);
+    const size_t search = geo_xyz(geo) ? sizeof(SearchLds<2>) : sizeof(SearchLds<0>);
     return sizeof(int) * (size_t)search_lds_offset(wpb, n_layers) + (size_t)wpb * search;
 }
 

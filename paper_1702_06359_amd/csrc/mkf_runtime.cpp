@@ -205,7 +205,8 @@ void derive_params(mkf_ctx *ctx)
     P.max_cands = c.max_cands;
     P.max_holes = c.max_holes;
     P.hole_always = (c.flags & MKF_HOLE_ALWAYS) ? 1 : 0;
-    P.geo = (c.layer_kind[0] == 1 ? 1 : 0) | (c.layer_thickness[0] > 0.0 ? 2 : 0);
+    P.update3d = (c.flags & MKF_UPDATE_3D) ? 1 : 0;
+    P.geo = (c.layer_kind[0] == 1 ? 1 : 0) | (c.layer_thickness[0] > 0.0 || P.update3d ? 2 : 0);
     P.bins_phi = t.bins_phi;
     P.bins_z = t.bins_z;
     P.w_per_qpt = (float)(-0.00299792458 * c.bz);
@@ -224,7 +225,7 @@ mkf_status check_config(const mkf_config *c)
         return fail(MKF_E_INVALID, "need 1 <= n_seed_layers < n_layers <= %d", kMaxLayers);
     if (c->max_cands < 1 || c->max_cands > kMaxCands) return fail(MKF_E_INVALID, "max_cands must be 1..%d", kMaxCands);
     if (c->max_holes < 0 || c->max_holes > 7) return fail(MKF_E_INVALID, "max_holes must be 0..7");
-    if (c->flags & ~MKF_HOLE_ALWAYS) return fail(MKF_E_INVALID, "unknown config flags");
+    if (c->flags & ~(MKF_HOLE_ALWAYS | MKF_UPDATE_3D)) return fail(MKF_E_INVALID, "unknown config flags");
     bool any_disk = false;
     for (int L = 0; L < c->n_layers; ++L) {
         const int kind = c->layer_kind[L];
@@ -244,8 +245,8 @@ mkf_status check_config(const mkf_config *c)
         }
         if (!(c->layer_x0[L] >= 0) || !std::isfinite(c->layer_x0[L])) return fail(MKF_E_INVALID, "layer_x0 must be >= 0");
     }
-    if (any_disk && (!(c->sigma_r > 0) || !std::isfinite(c->sigma_r)))
-        return fail(MKF_E_INVALID, "sigma_r must be positive when a disk exists");
+    if ((any_disk || (c->flags & MKF_UPDATE_3D)) && (!(c->sigma_r > 0) || !std::isfinite(c->sigma_r)))
+        return fail(MKF_E_INVALID, "sigma_r must be positive with a disk or the 3x3 measurement");
     for (int L = 1; L < c->n_layers; ++L)
         if (c->layer_kind[L] != c->layer_kind[0])
             return fail(MKF_E_INVALID, "layers must be all cylinders or all disks (mixed lists are not supported)");

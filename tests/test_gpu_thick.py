@@ -1,5 +1,6 @@
-"""GPU two-step building and fitting on layers of finite thickness against
-the FP64 oracle (barrel cylinders and endcap disks).
+"""GPU two-step building and fitting on layers of finite thickness, and the
+3x3 global-Cartesian measurement, against the FP64 oracle (barrel cylinders
+and endcap disks).
 
 Same protocol as the thin-layer tests: identical hit lists for every seed
 the oracle does not flag as tie-sensitive, states and covariances within the
@@ -153,5 +154,46 @@ def test_mixed_thickness_is_rejected(gpu_required):
         abi.Context(cfg)
     cfg = abi.config_from_geometry(BARREL, max_cands=2)
     cfg.layer_thickness[0] = 9.0          # deeper than twice the radius
+    with pytest.raises(abi.MkfError):
+        abi.Context(cfg)
+
+
+@pytest.mark.parametrize("name,g", [("thin_barrel", synth.Geometry()), ("thick_endcap", ENDCAP)])
+def test_update3d_build_parity(gpu_required, name, g):
+    """The 3x3 global-Cartesian measurement (MKF_UPDATE_3D) in the build."""
+    ev = synth.make_event(2003, cfg=246, event=0, geometry=g, noise=0.3)
+    print(f"case update3d {name} ckf n=2003 k=6", flush=True)
+    c = abi.Context(abi.config_from_geometry(g, max_cands=6, update3d=True))
+    try:
+        h = c.load_event(ev)
+        a = c.build(h, ev.n_seeds)
+        b = c.build_batch([h], [ev.n_seeds])[0]
+    finally:
+        c.close()
+    _equal(a, b)
+    cfg = oracle.config(g, max_cands=6, update3d=True)
+    o = oracle.build_tracks(cfg, ev.hits, ev.seed_par, ev.seed_cov, ev.seed_hits, n_threads=8)
+    rep = compare_build(a, o, cfg, ev.hits, ev.seed_par, ev.seed_cov)
+    report(f"update3d_{name}_ckf_2003", rep)
+    assert_build_parity(rep)
+
+
+@pytest.mark.parametrize("name,g", [("thin_barrel", synth.Geometry()), ("thick_barrel", BARREL)])
+def test_update3d_fit_parity(gpu_required, name, g):
+    ev = synth.make_event(3001, cfg=247, event=0, geometry=g, noise=0.1)
+    print(f"case update3d {name} fit n=3001", flush=True)
+    c = abi.Context(abi.config_from_geometry(g, max_cands=6, update3d=True))
+    try:
+        h = c.load_event(abi.EventArrays(ev.hits))
+        out = c.fit(h, ev.prior_par, ev.prior_cov, ev.truth_hit)
+    finally:
+        c.close()
+    o = oracle.fit(oracle.config(g, update3d=True), ev.hits, ev.prior_par, ev.prior_cov, ev.truth_hit, n_threads=8)
+    _check(f"update3d_{name}_fit", out, o, prior_cov=ev.prior_cov, disk=g.is_disk)
+
+
+def test_update3d_needs_sigma_r(gpu_required):
+    cfg = abi.config_from_geometry(synth.Geometry(), max_cands=2, update3d=True)
+    cfg.sigma_r = 0.0
     with pytest.raises(abi.MkfError):
         abi.Context(cfg)
