@@ -187,7 +187,7 @@ def workload_ckf(args):
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
-                "traffic": measured_traffic("k_build_batch<6,false>") if tuning["lanes_per_seed"] == 6 else None,
+                "traffic": measured_traffic("k_build_batch<6,false,0>") if tuning["lanes_per_seed"] == 6 else None,
                 "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
                 "flop_per_launch": int(flops), "counters": st}
     # the same steps with the final fit of every built track chained on the device

@@ -18,8 +18,8 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_record_matches_kernel_sources_or_is_withheld(tmp_path, monkeypatch):
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    v = bench.measured_traffic("k_build_batch<6,false>")
-    assert v is None or v == int(round(rec["kernels"]["k_build_batch<6,false>"]["bytes_per_launch"]))
+    v = bench.measured_traffic("k_build_batch<6,false,0>")
+    assert v is None or v == int(round(rec["kernels"]["k_build_batch<6,false,0>"]["bytes_per_launch"]))
     # a record taken on other kernel sources is not reported
     fake = dict(rec, source_sha256="0" * 64)
     (tmp_path / "profiles").mkdir()
@@ -28,7 +28,7 @@ def test_traffic_record_matches_kernel_sources_or_is_withheld(tmp_path, monkeypa
         os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
         (tmp_path / f).write_bytes(open(os.path.join(ROOT, f), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("k_build_batch<6,false>") is None
+    assert bench.measured_traffic("k_build_batch<6,false,0>") is None
 
 
 def test_flop_constants_are_consistent():
