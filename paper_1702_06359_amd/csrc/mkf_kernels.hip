@@ -438,7 +438,8 @@ constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
 // {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}); 8 on thick ones, where every
 // pair carries its candidate to the hit's own surface and so needs the whole
 // predicted state ({x, y, z, chi2}, {q/pT, sin phi, cos phi, sin theta},
-// {cos theta, -, -, C0}, then C1..C20).
+// {cos theta, phi, theta, C0}, then C1..C20), from which the kept children
+// also take their parent's state.
 template <int kOwn>
 struct SearchLdsT {
     float4 own[kOwn][kWave];
@@ -786,7 +787,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     } else {
         W.own[0][lane] = make_float4(pp[0], pp[1], pp[2], chi2);
         W.own[1][lane] = make_float4(pp[3], tg.sph, tg.cph, tg.sth);
-        W.own[2][lane] = make_float4(tg.cth, 0.f, 0.f, pc[0]);
+        W.own[2][lane] = make_float4(tg.cth, pp[4], pp[5], pc[0]);
 #pragma unroll
         for (int i = 0; i < 5; ++i)
             W.own[3 + i][lane] = make_float4(pc[1 + 4 * i], pc[2 + 4 * i], pc[3 + 4 * i], pc[4 + 4 * i]);
@@ -923,14 +924,36 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const bool with_hit = alive && hid != kHoleId;
     float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
     if (with_hit) hv = load_global(E.hits + E.layer_off[L] + (int)hid);   // in flight during the shuffles
+    if constexpr (!kXyz) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
+        for (int i = 0; i < 6; ++i) S.p[i] = __shfl(S.p[i], src);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) S.c[i] = __shfl(S.c[i], src);
-    S.tg.sph = __shfl(S.tg.sph, src);
-    S.tg.cph = __shfl(S.tg.cph, src);
-    S.tg.sth = __shfl(S.tg.sth, src);
-    S.tg.cth = __shfl(S.tg.cth, src);
+        for (int i = 0; i < 21; ++i) S.c[i] = __shfl(S.c[i], src);
+        S.tg.sph = __shfl(S.tg.sph, src);
+        S.tg.cph = __shfl(S.tg.cph, src);
+        S.tg.sth = __shfl(S.tg.sth, src);
+        S.tg.cth = __shfl(S.tg.cth, src);
+    } else {
+        // the whole prediction of every lane is still in the search LDS, so
+        // no lane keeps its state in registers through the search
+        const float4 r0 = W.own[0][src], r1 = W.own[1][src], r2 = W.own[2][src];
+        S.p[0] = r0.x;
+        S.p[1] = r0.y;
+        S.p[2] = r0.z;
+        S.p[3] = r1.x;
+        S.p[4] = r2.y;
+        S.p[5] = r2.z;
+        S.tg = Trig{r1.y, r1.z, r1.w, r2.x};
+        S.c[0] = r2.w;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const float4 v = W.own[3 + i][src];
+            S.c[1 + 4 * i] = v.x;
+            S.c[2 + 4 * i] = v.y;
+            S.c[3 + 4 * i] = v.z;
+            S.c[4 + 4 * i] = v.w;
+        }
+    }
     const int p_holes = __shfl(S.n_holes, src);
     const int p_stopped = __shfl(S.stopped, src);
     const int p_status = __shfl(S.status, src);
@@ -1021,7 +1044,7 @@ __host__ __device__ constexpr int search_lds_offset(int waves, int n_layers)
 // seeds) - from a device counter when persistent, else from its block index -
 // and runs every building layer of its seeds with the state in registers.
 template <int G, bool kStats, int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_batch(const Params P, const BatchArgs B, int persistent)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_build_batch(const Params P, const BatchArgs B, int persistent)
 {
     extern __shared__ int s_dyn[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -1057,7 +1080,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // Per-layer builder: one event, one layer per launch, candidate state in
 // device memory (structure of arrays, slot = seed * G + rank) between layers.
 template <int G, bool kStats, int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
 {
     const DevEvent &E = *Ep;
     const int lane = threadIdx.x & (kWave - 1);
@@ -1129,7 +1152,9 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
     chi2 = 0.f;
     nupd = 0;
     status = 0;
-    constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
+    // bit 2 of kGeo: the 3x3 measurement (fit kernels only; the build kernels
+    // test it at run time)
+    constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo), kFit3d = (kGeo & 4) != 0;
     Trig tg = trig_of(p);
     for (int L = 0; L < P.n_layers; ++L) {
         const int h = hit_of(L);
@@ -1160,6 +1185,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
         if (h >= 0) {
             float ch, sh, g2h;
             if constexpr (kXyz) {
+                hv = load_global(E.hits + E.layer_off[L] + h);   // again: short live range across the step
                 const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
                 const float irh = fast_rcp(rh);
                 ch = hv.x * irh;
@@ -1173,7 +1199,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
             }
             // Joseph form: a fit starts from a wide prior, where the plain
             // form C - K H C would lose FP32 digits
-            if (kXyz && P.update3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+            if (kFit3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
             else chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
             ++nupd;
 #pragma unroll
@@ -1186,7 +1212,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
 
 // Fit with known hits: one lane per track, no branching beyond skipped layers.
 template <int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_fit(const Params P, const BatchArgs B)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_fit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= B.total_tracks) return;
@@ -1275,7 +1301,7 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
 // Final fit of every built track of a batch (after the build): one lane per
 // seed, hits from the build's output.
 template <int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_refit(const Params P, const BatchArgs B)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_refit(const Params P, const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= B.total_seeds) return;
@@ -1475,11 +1501,13 @@ hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_seeds <= 0) return hipSuccess;
     const unsigned grid = blocks_for(b.total_seeds, 256);
-    switch (p.geo) {
+    switch (p.geo | (p.update3d ? 4 : 0)) {
     case 0: k_refit<0><<<grid, 256, 0, s>>>(p, b); break;
     case 1: k_refit<1><<<grid, 256, 0, s>>>(p, b); break;
     case 2: k_refit<2><<<grid, 256, 0, s>>>(p, b); break;
     case 3: k_refit<3><<<grid, 256, 0, s>>>(p, b); break;
+    case 6: k_refit<6><<<grid, 256, 0, s>>>(p, b); break;
+    case 7: k_refit<7><<<grid, 256, 0, s>>>(p, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1489,11 +1517,13 @@ hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_tracks <= 0) return hipSuccess;
     const unsigned grid = blocks_for(b.total_tracks, 256);
-    switch (p.geo) {
+    switch (p.geo | (p.update3d ? 4 : 0)) {
     case 0: k_fit<0><<<grid, 256, 0, s>>>(p, b); break;
     case 1: k_fit<1><<<grid, 256, 0, s>>>(p, b); break;
     case 2: k_fit<2><<<grid, 256, 0, s>>>(p, b); break;
     case 3: k_fit<3><<<grid, 256, 0, s>>>(p, b); break;
+    case 6: k_fit<6><<<grid, 256, 0, s>>>(p, b); break;
+    case 7: k_fit<7><<<grid, 256, 0, s>>>(p, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
