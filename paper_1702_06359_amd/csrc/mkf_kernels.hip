@@ -142,57 +142,76 @@ __global__ void __launch_bounds__(256) k_index_bin(const Params P, const BatchAr
     }
 }
 
-// Ranks and bin offsets of a layer whose bin counters fit in LDS (between
-// k_index_bin and k_index_scatter): one 1024-thread block per (event, layer)
-// ranks its hits in their bins with LDS atomics and scans the counts in LDS,
-// so there is no device-wide atomic and no count array to clear.  kShort
-// packs two 16-bit counters per word (layers of at most 65,535 hits).
+// Ranks and bin offsets of a layer (between k_index_bin and
+// k_index_scatter), its bins split into `nsplit` ranges of `chunk` bins (a
+// multiple of 64): one 1024-thread block per (event, layer, range) reads the
+// bin of every hit of the layer, ranks those in its range with LDS atomics,
+// counts those below it, and scans its range's counts in LDS into absolute
+// offsets.  No device-wide atomic, no count array to clear, and no block
+// waits for another; the split fills the machine when a batch has few
+// (event, layer) pairs.  kShort packs two 16-bit counters per word (layers of
+// at most 65,535 hits).
 template <bool kShort>
-__global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchArgs B)
+__global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchArgs B, int nsplit, int chunk)
 {
     extern __shared__ unsigned s_cnt[];
     __shared__ int s_wave[16];
-    const int e = blockIdx.x / P.n_layers;
-    const int L = blockIdx.x - e * P.n_layers;
+    const int part = blockIdx.x % nsplit;
+    const int el = blockIdx.x / nsplit;
+    const int e = el / P.n_layers;
+    const int L = el - e * P.n_layers;
     const DevEvent &E = B.events[e];
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const int nb = P.bins_phi * P.bins_z;
-    const int nw = kShort ? (nb + 1) / 2 : nb;
+    int *off = E.bin_off + L * (nb + 1);
+    if (part == nsplit - 1 && threadIdx.x == 0) off[nb] = h1;
+    const int lo = part * chunk;
+    if (lo >= nb) return;                     // an empty range (whole block)
+    const int nr = min(chunk, nb - lo);       // bins of this range
+    const int nw = kShort ? (nr + 1) / 2 : nr;
     for (int i = threadIdx.x; i < nw; i += blockDim.x) s_cnt[i] = 0u;
     __syncthreads();
     // four hits per thread and step, their loads issued together
     constexpr int kU = 4;
     const int stride = blockDim.x;
+    int below = 0;   // hits of this thread in bins before the range
     for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
         int bins[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) bins[u] = load_global(E.bin_of + min(h + u * stride, h1 - 1));
         int rank[kU];   // all atomics of the step in flight before their results are stored
+        bool mine[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int bin = bins[u];
+            const int bin = bins[u] - lo;
             const bool in = h + u * stride < h1;
+            mine[u] = in && bin >= 0 && bin < nr;
+            below += (in && bin < 0) ? 1 : 0;
             if (kShort) {
                 const int sh = (bin & 1) * 16;
-                rank[u] = in ? (int)((atomicAdd(&s_cnt[bin >> 1], 1u << sh) >> sh) & 0xFFFFu) : 0;
+                rank[u] = mine[u] ? (int)((atomicAdd(&s_cnt[bin >> 1], 1u << sh) >> sh) & 0xFFFFu) : 0;
             } else {
-                rank[u] = in ? (int)atomicAdd(&s_cnt[bin], 1u) : 0;
+                rank[u] = mine[u] ? (int)atomicAdd(&s_cnt[bin], 1u) : 0;
             }
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
-            if (h + u * stride < h1) store_global(E.bin_rank + h + u * stride, rank[u]);
+            if (mine[u]) store_global(E.bin_rank + h + u * stride, rank[u]);
     }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    // block sum of `below`: the offset of the range's first bin in the layer
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if (lane == 0) s_wave[wave] = below;
     __syncthreads();
-    // exclusive scan of the counts into offsets relative to the layer, kept
-    // in LDS (same packing) and written out absolute; each thread owns 32
+    int carry = 0;
+    for (int w = 0; w < n_waves; ++w) carry += s_wave[w];
+    __syncthreads();
+    // exclusive scan of the counts, written out absolute; each thread owns 32
     // consecutive bins (one step for up to 32,768 bins)
     constexpr int kPer = 32;
     constexpr int kWords = kShort ? kPer / 2 : kPer;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    int *off = E.bin_off + L * (nb + 1);
-    int carry = 0;
-    for (int base = 0; base < nb; base += blockDim.x * kPer) {
+    for (int base = 0; base < nr; base += blockDim.x * kPer) {
         const int b0 = base + threadIdx.x * kPer;   // a multiple of 32: its words are 16-byte aligned
         const int w0 = kShort ? b0 / 2 : b0;
         unsigned w[kWords];
@@ -209,7 +228,7 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
         int v[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
-            v[j] = b0 + j >= nb ? 0 : kShort ? (int)((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) : (int)w[j];
+            v[j] = b0 + j >= nr ? 0 : kShort ? (int)((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) : (int)w[j];
         int sum = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) sum += v[j];
@@ -234,29 +253,12 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
         int run = carry + (wave > 0 ? s_wave[wave - 1] : 0) + x - sum;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const int r = run;
+            if (b0 + j < nr) store_global(off + lo + b0 + j, h0 + run);
             run += v[j];
-            if (kShort) {
-                if (j & 1) w[j >> 1] |= (unsigned)r << 16;
-                else w[j >> 1] = (unsigned)r;
-            } else {
-                w[j] = (unsigned)r;
-            }
-            if (b0 + j < nb) store_global(off + b0 + j, h0 + r);
-        }
-        if (w0 + kWords <= nw) {
-#pragma unroll
-            for (int j = 0; j < kWords; j += 4)
-                *reinterpret_cast<uint4 *>(s_cnt + w0 + j) = make_uint4(w[j], w[j + 1], w[j + 2], w[j + 3]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < kWords; ++j)
-                if (w0 + j < nw) s_cnt[w0 + j] = w[j];
         }
         carry += s_wave[n_waves - 1];
         __syncthreads();
     }
-    if (threadIdx.x == 0) off[nb] = h1;
 }
 
 // Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it and
@@ -1362,6 +1364,20 @@ hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bo
 // lowered to the 64 KB default if a larger launch is refused).
 static std::atomic<int> g_lds_limit[64];
 
+static std::atomic<int> g_cu_count[64];
+
+static int compute_units()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int v = g_cu_count[dev & 63].load();
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        g_cu_count[dev & 63].store(v);
+    }
+    return v;
+}
+
 static size_t lds_per_block()
 {
     int dev = 0;
@@ -1387,7 +1403,12 @@ hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
     const size_t nb = (size_t)p.bins_phi * p.bins_z;
     const size_t lds = lds_per_block();
     const unsigned blocks = (unsigned)(b.n_events * p.n_layers);
-    const bool fits = nb * 4 <= lds || ((nb + 1) / 2 * 4 <= lds && b.max_layer_hits <= 0xFFFF);
+    // bin ranges per (event, layer): about two blocks per compute unit in all
+    const int n_cu = compute_units();
+    const int nsplit = (int)std::max<size_t>(1, std::min<size_t>({(size_t)16, (nb + 63) / 64,
+                                                                  (size_t)(2 * n_cu + blocks - 1) / blocks}));
+    const size_t chunk = ((nb + nsplit - 1) / nsplit + 63) / 64 * 64;
+    const bool fits = chunk * 4 <= lds || (chunk / 2 * 4 <= lds && b.max_layer_hits <= 0xFFFF);
     // chunks per (event, layer): about one hit per thread for the largest
     // layer, striding beyond that
     const dim3 grid(std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256))), blocks);
@@ -1397,13 +1418,13 @@ hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
         if (err != hipSuccess) return err;
     }
     bool ranked = false;
-    if (nb * 4 <= lds) {
-        k_index_lds<false><<<blocks, 1024, nb * 4, s>>>(p, b);
+    if (chunk * 4 <= lds) {
+        k_index_lds<false><<<blocks * nsplit, 1024, chunk * 4, s>>>(p, b, nsplit, (int)chunk);
         ranked = hipGetLastError() == hipSuccess;
         if (!ranked) lds_refused();   // not launched: try a smaller form
     }
-    if (!ranked && (nb + 1) / 2 * 4 <= lds_per_block() && b.max_layer_hits <= 0xFFFF) {
-        k_index_lds<true><<<blocks, 1024, (nb + 1) / 2 * 4, s>>>(p, b);
+    if (!ranked && chunk / 2 * 4 <= lds_per_block() && b.max_layer_hits <= 0xFFFF) {
+        k_index_lds<true><<<blocks * nsplit, 1024, chunk / 2 * 4, s>>>(p, b, nsplit, (int)chunk);
         ranked = hipGetLastError() == hipSuccess;
         if (!ranked) lds_refused();
     }
