@@ -154,3 +154,42 @@ def test_mixed_layer_kinds_are_rejected(gpu_required):
     cfg.sigma_r = 0.0
     with pytest.raises(abi.MkfError):
         abi.Context(cfg)
+
+
+def test_disk_edge_cases(ctx6):
+    """Empty outer disks (hole, then stop), seeds heading away from the next
+    disk (propagation fails: status 2, state kept on the seed's disk), and a
+    disk whose extra hits all sit beyond the grid's outer radius (one edge
+    bin): parity with the oracle in each."""
+    ev = synth.make_event(300, cfg=235, event=0, geometry=GEO, noise=0.2)
+
+    def run(hits, sp):
+        h = ctx6.load_event(abi.EventArrays(hits, sp, ev.seed_cov, ev.seed_hits))
+        try:
+            g = ctx6.build(h, ev.n_seeds)
+            b = ctx6.build_batch([h], [ev.n_seeds])[0]
+        finally:
+            ctx6.unload_event(h)
+        _equal(g, b)
+        e2 = synth.Event(GEO, hits, sp, ev.seed_cov, ev.seed_hits, ev.truth_hit, ev.truth_par, ev.vertex_par,
+                         ev.prior_par, ev.prior_cov, ev.n_noise)
+        cfg, o = _oracle(e2, 6)
+        assert_build_parity(compare_build(g, o, cfg, hits, sp, ev.seed_cov))
+        return g, o
+
+    hits = [x.copy() for x in ev.hits]
+    for L in (7, 8, 9):
+        hits[L] = np.zeros((0, 3))
+    print("case disk edge: empty outer disks", flush=True)
+    g, _ = run(hits, ev.seed_par)
+    assert (g["status"] == 1).all()
+    sp = ev.seed_par.copy()
+    sp[::3, 5] = np.pi - sp[::3, 5]          # every third seed heads to -z
+    print("case disk edge: seeds heading away", flush=True)
+    g, o = run(ev.hits, sp)
+    assert (g["status"][::3] == 2).all() and (o["status"][::3] == 2).all()
+    assert np.allclose(g["par"][::3, 2], GEO.disk_z[2], atol=1e-4)
+    crowd = [x.copy() for x in ev.hits]
+    crowd[5] = np.concatenate([crowd[5], np.tile([[100.0, 0.0, GEO.disk_z[5]]], (5000, 1))])
+    print("case disk edge: crowded outer edge bin", flush=True)
+    run(crowd, ev.seed_par)

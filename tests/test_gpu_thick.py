@@ -197,3 +197,29 @@ def test_update3d_needs_sigma_r(gpu_required):
     cfg.sigma_r = 0.0
     with pytest.raises(abi.MkfError):
         abi.Context(cfg)
+
+
+def test_thick_edge_cases(gpu_required):
+    """Empty outer thick layers (hole, then stop on the average surface) and
+    a layer with 5,000 extra hits in one edge bin: parity with the oracle."""
+    ev = synth.make_event(300, cfg=248, event=0, geometry=BARREL, noise=0.2)
+    c = _ctx(BARREL, 6)
+    try:
+        for name, mod in (("empty outer layers", lambda h: [np.zeros((0, 3)) if L >= 7 else x for L, x in enumerate(h)]),
+                          ("crowded edge bin", lambda h: [np.concatenate([x, np.tile([[20.1, 0.0, 1e4]], (5000, 1))])
+                                                          if L == 5 else x for L, x in enumerate(h)])):
+            hits = mod([x.copy() for x in ev.hits])
+            print(f"case thick edge: {name}", flush=True)
+            h = c.load_event(abi.EventArrays(hits, ev.seed_par, ev.seed_cov, ev.seed_hits))
+            g = c.build(h, ev.n_seeds)
+            c.unload_event(h)
+            e2 = synth.Event(BARREL, hits, ev.seed_par, ev.seed_cov, ev.seed_hits, ev.truth_hit, ev.truth_par,
+                             ev.vertex_par, ev.prior_par, ev.prior_cov, ev.n_noise)
+            cfg, o = _oracle(e2, 6)
+            assert_build_parity(compare_build(g, o, cfg, hits, ev.seed_par, ev.seed_cov))
+            if name == "empty outer layers":
+                assert (g["status"] == 1).all()
+                r = np.hypot(g["par"][:, 0], g["par"][:, 1])
+                assert np.allclose(r, BARREL.radii[8], atol=1e-3)   # hole on 7, stopped on 8
+    finally:
+        c.close()
