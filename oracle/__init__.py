@@ -102,6 +102,9 @@ def lib():
         L.orc_build.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip, ip,
                                 C.c_int32, C.POINTER(OrcTrack), C.c_int32]
         L.orc_replay.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), dp, dp, ip, dp, ip]
+        L.orc_build_beam.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, dp, dp, ip, ip,
+                                     C.c_int32, C.POINTER(OrcTrack), C.POINTER(OrcTrack), C.c_int32]
+        L.orc_build_beam.restype = None
         L.orc_circle_prior.argtypes = [C.POINTER(OrcConfig), C.POINTER(OrcHits), C.c_int32, ip, dp, dp, dp, ip]
         L.orc_circle_prior.restype = None
         L.orc_replay.restype = C.c_double
@@ -298,6 +301,25 @@ def build_tracks(cfg: OrcConfig, hits, seed_par, seed_cov, seed_hits, seed_ids=N
                     _ip(ids) if ids is not None else None, n_sel,
                     out.ctypes.data_as(C.POINTER(OrcTrack)), int(n_threads))
     return out
+
+
+def build_beam(cfg: OrcConfig, hits, seed_par, seed_cov, seed_hits, seed_ids=None, n_threads=1):
+    """As build_tracks, plus the whole final beam: (tracks, beam) with beam of
+    shape (n_sel, max_cands) (status -1 beyond the beam)."""
+    hs = hits if isinstance(hits, HitSet) else HitSet(hits)
+    n_total = int(np.asarray(seed_par).shape[0])
+    sp = _f64(seed_par, (n_total, 6))
+    sc = _f64(seed_cov, (n_total, 21))
+    sh = np.ascontiguousarray(seed_hits, dtype=np.int32).reshape(n_total, cfg.n_seed_layers)
+    ids = None if seed_ids is None else np.ascontiguousarray(seed_ids, dtype=np.int32)
+    n_sel = n_total if ids is None else int(ids.shape[0])
+    k = min(int(cfg.max_cands), MAX_CANDS)
+    out = np.zeros(n_sel, dtype=TRACK_DTYPE)
+    beam = np.zeros(n_sel * k, dtype=TRACK_DTYPE)
+    lib().orc_build_beam(C.byref(cfg), C.byref(hs.s), n_total, _dp(sp), _dp(sc), _ip(sh),
+                         _ip(ids) if ids is not None else None, n_sel, out.ctypes.data_as(C.POINTER(OrcTrack)),
+                         beam.ctypes.data_as(C.POINTER(OrcTrack)), int(n_threads))
+    return out, beam.reshape(n_sel, k)
 
 
 def replay(cfg: OrcConfig, hits, seed_par, seed_cov, layer_hits):

@@ -760,6 +760,7 @@ typedef struct {
     const double *seed_par, *seed_cov;
     const int32_t *seed_hits, *seed_ids;
     orc_track *out;
+    orc_track *beam;    /* optional: [n_sel][max_cands], every rank of the final beam */
 } build_ctx;
 
 static void build_one(void *vctx, int64_t row)
@@ -932,6 +933,30 @@ static void build_one(void *vctx, int64_t row)
     o->n_prop = n_prop;
     o->n_accept = n_accept;
     o->n_update = n_update;
+    if (bc->beam) {
+        /* the whole final beam, rank by rank; ranks beyond it are empty (status -1) */
+        for (int r = 0; r < k; ++r) {
+            orc_track *b = &bc->beam[row * k + r];
+            *b = *o;
+            if (r >= nb) {
+                memset(b->par, 0, sizeof(b->par));
+                memset(b->cov, 0, sizeof(b->cov));
+                b->chi2 = 0.0;
+                for (int L = 0; L < ORC_MAX_LAYERS; ++L) b->hits[L] = -1;
+                b->n_hits = b->n_holes = 0;
+                b->status = -1;
+                continue;
+            }
+            const cand_t *cd = &beam[r];
+            memcpy(b->par, cd->par, sizeof(b->par));
+            pack21(cd->C, b->cov);
+            b->chi2 = cd->chi2;
+            for (int L = 0; L < ORC_MAX_LAYERS; ++L) b->hits[L] = L < nl ? cd->hits[L] : -1;
+            b->n_hits = cd->n_hits;
+            b->n_holes = cd->n_holes;
+            b->status = cd->status;
+        }
+    }
 }
 
 void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total,
@@ -939,7 +964,16 @@ void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_tota
                const int32_t *seed_ids, int32_t n_sel, orc_track *out, int32_t n_threads)
 {
     (void)n_seeds_total;
-    build_ctx bc = {cfg, hits, seed_par, seed_cov, seed_hits, seed_ids, out};
+    build_ctx bc = {cfg, hits, seed_par, seed_cov, seed_hits, seed_ids, out, NULL};
+    parallel_for(n_sel, n_threads, 4, build_one, &bc);
+}
+
+void orc_build_beam(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total, const double *seed_par,
+                    const double *seed_cov, const int32_t *seed_hits, const int32_t *seed_ids, int32_t n_sel,
+                    orc_track *out, orc_track *beam, int32_t n_threads)
+{
+    (void)n_seeds_total;
+    build_ctx bc = {cfg, hits, seed_par, seed_cov, seed_hits, seed_ids, out, beam};
     parallel_for(n_sel, n_threads, 4, build_one, &bc);
 }
 

@@ -141,6 +141,13 @@ void orc_build(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_tota
                const double *seed_par, const double *seed_cov, const int32_t *seed_hits,
                const int32_t *seed_ids, int32_t n_sel, orc_track *out, int32_t n_threads);
 
+/* As orc_build, and also every rank of each seed's final beam:
+ * beam[i * max_cands + r] is rank r of seed seed_ids[i] (par, cov, chi2,
+ * hits, n_hits, n_holes, status; status -1 for ranks beyond the beam). */
+void orc_build_beam(const orc_config *cfg, const orc_hits *hits, int32_t n_seeds_total,
+                    const double *seed_par, const double *seed_cov, const int32_t *seed_hits,
+                    const int32_t *seed_ids, int32_t n_sel, orc_track *out, orc_track *beam, int32_t n_threads);
+
 /* Replay a given hit list for one seed through the building rules: propagate
  * layer by layer, update with the listed hit (or take a hole for -1).  Writes
  * per-layer chi2 (-1 for holes) and returns the summed chi2; *ok is 0 when a

@@ -107,6 +107,16 @@ def test_beam_equals_exhaustive_enumeration_on_tiny_events(rng_seed):
         assert np.allclose(out["par"], best["par"], rtol=1e-12, atol=1e-12)
         if s == 0:
             assert max_live >= 2      # the planted hits really branch the search
+        # nothing was pruned (max_live <= 16), so the whole final beam is every
+        # path, in the beam order
+        _, beam = oracle.build_beam(cfg, hits, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=[s])
+        for r in range(16):
+            if r < len(paths):
+                assert list(beam[0, r]["hits"][:10]) == paths[r]["hits"]
+                assert beam[0, r]["chi2"] == pytest.approx(paths[r]["chi2"], rel=1e-12, abs=1e-12)
+                assert np.allclose(beam[0, r]["par"], paths[r]["par"], rtol=1e-12, atol=1e-12)
+            else:
+                assert beam[0, r]["status"] == -1
 
 
 @pytest.mark.parametrize("rng_seed", [0, 1, 2])
