@@ -197,6 +197,13 @@ void mkf_destroy(mkf_ctx *ctx);
 /* Message of the last failed call on this thread (static storage). */
 const char *mkf_last_error(void);
 
+/* 1 when a device error that leaves the GPU's HIP context unusable (a
+ * faulting kernel: illegal address, launch failure, ...) was seen on the
+ * context's device since the process started; then only mkf_destroy is
+ * meaningful.  Any other MKF_E_DEVICE leaves the context usable.  0 for a
+ * healthy context or NULL. */
+int32_t mkf_ctx_broken(const mkf_ctx *ctx);
+
 /* Change launch shapes (copied).  Loaded events are re-indexed on their next
  * build when the bin grid changes.  MKF_E_INVALID for values out of range. */
 mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t);
@@ -226,6 +233,7 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
                                     NULL); results, counters and timers are final after mkf_sync or
                                     any call that waits for the stream (fetch, stats, timers) */
 #define MKF_BATCH_FIT 0x10u      /* then fit every built track on the device (mkf_fetch_fit) */
+#define MKF_BATCH_BEAM 0x20u     /* also keep every rank of each seed's final beam (mkf_fetch_beam) */
 
 /* Batched builder: all listed events in one launch whose waves each take
  * (event, seed group) work items - one per wave as the hardware dispatches
@@ -252,6 +260,16 @@ mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
  * hit on one of layers 0-2, or collinear points: no prior, nothing fitted).
  * Waits for the stream.  Errors: MKF_E_INVALID, MKF_E_NOTFOUND, MKF_E_DEVICE. */
 mkf_status mkf_fetch_fit(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
+
+/* Every rank of each seed's final beam from the last mkf_build_batch with
+ * MKF_BATCH_BEAM (Section 3.2.1: up to max_cands candidates survive each
+ * layer; the build's output is rank 0).  out->n must equal n_seeds *
+ * max_cands; row seed * max_cands + r is rank r, in the beam order (n_hits
+ * descending, chi2 ascending), with the same fields as mkf_build's output;
+ * ranks beyond the beam have status -1, no hits (-1) and ndof 0.  Waits for
+ * the stream.  Errors: MKF_E_INVALID (NULL, wrong n), MKF_E_NOTFOUND,
+ * MKF_E_STATE (no build of this event kept its beam), MKF_E_DEVICE. */
+mkf_status mkf_fetch_beam(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 
 /* Work counters of the last build of an event. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out);

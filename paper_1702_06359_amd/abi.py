@@ -25,7 +25,7 @@ MAX_CANDS = 8
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_AGAIN, E_NOTFOUND, E_STATE = 0, -1, -2, -3, -4, -5, -6
 HOLE_ALWAYS = 0x1
 UPDATE_3D = 0x2
-BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC, BATCH_FIT = 0x1, 0x2, 0x4, 0x8, 0x10
+BATCH_REINDEX, BATCH_STATS, BATCH_GRAPH, BATCH_ASYNC, BATCH_FIT, BATCH_BEAM = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 TIMER_BUILD, TIMER_INDEX, TIMER_FIT = 0, 1, 2
 
 _STATUS_NAMES = {0: "MKF_OK", -1: "MKF_E_INVALID", -2: "MKF_E_NOMEM", -3: "MKF_E_DEVICE",
@@ -111,6 +111,8 @@ _PROTOS = {
     "mkf_build_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
     "mkf_fetch_tracks": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_fetch_fit": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
+    "mkf_fetch_beam": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
+    "mkf_ctx_broken": (C.c_int32, [_ctx_p]),
     "mkf_get_stats": (C.c_int, [_ctx_p, C.c_int32, _P(BuildStats)]),
     "mkf_fit": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_double), _P(C.c_double), _P(C.c_int32),
                           _P(Tracks)]),
@@ -373,6 +375,18 @@ class Context:
         out = TrackArrays(n_seeds, self.n_layers)
         check(lib().mkf_fetch_fit(self.h, int(handle), C.byref(out.tracks)))
         return out.as_dict()
+
+    def broken(self) -> bool:
+        """True once a device fault made the GPU's context unusable."""
+        return bool(lib().mkf_ctx_broken(self.h))
+
+    def fetch_beam(self, handle: int, n_seeds: int):
+        """Every rank of each seed's final beam (after build_batch with
+        BATCH_BEAM): arrays of shape (n_seeds, max_cands, ...)."""
+        k = int(self.config.max_cands)
+        out = TrackArrays(n_seeds * k, self.n_layers)
+        check(lib().mkf_fetch_beam(self.h, int(handle), C.byref(out.tracks)))
+        return {name: v.reshape((n_seeds, k) + v.shape[1:]) for name, v in out.as_dict().items()}
 
     def get_stats(self, handle: int) -> Dict[str, int]:
         s = BuildStats()

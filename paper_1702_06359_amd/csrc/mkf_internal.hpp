@@ -91,6 +91,14 @@ struct DevEvent {
     double *rf_chi2;                     // [n_seeds]
     int *rf_nupd;                        // [n_seeds]
     int *rf_status;                      // [n_seeds]
+    // the whole final beam (set only for a build that asks for it; null otherwise)
+    double *beam_par;                    // [n_seeds * max_cands][6]
+    double *beam_cov;                    // [n_seeds * max_cands][21]
+    int *beam_hits;                      // [n_seeds * max_cands][n_layers]
+    int *beam_nhits;
+    int *beam_nholes;
+    double *beam_chi2;
+    int *beam_status;                    // -1: no candidate at that rank
     unsigned long long *stats;           // [5] mkf_build_stats counters
     // plain per-layer builder state (slots = n_seeds * lanes_per_seed)
     float *st_par;                       // [6][slots]

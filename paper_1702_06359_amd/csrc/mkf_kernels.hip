@@ -1000,6 +1000,27 @@ __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, co
                                               int seed, const Hist &H)
 {
     const int gbase = (lane / G) * G;
+    if (E.beam_par && lane < (kWave / G) * G && seed < E.n_seeds && lane - gbase < P.max_cands) {
+        // every rank of the final beam: rank r sits in lane gbase + r
+        const int r = lane - gbase;
+        const size_t b = (size_t)seed * P.max_cands + r;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) store_global(E.beam_par + 6 * b + i, S.live ? (double)S.p[i] : 0.0);
+#pragma unroll
+        for (int i = 0; i < 21; ++i) store_global(E.beam_cov + 21 * b + i, S.live ? (double)S.c[i] : 0.0);
+        store_global(E.beam_chi2 + b, S.live ? (double)S.chi2 : 0.0);
+        store_global(E.beam_nhits + b, S.live ? S.n_hits : 0);
+        store_global(E.beam_nholes + b, S.live ? S.n_holes : 0);
+        store_global(E.beam_status + b, S.live ? S.status : -1);
+        int *bh = E.beam_hits + b * P.n_layers;
+        for (int L = 0; L < P.n_seed_layers; ++L)
+            store_global(bh + L, S.live ? load_global(E.seed_hits + (size_t)seed * P.n_seed_layers + L) : -1);
+        int cur = r;
+        for (int L = P.n_layers - 1; L >= P.n_seed_layers; --L) {
+            store_global(bh + L, S.live ? H.hit[L * H.stride + gbase + cur] : -1);
+            if (S.live) cur = H.par[L * H.stride + gbase + cur];
+        }
+    }
     if (lane != gbase || seed >= E.n_seeds) return;
     const size_t s = (size_t)seed;
 #pragma unroll

@@ -22,6 +22,26 @@ mkf_status fail(mkf_status st, const char *fmt, ...)
 
 // ---------------------------------------------------------------- memory
 
+static std::atomic<unsigned long long> g_broken{0};   // one bit per device
+
+void note_device_error(hipError_t e)
+{
+    switch (e) {
+    case hipErrorIllegalAddress:
+    case hipErrorLaunchFailure:
+    case hipErrorAssert: {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        g_broken.fetch_or(1ull << (dev & 63));
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+bool device_broken(int device) { return (g_broken.load() >> (device & 63)) & 1ull; }
+
 void *CtxHeap::alloc(size_t bytes)
 {
     if (bytes == 0) bytes = 256;
@@ -555,7 +575,32 @@ void destroy_event(mkf_ctx *ctx, EventRec *rec)
     rec->heap->release(rec->plain);
     rec->heap->release(rec->index);
     rec->heap->release(rec->data);
-    rec->plain = rec->index = rec->data = nullptr;
+    rec->heap->release(rec->beam);
+    rec->plain = rec->index = rec->data = rec->beam = nullptr;
+}
+
+// Storage for every rank of the final beam of an event (max_cands per seed).
+mkf_status ensure_beam(mkf_ctx *ctx, EventRec *rec)
+{
+    if (rec->beam) return MKF_OK;
+    const size_t n = (size_t)rec->shape.n_seeds * ctx->cfg.max_cands, nl = (size_t)rec->shape.n_layers;
+    auto carve = [&](void *base) {
+        Carver c(base);
+        DevEvent &v = rec->beam_view;
+        v.beam_par = c.take<double>(6 * n);
+        v.beam_cov = c.take<double>(21 * n);
+        v.beam_chi2 = c.take<double>(n);
+        v.beam_hits = c.take<int>(nl * n);
+        v.beam_nhits = c.take<int>(n);
+        v.beam_nholes = c.take<int>(n);
+        v.beam_status = c.take<int>(n);
+        return c.off;
+    };
+    const size_t bytes = carve(nullptr);
+    rec->beam = rec->heap->alloc(bytes);
+    if (!rec->beam) return fail(MKF_E_NOMEM, "final beam: %zu bytes", bytes);
+    carve(rec->beam);
+    return MKF_OK;
 }
 
 // Make sure the event's index tables match the current bin grid.  *rebuilt is
@@ -584,7 +629,7 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t 
 }
 
 mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
-                       BatchArgs *args, hipStream_t s)
+                       BatchArgs *args, hipStream_t s, bool beam)
 {
     const int n = (int)recs.size();
     size_t off = 0;
@@ -612,6 +657,16 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
         const EventShape &sh = recs[i]->shape;
         for (int L = 0; L < sh.n_layers; ++L) max_layer = std::max(max_layer, sh.layer_off[L + 1] - sh.layer_off[L]);
         ev[i] = recs[i]->view;
+        if (beam) {   // this build also writes every rank of the final beam
+            const DevEvent &b = recs[i]->beam_view;
+            ev[i].beam_par = b.beam_par;
+            ev[i].beam_cov = b.beam_cov;
+            ev[i].beam_hits = b.beam_hits;
+            ev[i].beam_nhits = b.beam_nhits;
+            ev[i].beam_nholes = b.beam_nholes;
+            ev[i].beam_chi2 = b.beam_chi2;
+            ev[i].beam_status = b.beam_status;
+        }
         ip[i] = (int)items;
         hp[i] = (int)hits;
         tp[i] = (int)trks;
@@ -743,6 +798,8 @@ extern "C" {
 const char *mkf_version(void) { return "mkf 0.1 (gfx950, FP32 Kalman filter)"; }
 
 const char *mkf_last_error(void) { return g_err; }
+
+int32_t mkf_ctx_broken(const mkf_ctx *ctx) { return ctx && device_broken(ctx->device) ? 1 : 0; }
 
 mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *hip_stream, mkf_ctx **out)
 {
@@ -959,8 +1016,10 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
 mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags, mkf_tracks *outs)
 {
     if (!ctx) return fail(MKF_E_INVALID, "NULL context");
-    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH | MKF_BATCH_ASYNC | MKF_BATCH_FIT))
+    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_GRAPH | MKF_BATCH_ASYNC | MKF_BATCH_FIT |
+                  MKF_BATCH_BEAM))
         return fail(MKF_E_INVALID, "unknown flags");
+    const bool beam = flags & MKF_BATCH_BEAM;
     const bool async = flags & MKF_BATCH_ASYNC;
     flags &= ~MKF_BATCH_ASYNC;
     if (async && outs) return fail(MKF_E_INVALID, "an asynchronous batch returns no host outputs (outs must be NULL)");
@@ -971,6 +1030,9 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
         for (int i = 0; i < n; ++i)
             if ((st = check_tracks(&outs[i], recs[i]->shape.n_seeds, "build_batch")) != MKF_OK) return st;
     if (n == 0) return MKF_OK;
+    if (beam)
+        for (EventRec *r : recs)
+            if ((st = ensure_beam(ctx, r)) != MKF_OK) return st;
     bool need_index = false;
     if ((st = reindex_if_needed(ctx, recs, &need_index)) != MKF_OK) return st;
     if (need_index) flags |= MKF_BATCH_REINDEX;
@@ -993,7 +1055,7 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
                 return st;
             }
             BatchArgs args{};
-            if ((st = stage_batch(ctx, recs, g->scratch, ctx->batch_host, spi, &args, ctx->stream)) != MKF_OK) {
+            if ((st = stage_batch(ctx, recs, g->scratch, ctx->batch_host, spi, &args, ctx->stream, beam)) != MKF_OK) {
                 ctx->heap.release(g->scratch);
                 return st;
             }
@@ -1026,7 +1088,8 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
     } else {
         if ((st = ensure_batch_scratch(ctx, n)) != MKF_OK) return st;
         BatchArgs args{};
-        if ((st = stage_batch(ctx, recs, ctx->batch_dev, ctx->batch_host, spi, &args, ctx->stream)) != MKF_OK) return st;
+        if ((st = stage_batch(ctx, recs, ctx->batch_dev, ctx->batch_host, spi, &args, ctx->stream, beam)) != MKF_OK)
+            return st;
         if ((st = run_pipeline(ctx, args, recs, flags, true, ctx->stream)) != MKF_OK) return st;
     }
     if (async) {
@@ -1076,6 +1139,32 @@ mkf_status mkf_fetch_fit(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
         return st;
     MKF_HIP(hipStreamSynchronize(ctx->stream));
     finish_ndof(out);
+    return MKF_OK;
+}
+
+mkf_status mkf_fetch_beam(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
+{
+    if (!ctx || !out) return fail(MKF_E_INVALID, "NULL argument");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    if (!rec->beam) return fail(MKF_E_STATE, "no build of this event kept its beam (MKF_BATCH_BEAM)");
+    const size_t n = (size_t)rec->shape.n_seeds * ctx->cfg.max_cands, nl = (size_t)rec->shape.n_layers;
+    mkf_status st = check_tracks(out, (int)n, "fetch_beam");
+    if (st != MKF_OK) return st;
+    const DevEvent &v = rec->beam_view;
+    hipStream_t s = ctx->stream;
+    if ((st = copy_d2h(out->par, v.beam_par, 48 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->cov, v.beam_cov, 168 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->hits, v.beam_hits, 4 * nl * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->n_hits, v.beam_nhits, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->n_holes, v.beam_nholes, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->chi2, v.beam_chi2, 8 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->status, v.beam_status, 4 * n, s)) != MKF_OK ||
+        (st = copy_d2h(out->ndof, v.beam_nhits, 4 * n, s)) != MKF_OK)
+        return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    if (out->ndof)
+        for (size_t i = 0; i < n; ++i) out->ndof[i] = out->status && out->status[i] < 0 ? 0 : 2 * out->ndof[i] - 5;
     return MKF_OK;
 }
 

@@ -22,10 +22,18 @@ namespace mkf {
 // thread-local message of the last failure
 mkf_status fail(mkf_status st, const char *fmt, ...);
 
+// Records errors after which the device's HIP context is unusable (a faulting
+// kernel); mkf_ctx_broken reports them.
+void note_device_error(hipError_t e);
+bool device_broken(int device);
+
 #define MKF_HIP(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return ::mkf::fail(MKF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                                \
+            ::mkf::note_device_error(e_);                                                      \
+            return ::mkf::fail(MKF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
+        }                                                                                      \
     } while (0)
 
 // Source of device memory for events: the caller's hooks / hipMalloc, or
@@ -74,6 +82,8 @@ struct EventRec {
     void *data = nullptr;          // hits, seeds, tracks, outputs, stats, descriptor
     void *index = nullptr;         // bin counts and offsets
     void *plain = nullptr;         // per-layer builder state
+    void *beam = nullptr;          // every rank of the final beam (allocated on first request)
+    DevEvent beam_view{};          // its arrays (only the beam_* members are set)
     int index_bins_phi = 0, index_bins_z = 0;   // grid the index was built for (0 = none)
     int plain_G = 0;
     DevEvent view{};               // host copy of the device descriptor
@@ -152,7 +162,8 @@ mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStr
 void destroy_event(mkf_ctx *ctx, EventRec *rec);
 mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s);
 mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
-                       BatchArgs *args, hipStream_t s);
+                       BatchArgs *args, hipStream_t s, bool beam = false);
+mkf_status ensure_beam(mkf_ctx *ctx, EventRec *rec);
 size_t batch_scratch_bytes(int n_events);
 int resolve_lanes(const mkf_ctx *ctx);
 int seeds_per_item(int G);

@@ -286,6 +286,10 @@ def test_abi_errors(ctx6):
     ev = synth.make_event(20, cfg=217, event=0)
     h = ctx6.load_event(ev)
     try:
+        assert not ctx6.broken()
+        with pytest.raises(abi.MkfError) as e:   # no build kept this event's beam yet
+            ctx6.fetch_beam(h, ev.n_seeds)
+        assert e.value.status == abi.E_STATE
         with pytest.raises(abi.MkfError) as e:
             ctx6.build(h + 1000, ev.n_seeds)
         assert e.value.status == abi.E_NOTFOUND
@@ -311,3 +315,54 @@ def test_abi_errors(ctx6):
         assert ctx6.build(h, ev.n_seeds)["status"].shape == (20,)
     finally:
         ctx6.unload_event(h)
+
+
+def test_full_final_beam_parity(ctx6):
+    """Every rank of each seed's final beam (BATCH_BEAM) against the
+    oracle's beam: the same live ranks with the same hit lists in the same
+    order (as sets where two consecutive ranks are within the rank-tie gap),
+    states within the tolerances; rank 0 is the build's output."""
+    from parity_util import TOL, state_errors
+    ev = synth.make_event(1500, cfg=220, event=0, noise=0.5)
+    print("case full beam n=1500 k=6 noise=0.5", flush=True)
+    h = ctx6.load_event(ev)
+    try:
+        g = ctx6.build_batch([h], [ev.n_seeds], flags=abi.BATCH_BEAM)[0]
+        beam = ctx6.fetch_beam(h, ev.n_seeds)
+        plain = ctx6.build_batch([h], [ev.n_seeds])[0]
+    finally:
+        ctx6.unload_event(h)
+    _equal(g, plain)
+    for k in FIELDS:
+        assert np.array_equal(beam[k][:, 0], g[k]), k
+    cfg = oracle.config(ev.geometry, max_cands=6)
+    out, ob = oracle.build_beam(cfg, ev.hits, ev.seed_par, ev.seed_cov, ev.seed_hits, n_threads=8)
+    tol = TOL["build"]
+    tie = (out["m_cut"] < tol["eps_cut"]) | (out["m_rank"] < tol["eps_rank"]) | (out["m_prop"] < tol["eps_prop"])
+    n_checked = n_ranks = 0
+    gp, gc, op, oc = [], [], [], []
+    for s in np.flatnonzero(~tie):
+        live = ob[s]["status"] >= 0
+        assert ((beam["status"][s] >= 0) == live).all(), s
+        oh = [tuple(x) for x in ob[s]["hits"][live][:, :10]]
+        gh = [tuple(x) for x in beam["hits"][s][live]]
+        # inner ranks closer than the rank-tie gap may come in either order
+        chi = ob[s]["chi2"][live]
+        nh = ob[s]["n_hits"][live]
+        close = [(nh[r] == nh[r + 1]) and (chi[r + 1] - chi[r]) / (1.0 + chi[r]) < tol["eps_rank"]
+                 for r in range(len(chi) - 1)]
+        if any(close):
+            assert sorted(oh) == sorted(gh), s
+        else:
+            assert oh == gh, s
+        for r in range(int(live.sum())):
+            j = gh.index(oh[r])
+            gp.append(beam["par"][s, j]); gc.append(beam["cov"][s, j])
+            op.append(ob[s, r]["par"]); oc.append(ob[s, r]["cov"])
+        n_checked += 1
+        n_ranks += int(live.sum())
+    dpar, dcov = state_errors(np.array(gp), np.array(gc), np.array(op), np.array(oc))
+    report("full_beam_1500", dict(seeds=n_checked, ranks=n_ranks, ties=int(tie.sum()),
+                                  max_dpar_sigma=float(dpar.max()), max_dcov_rel=float(dcov.max())))
+    assert n_ranks > n_checked      # the beams really hold several candidates
+    assert dpar.max() <= tol["tau_par_sigma"] and dcov.max() <= tol["tau_cov_rel"]
