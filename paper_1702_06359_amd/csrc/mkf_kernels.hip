@@ -207,7 +207,8 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
     int carry = 0;
     for (int w = 0; w < n_waves; ++w) carry += s_wave[w];
     __syncthreads();
-    // exclusive scan of the counts, written out absolute; each thread owns 32
+    // exclusive scan of the counts into offsets relative to the layer, kept in
+    // LDS (same packing: at most 65,535 hits when short); each thread owns 32
     // consecutive bins (one step for up to 32,768 bins)
     constexpr int kPer = 32;
     constexpr int kWords = kShort ? kPer / 2 : kPer;
@@ -253,11 +254,30 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
         int run = carry + (wave > 0 ? s_wave[wave - 1] : 0) + x - sum;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            if (b0 + j < nr) store_global(off + lo + b0 + j, h0 + run);
+            if (kShort) {
+                if (j & 1) w[j >> 1] |= (unsigned)run << 16;
+                else w[j >> 1] = (unsigned)run;
+            } else {
+                w[j] = (unsigned)run;
+            }
             run += v[j];
+        }
+        if (w0 + kWords <= nw) {
+#pragma unroll
+            for (int j = 0; j < kWords; j += 4)
+                *reinterpret_cast<uint4 *>(s_cnt + w0 + j) = make_uint4(w[j], w[j + 1], w[j + 2], w[j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWords; ++j)
+                if (w0 + j < nw) s_cnt[w0 + j] = w[j];
         }
         carry += s_wave[n_waves - 1];
         __syncthreads();
+    }
+    // written out absolute, consecutive threads on consecutive bins
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        const int r = kShort ? (int)((s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu) : (int)s_cnt[i];
+        store_global(off + lo + i, h0 + r);
     }
 }
 
