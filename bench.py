@@ -101,7 +101,7 @@ def cpu_baseline_build(ev, k, target_cpu_s=15.0):
     cfg = oracle.config(ev.geometry, max_cands=k)
     threads = max(1, min(16, os.cpu_count() or 1))
     hs = oracle.HitSet(ev.hits)
-    probe = np.arange(min(8, ev.n_seeds), dtype=np.int32)
+    probe = np.arange(min(64, ev.n_seeds), dtype=np.int32)
     t0 = time.perf_counter()
     oracle.build_tracks(cfg, hs, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=probe, n_threads=1)
     per_seed = (time.perf_counter() - t0) / len(probe)
@@ -111,8 +111,10 @@ def cpu_baseline_build(ev, k, target_cpu_s=15.0):
     oracle.build_tracks(cfg, hs, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=rows, n_threads=threads)
     wall = time.perf_counter() - t0
     return {"value": n / wall, "unit": "tracks/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": 1.0 / per_seed,
             "sample": f"{n} seeds of one 20,000-track event (FP64 oracle, brute-force hit search), "
-                      f"{wall:.1f} s wall on {threads} threads"}
+                      f"{wall:.1f} s wall on {threads} threads; single-thread rate from the first "
+                      f"{len(probe)} seeds"}
 
 
 def serve_latency(ctx, pool, n_submit, rate_hz, seed=0):
@@ -227,25 +229,61 @@ def workload_ckf(args):
         result["endcap"] = endcap_leg(args)
         log("two-step workload")
         result["two_step"] = two_step_leg(args)
+        log("best-hit latency")
+        result["best_hit"] = best_hit_latency()
         log("serving latency run")
         pool_sizes = synth.loguniform_sizes(16, 500, 50000, cfg=4)
         pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(pool_sizes)]
-        ctx.serve_config(16 << 30, max_in_flight=64)
+        budget = 16 << 30
+        ctx.serve_config(budget, max_in_flight=64)
         # saturated rate: everything submitted at once
         t0 = time.perf_counter()
-        lat = serve_latency(ctx, pool, 96, 1e9)
+        serve_latency(ctx, pool, 96, 1e9)
         sat = 96 / (time.perf_counter() - t0)
-        lat = serve_latency(ctx, pool, 200, 0.5 * sat, seed=1)
-        result["serving"] = {"events": 200, "rate_events_per_s": round(0.5 * sat, 1),
-                             "saturated_events_per_s": round(sat, 1),
-                             "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                             "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                             "tracks_per_event_mean": float(np.mean(pool_sizes))}
+        rates = []
+        for frac in (0.5, 0.8):
+            serve_latency(ctx, pool, 256, frac * sat, seed=2)            # warm-up
+            lat = serve_latency(ctx, pool, 4096, frac * sat, seed=1)
+            rates.append({"load": frac, "rate_events_per_s": round(frac * sat, 1), "events": 4096,
+                          "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                          "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)})
+        result["serving"] = {"saturated_events_per_s": round(sat, 1), "hbm_budget_bytes": budget,
+                             "tracks_per_event_mean": float(np.mean(pool_sizes)),
+                             "latency_p50_ms": rates[0]["latency_p50_ms"],
+                             "latency_p99_ms": rates[0]["latency_p99_ms"], "rates": rates}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline_build(evs[0], k, args.cpu_seconds)
     ctx.close()
     return result
+
+
+def best_hit_latency(reps=10):
+    """1 event x 1,000 tracks, no noise, one candidate per seed, plain
+    per-layer builder: median latency with the event resident on the device,
+    and end to end (load + index + build + copy of the tracks to the host)."""
+    from paper_1702_06359_amd import synth
+    ev = synth.best_hit_event(1000)
+    ctx = make_ctx(1)
+    h = ctx.load_event(ev)
+    lib_build_plain(ctx, h)
+    dev = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        lib_build_plain(ctx, h)
+        dev.append(time.perf_counter() - t0)
+    ctx.unload_event(h)
+    e2e = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        h = ctx.load_event(ev)
+        ctx.build(h, ev.n_seeds)
+        e2e.append(time.perf_counter() - t0)
+        ctx.unload_event(h)
+    ctx.close()
+    return {"workload": "best-hit building, 1 event x 1,000 tracks, no noise, k=1, plain builder",
+            "device_resident_ms_p50": round(float(np.median(dev)) * 1e3, 4),
+            "end_to_end_ms_p50": round(float(np.median(e2e)) * 1e3, 4)}
 
 
 def geometry_leg(args, evs, geometry, workload, steps=None):

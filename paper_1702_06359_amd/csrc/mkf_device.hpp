@@ -397,7 +397,8 @@ __device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, f
 // Second step of the two-step propagation on a layer of finite thickness:
 // from the layer's average cylinder to the nearby cylinder of radius r
 // through a hit, ahead or behind.  Of the two roots of the path quadratic
-// (principal branch) the one of smaller |s|.  False when r is never reached.
+// (principal branch) the one of smaller |s|.  False when r is never reached;
+// o and F are then those of a zero step, so callers may use them unguarded.
 __device__ __forceinline__ bool step_near_cyl(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
                                               float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
 {
@@ -408,10 +409,10 @@ __device__ __forceinline__ bool step_near_cyl(const float (&p)[6], const Trig &t
     const float D = fmaf(r, r, -fmaf(x, x, y * y));
     const float alpha = fmaf(w, e, 1.f) - 0.25f * w * w * D;
     const float disc = fmaf(b, b, alpha * D);
-    if (!(disc >= 0.f)) return false;
-    const float qd = __builtin_amdgcn_sqrtf(disc);
+    bool ok = disc >= 0.f;
+    const float qd = __builtin_amdgcn_sqrtf(fmaxf(disc, 0.f));
     const float bq = b >= 0.f ? b + qd : b - qd;
-    float s;
+    float s = 0.f;
     if (bq != 0.f) {
         const float T1 = 0.5f * D / bq;
         s = 2.f * T1 * atanc(w * T1);
@@ -420,14 +421,15 @@ __device__ __forceinline__ bool step_near_cyl(const float (&p)[6], const Trig &t
             const float s2 = 2.f * T2 * atanc(w * T2);
             if (fabsf(s2) < fabsf(s)) s = s2;
         }
-    } else if (D == 0.f) {
-        s = 0.f;
-    } else {
-        return false;
+    } else if (D != 0.f) {
+        ok = false;
     }
-    if (!(fabsf(s) < kInf)) return false;
+    if (!ok || !(fabsf(s) < kInf)) {
+        ok = false;
+        s = 0.f;
+    }
     helix_cyl(p, tg, s, w_per_qpt, o, F, sn_out, cn_out);
-    return true;
+    return ok;
 }
 
 __device__ __forceinline__ void helix_plane(const float (&p)[6], const Trig &tg, float s, float zd, float w_per_qpt,
@@ -509,10 +511,11 @@ __device__ __forceinline__ void helix_plane(const float (&p)[6], const Trig &tg,
 __device__ __forceinline__ bool step_near_plane(const float (&p)[6], const Trig &tg, float zd, float w_per_qpt,
                                                 float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
 {
-    const float s = (zd - p[2]) * (tg.sth * fast_rcp(tg.cth));
-    if (!(fabsf(s) < kInf)) return false;
+    float s = (zd - p[2]) * (tg.sth * fast_rcp(tg.cth));
+    const bool ok = fabsf(s) < kInf;
+    if (!ok) s = 0.f;   // a zero step: o and F stay defined
     helix_plane(p, tg, s, zd, w_per_qpt, o, F, sn_out, cn_out);
-    return true;
+    return ok;
 }
 
 // Multiple scattering in a layer of x0 radiation lengths, crossed at the
