@@ -366,3 +366,27 @@ def test_full_final_beam_parity(ctx6):
                                   max_dpar_sigma=float(dpar.max()), max_dcov_rel=float(dcov.max())))
     assert n_ranks > n_checked      # the beams really hold several candidates
     assert dpar.max() <= tol["tau_par_sigma"] and dcov.max() <= tol["tau_cov_rel"]
+
+
+def test_maximum_layers_and_candidates(gpu_required):
+    """MKF_MAX_LAYERS (16 cylinders, r = 4 .. 64 cm) and MKF_MAX_CANDS (8
+    candidates per seed on 8 lanes): parity with the oracle, plain and
+    batched builders identical."""
+    geo = synth.Geometry(n_layers=16, radii=tuple(4.0 * (i + 1) for i in range(16)),
+                         x0=tuple(0.002 for _ in range(16)))
+    ev = synth.make_event(600, cfg=221, event=0, geometry=geo, noise=0.3, pt_range=(1.0, 10.0))
+    print("case max layers 16, k=8", flush=True)
+    c = abi.Context(abi.config_from_geometry(geo, max_cands=abi.MAX_CANDS, max_holes=2))
+    try:
+        h = c.load_event(ev)
+        a = c.build(h, ev.n_seeds)
+        b = c.build_batch([h], [ev.n_seeds])[0]
+    finally:
+        c.close()
+    _equal(a, b)
+    cfg = oracle.config(geo, max_cands=abi.MAX_CANDS, max_holes=2)
+    o = oracle.build_tracks(cfg, ev.hits, ev.seed_par, ev.seed_cov, ev.seed_hits, n_threads=8)
+    rep = compare_build(a, o, cfg, ev.hits, ev.seed_par, ev.seed_cov)
+    report("max_layers_k8", rep)
+    assert_build_parity(rep)
+    assert (a["n_hits"] >= 14).mean() > 0.9
