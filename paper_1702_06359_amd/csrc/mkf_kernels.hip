@@ -488,15 +488,22 @@ __device__ __forceinline__ int lanes_below(unsigned long long m)
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// Exclusive prefix sum over the wavefront with DPP moves (no LDS round
+// trips): within each row of 16 lanes by shifts of 1, 2, 3, 4 and 8 lanes,
+// then across rows by broadcasting lane 15 into rows 1 and 3 and lane 31
+// into rows 2 and 3.  Disabled lanes of a step add 0.
 __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
 {
-    int s = x;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(s, o);
-        if (lane >= o) s += t;
-    }
-    return s - x;
+    (void)lane;
+    int v = x;
+    v += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);   // row_shr:3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, true);   // row_shr:4, banks 1-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, true);   // row_shr:8, banks 2-3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true);   // row_bcast:31 into rows 2, 3
+    return v - x;
 }
 
 template <int K, bool kStats, int kGeo>
