@@ -69,6 +69,26 @@ __device__ __forceinline__ unsigned long long group_min(unsigned long long v, in
     return v;
 }
 
+template <int G>
+__device__ __forceinline__ unsigned group_min32(unsigned v, int gbase, int slot)
+{
+    if constexpr ((G & (G - 1)) == 0) {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const unsigned t = (unsigned)__shfl_xor((int)v, o);
+            v = t < v ? t : v;
+        }
+    } else {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int s2 = slot + o >= G ? slot + o - G : slot + o;
+            const unsigned t = (unsigned)__shfl((int)v, gbase + s2);
+            v = t < v ? t : v;
+        }
+    }
+    return v;
+}
+
 __global__ void k_fill_i32(int *__restrict__ p, int v, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -926,22 +946,31 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const int child_hits = S.n_hits + 1;
 
     // 4. keep the max_cands best entries of the seed: repeated group minimum
-    unsigned long long mine = ~0ull;
+    //    over 32-bit keys (n_hits, the accumulated chi2 to 2^-15 relative,
+    //    parent rank; unique within a group, one entry per lane and round);
+    //    each round's winner leaves its full key in the search LDS, free by
+    //    now, for the lane of that rank
+    unsigned long long *sel = reinterpret_cast<unsigned long long *>(W.acc);
+    unsigned filled = 0;
     for (int r = 0; r < P.max_cands; ++r) {
         const bool has_hit = S.live && lk[0] != ~0ull;
         const unsigned long long hk =
             has_hit ? beam_key(child_hits, __uint_as_float((unsigned)(lk[0] >> 32)), slot, (unsigned)lk[0])
                     : (tail ? tail_key : ~0ull);
         if (__ballot(hk != ~0ull) == 0) break;   // every seed of the wavefront is exhausted
-        const unsigned long long m = group_min<G>(hk, gbase, slot);
-        const bool won = (hk == m) & (m != ~0ull);
+        const unsigned k32 = hk == ~0ull ? ~0u : ((unsigned)(hk >> 32) & ~7u) | (unsigned)slot;
+        const unsigned m = group_min32<G>(k32, gbase, slot);
+        const bool won = (k32 == m) & (m != ~0u);
+        if (won) sel[gbase + r] = hk;
+        filled |= (m != ~0u ? 1u : 0u) << r;
         const bool pop = won & has_hit;
 #pragma unroll
         for (int i = 0; i < K - 1; ++i) lk[i] = pop ? lk[i + 1] : lk[i];
         lk[K - 1] = pop ? ~0ull : lk[K - 1];
         tail = tail & !(won & !has_hit);
-        mine = slot == r ? m : mine;
     }
+    wave_lds_sync();
+    unsigned long long mine = (slot < P.max_cands && ((filled >> slot) & 1u)) ? sel[lane] : ~0ull;
     if (lane >= (kWave / G) * G) mine = ~0ull;   // lanes outside every seed group
 
     // 5. each kept entry moves to the lane of its rank: fetch the parent's
