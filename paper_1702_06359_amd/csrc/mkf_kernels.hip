@@ -162,74 +162,34 @@ __global__ void __launch_bounds__(256) k_index_bin(const Params P, const BatchAr
     }
 }
 
-// Ranks and bin offsets of a layer (between k_index_bin and
-// k_index_scatter), its bins split into `nsplit` ranges of `chunk` bins (a
-// multiple of 64): one 1024-thread block per (event, layer, range) reads the
-// bin of every hit of the layer, ranks those in its range with LDS atomics,
-// counts those below it, and scans its range's counts in LDS into absolute
-// offsets.  No device-wide atomic, no count array to clear, and no block
-// waits for another; the split fills the machine when a batch has few
-// (event, layer) pairs.  kShort packs two 16-bit counters per word (layers of
-// at most 65,535 hits).
+// Bin counters in LDS: one 32-bit counter per bin, or two 16-bit counters per
+// word when kShort (layers of at most 65,535 hits, so that neither half
+// carries into the other).
 template <bool kShort>
-__global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchArgs B, int nsplit, int chunk)
+__device__ __forceinline__ int lds_count(const unsigned *s_cnt, int i)
 {
-    extern __shared__ unsigned s_cnt[];
-    __shared__ int s_wave[16];
-    const int part = blockIdx.x % nsplit;
-    const int el = blockIdx.x / nsplit;
-    const int e = el / P.n_layers;
-    const int L = el - e * P.n_layers;
-    const DevEvent &E = B.events[e];
-    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
-    const int nb = P.bins_phi * P.bins_z;
-    int *off = E.bin_off + L * (nb + 1);
-    if (part == nsplit - 1 && threadIdx.x == 0) off[nb] = h1;
-    const int lo = part * chunk;
-    if (lo >= nb) return;                     // an empty range (whole block)
-    const int nr = min(chunk, nb - lo);       // bins of this range
-    const int nw = kShort ? (nr + 1) / 2 : nr;
-    for (int i = threadIdx.x; i < nw; i += blockDim.x) s_cnt[i] = 0u;
-    __syncthreads();
-    // four hits per thread and step, their loads issued together
-    constexpr int kU = 4;
-    const int stride = blockDim.x;
-    int below = 0;   // hits of this thread in bins before the range
-    for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
-        int bins[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) bins[u] = load_global(E.bin_of + min(h + u * stride, h1 - 1));
-        int rank[kU];   // all atomics of the step in flight before their results are stored
-        bool mine[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int bin = bins[u] - lo;
-            const bool in = h + u * stride < h1;
-            mine[u] = in && bin >= 0 && bin < nr;
-            below += (in && bin < 0) ? 1 : 0;
-            if (kShort) {
-                const int sh = (bin & 1) * 16;
-                rank[u] = mine[u] ? (int)((atomicAdd(&s_cnt[bin >> 1], 1u << sh) >> sh) & 0xFFFFu) : 0;
-            } else {
-                rank[u] = mine[u] ? (int)atomicAdd(&s_cnt[bin], 1u) : 0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            if (mine[u]) store_global(E.bin_rank + h + u * stride, rank[u]);
+    return kShort ? (int)((s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu) : (int)s_cnt[i];
+}
+
+// Adds one to counter `bin` and returns its previous value.
+template <bool kShort>
+__device__ __forceinline__ int lds_bump(unsigned *s_cnt, int bin)
+{
+    if (kShort) {
+        const int sh = (bin & 1) * 16;
+        return (int)((atomicAdd(&s_cnt[bin >> 1], 1u << sh) >> sh) & 0xFFFFu);
     }
+    return (int)atomicAdd(&s_cnt[bin], 1u);
+}
+
+// In-place exclusive scan of the nr counters in s_cnt, starting from
+// `carry`.  Each thread owns 32 consecutive bins per step (one step for up to
+// 32,768 bins).  Every thread of the block calls it; it ends on a barrier.
+template <bool kShort>
+__device__ __forceinline__ void lds_scan_counts(unsigned *s_cnt, int nr, int carry, int *s_wave)
+{
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    // block sum of `below`: the offset of the range's first bin in the layer
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) below += __shfl_xor(below, o);
-    if (lane == 0) s_wave[wave] = below;
-    __syncthreads();
-    int carry = 0;
-    for (int w = 0; w < n_waves; ++w) carry += s_wave[w];
-    __syncthreads();
-    // exclusive scan of the counts into offsets relative to the layer, kept in
-    // LDS (same packing: at most 65,535 hits when short); each thread owns 32
-    // consecutive bins (one step for up to 32,768 bins)
+    const int nw = kShort ? (nr + 1) / 2 : nr;
     constexpr int kPer = 32;
     constexpr int kWords = kShort ? kPer / 2 : kPer;
     for (int base = 0; base < nr; base += blockDim.x * kPer) {
@@ -294,10 +254,128 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
         carry += s_wave[n_waves - 1];
         __syncthreads();
     }
+}
+
+// Ranks and bin offsets of a layer (between k_index_bin and
+// k_index_scatter), its bins split into `nsplit` ranges of `chunk` bins (a
+// multiple of 64): one 1024-thread block per (event, layer, range) reads the
+// bin of every hit of the layer, ranks those in its range with LDS atomics,
+// counts those below it, and scans its range's counts in LDS into absolute
+// offsets.  No device-wide atomic, no count array to clear, and no block
+// waits for another; the split fills the machine when a batch has few
+// (event, layer) pairs.  kShort packs two 16-bit counters per word (layers of
+// at most 65,535 hits).
+template <bool kShort>
+__global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchArgs B, int nsplit, int chunk)
+{
+    extern __shared__ unsigned s_cnt[];
+    __shared__ int s_wave[16];
+    const int part = blockIdx.x % nsplit;
+    const int el = blockIdx.x / nsplit;
+    const int e = el / P.n_layers;
+    const int L = el - e * P.n_layers;
+    const DevEvent &E = B.events[e];
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
+    const int nb = P.bins_phi * P.bins_z;
+    int *off = E.bin_off + L * (nb + 1);
+    if (part == nsplit - 1 && threadIdx.x == 0) off[nb] = h1;
+    const int lo = part * chunk;
+    if (lo >= nb) return;                     // an empty range (whole block)
+    const int nr = min(chunk, nb - lo);       // bins of this range
+    const int nw = kShort ? (nr + 1) / 2 : nr;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    // four hits per thread and step, their loads issued together
+    constexpr int kU = 4;
+    const int stride = blockDim.x;
+    int below = 0;   // hits of this thread in bins before the range
+    for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
+        int bins[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bins[u] = load_global(E.bin_of + min(h + u * stride, h1 - 1));
+        int rank[kU];   // all atomics of the step in flight before their results are stored
+        bool mine[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int bin = bins[u] - lo;
+            const bool in = h + u * stride < h1;
+            mine[u] = in && bin >= 0 && bin < nr;
+            below += (in && bin < 0) ? 1 : 0;
+            rank[u] = mine[u] ? lds_bump<kShort>(s_cnt, bin) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (mine[u]) store_global(E.bin_rank + h + u * stride, rank[u]);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    // block sum of `below`: the offset of the range's first bin in the layer
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if (lane == 0) s_wave[wave] = below;
+    __syncthreads();
+    int carry = 0;
+    for (int w = 0; w < n_waves; ++w) carry += s_wave[w];
+    __syncthreads();
+    // exclusive scan of the counts into offsets relative to the layer, kept in
+    // LDS in the same packing
+    lds_scan_counts<kShort>(s_cnt, nr, carry, s_wave);
     // written out absolute, consecutive threads on consecutive bins
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        const int r = kShort ? (int)((s_cnt[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu) : (int)s_cnt[i];
-        store_global(off + lo + i, h0 + r);
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) store_global(off + lo + i, h0 + lds_count<kShort>(s_cnt, i));
+}
+
+// Bin offsets and placement of one layer in one 1024-thread block per (event,
+// layer), after k_index_bin, for batches with enough (event, layer) pairs to
+// fill the machine: bin counts with LDS atomics, their scan in LDS, then every
+// hit placed at its bin's running offset (a second LDS atomic), so that no
+// rank is stored and the offsets are read from LDS.  The order inside a bin
+// is that of the atomics, which does not matter: every hit of a window is
+// tested and ties are broken by hit index.  `kU` hits per thread and step,
+// their loads issued together.
+template <bool kShort>
+__global__ void __launch_bounds__(1024) k_index_layer(const Params P, const BatchArgs B)
+{
+    extern __shared__ unsigned s_cnt[];
+    __shared__ int s_wave[16];
+    const int e = blockIdx.x / P.n_layers;
+    const int L = blockIdx.x - e * P.n_layers;
+    const DevEvent &E = B.events[e];
+    const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
+    const int nb = P.bins_phi * P.bins_z;
+    int *off = E.bin_off + L * (nb + 1);
+    const int nw = kShort ? (nb + 1) / 2 : nb;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    constexpr int kU = 8;
+    const int stride = blockDim.x;
+    for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
+        int bins[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bins[u] = load_global(E.bin_of + min(h + u * stride, h1 - 1));
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (h + u * stride < h1) lds_bump<kShort>(s_cnt, bins[u]);
+    }
+    __syncthreads();
+    lds_scan_counts<kShort>(s_cnt, nb, 0, s_wave);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) store_global(off + i, h0 + lds_count<kShort>(s_cnt, i));
+    if (threadIdx.x == 0) off[nb] = h1;
+    __syncthreads();   // every offset read before the placement moves them
+    for (int h = h0 + (int)threadIdx.x; h < h1; h += kU * stride) {
+        int bins[kU];
+        float4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int hh = min(h + u * stride, h1 - 1);
+            bins[u] = load_global(E.bin_of + hh);
+            v[u] = load_global(E.hits + hh);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (h + u * stride < h1) {
+                const int pos = lds_bump<kShort>(s_cnt, bins[u]);
+                store_global(E.binned + h0 + pos, make_float4(v[u].x, v[u].y, v[u].z, __int_as_float(h + u * stride - h0)));
+            }
+        }
     }
 }
 
@@ -1480,15 +1558,29 @@ hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
     const size_t nb = (size_t)p.bins_phi * p.bins_z;
     const size_t lds = lds_per_block();
     const unsigned blocks = (unsigned)(b.n_events * p.n_layers);
-    // bin ranges per (event, layer): about two blocks per compute unit in all
     const int n_cu = compute_units();
+    // chunks per (event, layer) of the per-hit kernels: about one hit per
+    // thread for the largest layer, striding beyond that
+    const dim3 grid(std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256))), blocks);
+    // one block per (event, layer) when there are enough of them
+    if ((int)blocks * 4 >= n_cu) {
+        const size_t words = b.max_layer_hits <= 0xFFFF ? (nb + 1) / 2 : nb;
+        if (words * 4 <= lds) {
+            k_index_bin<<<grid, 256, 0, s>>>(p, b);
+            hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+            if (b.max_layer_hits <= 0xFFFF) k_index_layer<true><<<blocks, 1024, words * 4, s>>>(p, b);
+            else k_index_layer<false><<<blocks, 1024, words * 4, s>>>(p, b);
+            err = hipGetLastError();
+            if (err == hipSuccess) return err;
+            lds_refused();   // not launched: the split form below (the binning is repeated)
+        }
+    }
+    // bin ranges per (event, layer): about two blocks per compute unit in all
     const int nsplit = (int)std::max<size_t>(1, std::min<size_t>({(size_t)16, (nb + 63) / 64,
                                                                   (size_t)(2 * n_cu + blocks - 1) / blocks}));
     const size_t chunk = ((nb + nsplit - 1) / nsplit + 63) / 64 * 64;
     const bool fits = chunk * 4 <= lds || (chunk / 2 * 4 <= lds && b.max_layer_hits <= 0xFFFF);
-    // chunks per (event, layer): about one hit per thread for the largest
-    // layer, striding beyond that
-    const dim3 grid(std::max(1u, std::min(4096u, blocks_for(b.max_layer_hits, 256))), blocks);
     if (fits) {
         k_index_bin<<<grid, 256, 0, s>>>(p, b);
         const hipError_t err = hipGetLastError();
