@@ -192,19 +192,26 @@ def test_repeat_and_batch_composition_are_deterministic(ctx6):
         _equal(a, d)
 
 
-@pytest.mark.parametrize("case", ["barrel", "endcap", "thick", "wide"])
+@pytest.mark.parametrize("case", ["barrel", "endcap", "thick", "dense", "coarse", "one_bin", "large", "wide"])
 def test_one_block_per_layer_index(gpu_required, case):
     """Batches of at least a quarter as many (event, layer) pairs as compute
-    units index every layer in one block (16-bit bin counters up to 65,535
-    hits per layer, 32-bit beyond: the "wide" case); a single event takes the
-    split form.  Each event built alone first (split index), then the batch
-    re-indexed: bit-identical tracks."""
-    g = {"barrel": synth.Geometry(), "endcap": synth.Geometry.endcap(),
-         "thick": synth.Geometry(thickness=tuple(0.6 for _ in range(10))), "wide": synth.Geometry()}[case]
-    if case == "wide":
-        big = synth.make_event(60000, cfg=214, event=0, noise=0.1)
-        assert max(len(h) for h in big.hits) > 0xFFFF
+    units index every layer in one block: 16-bit bin counters up to 65,535
+    hits per layer (small events of three geometries; "dense": 12,000-hit
+    layers; "coarse": 3 bins per layer; "one_bin": a single bin; "large":
+    55,000-hit layers), 32-bit counters beyond ("wide": 66,000-hit layers).
+    A single event takes the split form.  Each event built alone first
+    (split index), then the batch re-indexed: bit-identical tracks."""
+    g = {"endcap": synth.Geometry.endcap(), "thick": synth.Geometry(thickness=tuple(0.6 for _ in range(10)))}.get(
+        case, synth.Geometry())
+    tuning = {"coarse": dict(bins_phi=3, bins_z=1), "one_bin": dict(bins_phi=1, bins_z=1)}.get(case, {})
+    if case in ("large", "wide"):
+        big = synth.make_event(50000 if case == "large" else 60000, cfg=214, event=0, noise=0.1)
+        assert (max(len(h) for h in big.hits) > 0xFFFF) == (case == "wide")
         evs, n_alone = [big] * 7, 1
+    elif case in ("dense", "coarse", "one_bin"):
+        evs = [synth.make_event(1000, cfg=216, event=i, noise=11.0) for i in range(8)]
+        assert min(len(h) for e in evs for h in e.hits) == 12000
+        n_alone = 3
     else:
         evs = [synth.make_event(n, cfg=215, event=i, noise=0.2, geometry=g)
                for i, n in enumerate((700, 1300, 90, 2100, 40, 1000, 555, 1600))]
@@ -212,16 +219,18 @@ def test_one_block_per_layer_index(gpu_required, case):
     assert len(evs) * g.n_layers * 4 >= 256
     c = abi.Context(abi.config_from_geometry(g, max_cands=6))
     try:
+        if tuning:
+            c.set_tuning(**tuning)
         hs = [c.load_event(e) for e in evs]
         print(f"case one-block index {case}: {len(evs)} events, "
-              f"largest layer {max(len(h) for e in evs for h in e.hits)} hits", flush=True)
+              f"largest layer {max(len(h) for e in evs for h in e.hits)} hits, tuning {tuning}", flush=True)
         alone = [c.build(h, e.n_seeds) for h, e in zip(hs[:n_alone], evs[:n_alone])]
         batch = c.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
     finally:
         c.close()
     for a, b in zip(alone, batch):
         _equal(a, b)
-    if case == "wide":
+    if case in ("large", "wide"):
         for b in batch[1:]:
             _equal(batch[0], b)
 
