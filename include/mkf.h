@@ -161,7 +161,7 @@ typedef struct {
 typedef struct {
     int32_t lanes_per_seed;   /* 1, 2, 4, 6 or 8, >= max_cands; 0 = smallest valid */
     int32_t waves_per_block;  /* 1 .. 4; 0 = 1 */
-    int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 1024 */
+    int32_t bins_phi;         /* hit-index bins in phi per layer, 1 .. 4096; 0 = 2048 */
     int32_t bins_z;           /* hit-index bins in z per layer, 1 .. 1024; 0 = 32 */
     int32_t persistent;       /* batched build: 1 = persistent waves on a device work queue,
                                  0 = one wave per work item dispatched by the hardware (default) */

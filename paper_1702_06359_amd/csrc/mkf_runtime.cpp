@@ -302,7 +302,7 @@ mkf_status check_tuning(const mkf_config &c, mkf_tuning *t)
     if (G < c.max_cands) return fail(MKF_E_INVALID, "lanes_per_seed must be >= max_cands");
     if (t->waves_per_block == 0) t->waves_per_block = 1;
     if (t->waves_per_block < 1 || t->waves_per_block > 4) return fail(MKF_E_INVALID, "waves_per_block must be 1..4");
-    if (t->bins_phi == 0) t->bins_phi = 1024;
+    if (t->bins_phi == 0) t->bins_phi = 2048;
     if (t->bins_z == 0) t->bins_z = 32;
     if (t->bins_phi < 1 || t->bins_phi > 4096 || t->bins_z < 1 || t->bins_z > 1024 ||
         (long long)t->bins_phi * t->bins_z > (1 << 20))
