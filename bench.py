@@ -47,6 +47,20 @@ KERNEL_SOURCES = ("paper_1702_06359_amd/csrc/mkf_kernels.hip", "paper_1702_06359
                   "paper_1702_06359_amd/csrc/mkf_internal.hpp")
 
 
+def fma_ceiling(ctx, n_blocks=2048, iters=4096, reps=5):
+    """Measured FP32 multiply-add throughput of the vector ALUs (no packed
+    instructions, like the library's kernels): best of `reps` launches of the
+    library's calibration kernel, untimed by the benchmark step."""
+    import torch
+    out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda")
+    ctx.calib_fma(out.data_ptr(), n_blocks, iters)
+    best = min(ctx.calib_fma(out.data_ptr(), n_blocks, iters)[0] for _ in range(reps))
+    flop = 2.0 * 8 * iters * 256 * n_blocks
+    tf = flop / (best * 1e-3) / 1e12
+    return {"tflops": round(tf, 2), "frac_of_peak": round(tf / PEAK_FP32_VALU_TFLOPS, 4),
+            "frac_of_nonpacked_peak": round(tf / (PEAK_FP32_VALU_TFLOPS / 2), 4)}
+
+
 def measured_traffic(kernel):
     """Calibrated bytes per launch of `kernel` (read + written) from the
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/traffic.json,
@@ -191,7 +205,8 @@ def workload_ckf(args):
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
                 "traffic": measured_traffic("k_build_batch<6,false,0>") if tuning["lanes_per_seed"] == 6 else None,
                 "kernel": "k_build_batch", "kernel_avg_ms": round(avg_ms, 4),
-                "flop_per_launch": int(flops), "counters": st}
+                "flop_per_launch": int(flops), "counters": st,
+                "fma_ceiling": fma_ceiling(ctx)}
     # the same steps with the final fit of every built track chained on the device
     def step_fit():
         ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC | abi.BATCH_FIT)
@@ -488,8 +503,9 @@ def workload_calib(args):
         ctx.calib_copy(src.data_ptr(), dst.data_ptr(), nbytes)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+    fma = fma_ceiling(ctx)
     ctx.close()
-    return {"metric": "calibration copy", "bytes_per_launch": nbytes, "launches": args.steps}
+    return {"metric": "calibration copy", "bytes_per_launch": nbytes, "launches": args.steps, "fma_ceiling": fma}
 
 
 def lib_build_plain(ctx, h):

@@ -342,6 +342,18 @@ mkf_status mkf_serve_drain(mkf_ctx *ctx);
  * counters against a known traffic.  Blocks until done. */
 mkf_status mkf_calib_copy(mkf_ctx *ctx, const void *src_dev, void *dst_dev, size_t bytes);
 
+/* FP32 multiply-add throughput of the vector ALUs (the ceiling of the
+ * ALU-bound kernels, which are built without packed FP32 instructions):
+ * n_blocks blocks of 256 threads, each lane running 8 independent chains
+ * x <- x * a + b for `iters` rounds (a multiple of 4) with no memory
+ * traffic, then storing the sum of its chains to dst_dev[thread] (device
+ * memory of n_blocks * 256 floats, owned by the caller).  Launched on the
+ * context stream between two HIP events; blocks until done and returns the
+ * elapsed device time in *ms and the FLOP executed (2 per multiply-add) in
+ * *flop.  Errors: MKF_E_INVALID (null pointers, n_blocks < 1, iters not a
+ * positive multiple of 4), MKF_E_DEVICE. */
+mkf_status mkf_calib_fma(mkf_ctx *ctx, float *dst_dev, int32_t n_blocks, int32_t iters, double *ms, double *flop);
+
 #ifdef __cplusplus
 }
 #endif

@@ -127,6 +127,8 @@ _PROTOS = {
     "mkf_serve_cancel": (C.c_int, [_ctx_p, C.c_uint64]),
     "mkf_serve_drain": (C.c_int, [_ctx_p]),
     "mkf_calib_copy": (C.c_int, [_ctx_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "mkf_calib_fma": (C.c_int, [_ctx_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -463,6 +465,13 @@ class Context:
 
     def calib_copy(self, src_ptr: int, dst_ptr: int, nbytes: int):
         check(lib().mkf_calib_copy(self.h, C.c_void_p(src_ptr), C.c_void_p(dst_ptr), int(nbytes)))
+
+    def calib_fma(self, dst_ptr: int, n_blocks: int, iters: int):
+        """(device ms, FLOP) of the FP32 multiply-add throughput kernel."""
+        ms, flop = C.c_double(), C.c_double()
+        check(lib().mkf_calib_fma(self.h, C.c_void_p(dst_ptr), int(n_blocks), int(iters), C.byref(ms),
+                                  C.byref(flop)))
+        return ms.value, flop.value
 
 
 def version() -> str:

@@ -141,5 +141,7 @@ hipError_t launch_build_layer(const Params &p, const DevEvent *ev_dev, const Dev
 hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s);
 hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_calib_fma(float *dst, int n_blocks, int iters, hipStream_t s);   // iters: multiple of 4
+int calib_fma_chains();
 
 }  // namespace mkf

@@ -102,6 +102,30 @@ __global__ void k_copy16(const float4 *__restrict__ src, float4 *__restrict__ ds
         dst[i] = src[i];
 }
 
+// FP32 multiply-add throughput of the vector ALUs: every lane runs
+// kFmaChains independent chains x <- x a + b for `iters` rounds, with no
+// memory traffic, and stores the sum of its chains (so nothing folds away).
+constexpr int kFmaChains = 8;
+
+__global__ void __launch_bounds__(256) k_calib_fma(float *__restrict__ out, int iters, float a, float b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    float x[kFmaChains];
+#pragma unroll
+    for (int i = 0; i < kFmaChains; ++i) x[i] = (float)(t & 1023) * 1e-3f + (float)i;
+    for (int it = 0; it < iters; it += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int i = 0; i < kFmaChains; ++i) x[i] = fmaf(x[i], a, b);
+        }
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < kFmaChains; ++i) sum += x[i];
+    store_global(out + t, sum);
+}
+
 // Clears the per-event work counters and/or hit-index bin counts of a batch
 // (a kernel rather than a memset so that it can sit in a captured graph).
 __global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_stats, int do_bins)
@@ -1505,6 +1529,14 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
     k_copy16<<<grid, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
     return hipGetLastError();
 }
+
+hipError_t launch_calib_fma(float *dst, int n_blocks, int iters, hipStream_t s)
+{
+    k_calib_fma<<<n_blocks, 256, 0, s>>>(dst, iters, 0.999999f, 1e-6f);
+    return hipGetLastError();
+}
+
+int calib_fma_chains() { return kFmaChains; }
 
 hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s)
 {

@@ -1415,4 +1415,25 @@ mkf_status mkf_calib_copy(mkf_ctx *ctx, const void *src_dev, void *dst_dev, size
     return MKF_OK;
 }
 
+mkf_status mkf_calib_fma(mkf_ctx *ctx, float *dst_dev, int32_t n_blocks, int32_t iters, double *ms, double *flop)
+{
+    if (!ctx || !dst_dev || n_blocks < 1 || iters < 4 || iters % 4 || !ms || !flop)
+        return fail(MKF_E_INVALID, "bad FMA calibration arguments");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    MKF_HIP(hipEventCreate(&ev[0]));
+    hipError_t e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], ctx->stream);
+    if (e == hipSuccess) e = launch_calib_fma(dst_dev, n_blocks, iters, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    hipEventDestroy(ev[0]);
+    if (ev[1]) hipEventDestroy(ev[1]);
+    MKF_HIP(e);
+    *ms = t;
+    *flop = 2.0 * calib_fma_chains() * (double)iters * 256.0 * (double)n_blocks;
+    return MKF_OK;
+}
+
 }  // extern "C"
