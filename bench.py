@@ -84,9 +84,9 @@ def log(*a):
 
 def gpu_count_guard(n):
     if n != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "detail": "events shard across GPUs with no exchange (see DESIGN.md); "
-                                    "multi-GPU runs are not part of this build"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
+                          "detail": "events would shard across GPUs with no exchange between them; "
+                                    "no multi-GPU launcher is provided"}))
         sys.exit(2)
 
 

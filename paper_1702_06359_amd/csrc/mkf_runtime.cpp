@@ -657,7 +657,7 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
         const EventShape &sh = recs[i]->shape;
         for (int L = 0; L < sh.n_layers; ++L) max_layer = std::max(max_layer, sh.layer_off[L + 1] - sh.layer_off[L]);
         ev[i] = recs[i]->view;
-        if (beam) {   // this build also writes every rank of the final beam
+        if (beam) {   // this launch also writes every rank of the final beam
             const DevEvent &b = recs[i]->beam_view;
             ev[i].beam_par = b.beam_par;
             ev[i].beam_cov = b.beam_cov;
