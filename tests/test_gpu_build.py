@@ -192,15 +192,18 @@ def test_repeat_and_batch_composition_are_deterministic(ctx6):
         _equal(a, d)
 
 
-@pytest.mark.parametrize("case", ["barrel", "endcap", "thick", "dense", "coarse", "one_bin", "large", "wide"])
+@pytest.mark.parametrize("case", ["barrel", "endcap", "thick", "dense", "coarse", "one_bin", "large", "wide",
+                                  "edges"])
 def test_one_block_per_layer_index(gpu_required, case):
     """Batches of at least a quarter as many (event, layer) pairs as compute
     units index every layer in one block: 16-bit bin counters up to 65,535
     hits per layer (small events of three geometries; "dense": 12,000-hit
     layers; "coarse": 3 bins per layer; "one_bin": a single bin; "large":
     55,000-hit layers), 32-bit counters beyond ("wide": 66,000-hit layers).
-    A single event takes the split form.  Each event built alone first
-    (split index), then the batch re-indexed: bit-identical tracks."""
+    "edges": no seeds, empty outer layers and a 5,000-hit edge bin among
+    small events.  A single event takes the split form.  Each event built
+    alone first (split index), then the batch re-indexed: bit-identical
+    tracks."""
     g = {"endcap": synth.Geometry.endcap(), "thick": synth.Geometry(thickness=tuple(0.6 for _ in range(10)))}.get(
         case, synth.Geometry())
     tuning = {"coarse": dict(bins_phi=3, bins_z=1), "one_bin": dict(bins_phi=1, bins_z=1)}.get(case, {})
@@ -216,6 +219,16 @@ def test_one_block_per_layer_index(gpu_required, case):
         evs = [synth.make_event(n, cfg=215, event=i, noise=0.2, geometry=g)
                for i, n in enumerate((700, 1300, 90, 2100, 40, 1000, 555, 1600))]
         n_alone = len(evs)
+    if case == "edges":
+        ev = evs[3]
+        hollow = [x.copy() for x in ev.hits]
+        for L in (7, 8, 9):
+            hollow[L] = np.zeros((0, 3))
+        crowd = [x.copy() for x in ev.hits]
+        crowd[5] = np.concatenate([crowd[5], np.tile([[20.0, 0.0, 1e4]], (5000, 1))])
+        evs[0] = abi.EventArrays(evs[0].hits, ev.seed_par[:0], ev.seed_cov[:0], ev.seed_hits[:0])
+        evs[1] = abi.EventArrays(hollow, ev.seed_par, ev.seed_cov, ev.seed_hits)
+        evs[2] = abi.EventArrays(crowd, ev.seed_par, ev.seed_cov, ev.seed_hits)
     assert len(evs) * g.n_layers * 4 >= 256
     c = abi.Context(abi.config_from_geometry(g, max_cands=6))
     try:
@@ -224,8 +237,9 @@ def test_one_block_per_layer_index(gpu_required, case):
         hs = [c.load_event(e) for e in evs]
         print(f"case one-block index {case}: {len(evs)} events, "
               f"largest layer {max(len(h) for e in evs for h in e.hits)} hits, tuning {tuning}", flush=True)
-        alone = [c.build(h, e.n_seeds) for h, e in zip(hs[:n_alone], evs[:n_alone])]
-        batch = c.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
+        counts = [len(e.seed_par) for e in evs]
+        alone = [c.build(h, n) for h, n in zip(hs[:n_alone], counts[:n_alone])]
+        batch = c.build_batch(hs, counts, flags=abi.BATCH_REINDEX)
     finally:
         c.close()
     for a, b in zip(alone, batch):
