@@ -121,19 +121,21 @@ def test_crowded_layers(ctx6):
 
 
 def test_full_size_events_sampled_seeds(ctx6):
-    """Two 20,000-track events (10 % noise) in the batched launch the
-    benchmark times; 150 sampled seeds per event checked against the oracle."""
-    evs = synth.ckf_events(2, 20000, 0.10)
+    """The benchmark's workload and launch: ten 20,000-track events (10 %
+    noise) indexed one block per layer and built in one batched launch with
+    the default tuning; 100 sampled seeds per event checked against the
+    oracle."""
+    evs = synth.ckf_events(10, 20000, 0.10)
     hs = [ctx6.load_event(e) for e in evs]
     try:
-        print("case ckf full size 2x20000 batched", flush=True)
+        print("case ckf full size 10x20000 batched", flush=True)
         outs = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
     finally:
         for h in hs:
             ctx6.unload_event(h)
     rng = np.random.default_rng(7)
     for i, (ev, g) in enumerate(zip(evs, outs)):
-        rows = np.sort(rng.choice(ev.n_seeds, 150, replace=False)).astype(np.int32)
+        rows = np.sort(rng.choice(ev.n_seeds, 100, replace=False)).astype(np.int32)
         cfg, o = _oracle(ev, 6, rows=rows, threads=16)
         rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov, rows=rows)
         report(f"ckf_full_event{i}", rep)
