@@ -77,19 +77,20 @@ def test_disk_combinatorial_parity_ragged(ctx6):
 
 
 def test_disk_full_size_events_sampled_seeds(ctx6):
-    """Two events of the endcap workload (10,000 tracks, 10 % noise) in the
-    batched launch the benchmark times; 150 sampled seeds per event."""
-    evs = synth.endcap_events(2)
+    """The endcap workload the benchmark times (ten events of 10,000 tracks,
+    10 % noise; one-block-per-layer index, one batched launch); 60 sampled
+    seeds per event."""
+    evs = synth.endcap_events(10)
     hs = [ctx6.load_event(e) for e in evs]
     try:
-        print("case disk ckf full size 2x10000 batched", flush=True)
+        print("case disk ckf full size 10x10000 batched", flush=True)
         outs = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
     finally:
         for h in hs:
             ctx6.unload_event(h)
     rng = np.random.default_rng(17)
     for i, (ev, g) in enumerate(zip(evs, outs)):
-        rows = np.sort(rng.choice(ev.n_seeds, 150, replace=False)).astype(np.int32)
+        rows = np.sort(rng.choice(ev.n_seeds, 60, replace=False)).astype(np.int32)
         cfg, o = _oracle(ev, 6, rows=rows, threads=16)
         rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov, rows=rows)
         report(f"disk_ckf_full_event{i}", rep)

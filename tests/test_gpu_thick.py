@@ -77,19 +77,20 @@ def test_thick_combinatorial_parity_ragged(gpu_required, name, g):
 
 
 def test_thick_full_size_sampled_seeds(gpu_required):
-    """Two 20,000-track events on the thick barrel (10 % noise) in one
-    batched launch; 150 sampled seeds per event."""
-    evs = [synth.make_event(20000, cfg=242, event=e, geometry=BARREL, noise=0.1) for e in range(2)]
+    """The two-step workload the benchmark times (ten 20,000-track events on
+    the 6 mm deep barrel, 10 % noise; one-block-per-layer index, one batched
+    launch); 40 sampled seeds per event."""
+    evs = [synth.make_event(20000, cfg=5, event=e, geometry=BARREL, noise=0.1) for e in range(10)]
     c = _ctx(BARREL, 6)
     try:
         hs = [c.load_event(e) for e in evs]
-        print("case thick barrel ckf full size 2x20000 batched", flush=True)
+        print("case thick barrel ckf full size 10x20000 batched", flush=True)
         outs = c.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
     finally:
         c.close()
     rng = np.random.default_rng(27)
     for i, (ev, g) in enumerate(zip(evs, outs)):
-        rows = np.sort(rng.choice(ev.n_seeds, 150, replace=False)).astype(np.int32)
+        rows = np.sort(rng.choice(ev.n_seeds, 40, replace=False)).astype(np.int32)
         cfg, o = _oracle(ev, 6, rows=rows, threads=16)
         rep = compare_build(g, o, cfg, ev.hits, ev.seed_par, ev.seed_cov, rows=rows)
         report(f"thick_barrel_full_event{i}", rep)
