@@ -240,6 +240,8 @@ def workload_ckf(args):
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:
+        log("host-inclusive step")
+        result["host_inclusive"] = host_inclusive(ctx, evs)
         log("endcap workload")
         result["endcap"] = endcap_leg(args)
         log("two-step workload")
@@ -299,6 +301,27 @@ def best_hit_latency(reps=10):
     return {"workload": "best-hit building, 1 event x 1,000 tracks, no noise, k=1, plain builder",
             "device_resident_ms_p50": round(float(np.median(dev)) * 1e3, 4),
             "end_to_end_ms_p50": round(float(np.median(e2e)) * 1e3, 4)}
+
+
+def host_inclusive(ctx, evs, reps=3):
+    """The headline workload from host buffers to host buffers: load every
+    event (copies of its FP64 hits and seeds, its hit index), one batched
+    build, copy of every track to the host, unload.  Median wall time of
+    `reps` steps after one warm-up step."""
+    from paper_1702_06359_amd import abi
+    arrays = [abi.EventArrays.from_synth(e) for e in evs]
+    counts = [e.n_seeds for e in evs]
+    times = []
+    for _ in range(reps + 1):
+        t0 = time.perf_counter()
+        hs = [ctx.load_event(a) for a in arrays]
+        ctx.build_batch(hs, counts)
+        for h in hs:
+            ctx.unload_event(h)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times[1:]))
+    return {"step": "load (host FP64 hits and seeds, index) + batched build + tracks to host + unload",
+            "tracks_per_s": round(sum(counts) / t, 1), "ms_per_step": round(t * 1e3, 3)}
 
 
 def geometry_leg(args, evs, geometry, workload, steps=None):
