@@ -204,8 +204,8 @@ def test_one_block_per_layer_index(gpu_required, case):
     55,000-hit layers), 32-bit counters beyond ("wide": 66,000-hit layers).
     "edges": no seeds, empty outer layers and a 5,000-hit edge bin among
     small events.  A single event takes the split form.  Each event built
-    alone first (split index), then the batch re-indexed: bit-identical
-    tracks."""
+    alone first (split index), then the batch re-indexed, eagerly and (three
+    cases) as a captured graph replayed twice: bit-identical tracks."""
     g = {"endcap": synth.Geometry.endcap(), "thick": synth.Geometry(thickness=tuple(0.6 for _ in range(10)))}.get(
         case, synth.Geometry())
     tuning = {"coarse": dict(bins_phi=3, bins_z=1), "one_bin": dict(bins_phi=1, bins_z=1)}.get(case, {})
@@ -242,10 +242,19 @@ def test_one_block_per_layer_index(gpu_required, case):
         counts = [len(e.seed_par) for e in evs]
         alone = [c.build(h, n) for h, n in zip(hs[:n_alone], counts[:n_alone])]
         batch = c.build_batch(hs, counts, flags=abi.BATCH_REINDEX)
+        graphs = []
+        if case in ("barrel", "thick", "edges"):
+            # the same pipeline captured once and replayed, eager calls between
+            for _ in range(2):
+                graphs.append(c.build_batch(hs, counts, flags=abi.BATCH_REINDEX | abi.BATCH_GRAPH))
+                c.build(hs[-1], counts[-1])
     finally:
         c.close()
     for a, b in zip(alone, batch):
         _equal(a, b)
+    for gr in graphs:
+        for a, b in zip(batch, gr):
+            _equal(a, b)
     if case in ("large", "wide"):
         for b in batch[1:]:
             _equal(batch[0], b)
