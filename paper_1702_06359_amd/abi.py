@@ -148,6 +148,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1702_06359_amd.build.build()")
+        # One HIP runtime per process: PyTorch ships its own, and the streams
+        # and device memory it hands to the library are only valid in that
+        # runtime.  Loaded first, it also serves the library (same soname);
+        # loaded after the library, a second runtime would come up beside it
+        # and the two contend for the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _PROTOS.items():
             fn = getattr(L, name)
@@ -238,15 +247,22 @@ class EventArrays:
 class TrackArrays:
     """Host output arrays plus the mkf_tracks that points at them."""
 
-    def __init__(self, n: int, n_layers: int):
-        self.par = np.zeros((n, 6))
-        self.cov = np.zeros((n, 21))
-        self.hits = np.zeros((n, n_layers), dtype=np.int32)
-        self.n_hits = np.zeros(n, dtype=np.int32)
-        self.n_holes = np.zeros(n, dtype=np.int32)
-        self.chi2 = np.zeros(n)
-        self.ndof = np.zeros(n, dtype=np.int32)
-        self.status = np.zeros(n, dtype=np.int32)
+    def __init__(self, n: int, n_layers: int, empty=None):
+        """empty(shape, dtype) makes each array (default: numpy zeros); a
+        factory over page-locked memory lets a caller reuse pinned buffers."""
+        mk = empty or (lambda shape, dtype: np.zeros(shape, dtype=dtype))
+        self.n = n
+        self.par = mk((n, 6), np.float64)
+        self.cov = mk((n, 21), np.float64)
+        self.hits = mk((n, n_layers), np.int32)
+        self.n_hits = mk((n,), np.int32)
+        self.n_holes = mk((n,), np.int32)
+        self.chi2 = mk((n,), np.float64)
+        self.ndof = mk((n,), np.int32)
+        self.status = mk((n,), np.int32)
+        for a in (self.par, self.cov, self.hits, self.n_hits, self.n_holes, self.chi2, self.ndof, self.status):
+            if not a.flags.c_contiguous:
+                raise ValueError("track arrays must be C-contiguous")
         t = Tracks()
         t.n = n
         t.par, t.cov, t.hits = _dp(self.par), _dp(self.cov), _ip(self.hits)
@@ -357,12 +373,15 @@ class Context:
         check(lib().mkf_build(self.h, int(handle), C.byref(out.tracks)))
         return out.as_dict()
 
-    def build_batch(self, handles: Sequence[int], n_seeds: Optional[Sequence[int]] = None, flags: int = 0):
+    def build_batch(self, handles: Sequence[int], n_seeds: Optional[Sequence[int]] = None, flags: int = 0,
+                    outs: Optional[Sequence["TrackArrays"]] = None):
+        """outs: caller-made TrackArrays to fill (their sizes give n_seeds)."""
         arr = np.ascontiguousarray(handles, dtype=np.int32)
-        if n_seeds is None:
+        if n_seeds is None and outs is None:
             check(lib().mkf_build_batch(self.h, _ip(arr), len(arr), flags, None))
             return None
-        outs = [TrackArrays(int(n), self.n_layers) for n in n_seeds]
+        if outs is None:
+            outs = [TrackArrays(int(n), self.n_layers) for n in n_seeds]
         tarr = (Tracks * len(outs))(*[o.tracks for o in outs])
         check(lib().mkf_build_batch(self.h, _ip(arr), len(arr), flags, tarr))
         return [o.as_dict() for o in outs]

@@ -1,8 +1,10 @@
 """Host-side checks of the C ABI (no GPU needed): the HIP library loads,
 exports every function include/mkf.h declares, and the Python binding's
 structures have the layout a C compiler gives the header's."""
+import ast
 import ctypes as C
 import os
+import sys
 import subprocess
 import tempfile
 
@@ -109,3 +111,17 @@ def test_invalid_config_rejected_before_device_work(libpath):
     cfg.layer_r[3] = cfg.layer_r[2]
     assert abi.lib().mkf_create(C.byref(cfg), None, None, C.byref(h)) == abi.E_INVALID
     assert "radii" in abi.last_error()
+
+
+def test_library_shares_one_hip_runtime_with_torch(libpath):
+    """Loading the library before anything imports torch must still leave a
+    single HIP runtime in the process (torch's), since torch's streams and
+    device memory are passed to the library."""
+    pytest.importorskip("torch")
+    code = ("from paper_1702_06359_amd import abi; abi.lib(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    libs = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
