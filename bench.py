@@ -246,6 +246,11 @@ def workload_ckf(args):
         result["endcap"] = endcap_leg(args)
         log("two-step workload")
         result["two_step"] = two_step_leg(args)
+        log("fit workload")
+        fit = workload_fit(argparse.Namespace(steps=5, warmup=1, no_cpu_baseline=True))
+        result["fit"] = {"workload": fit["config"]["workload"], "tracks_per_s": fit["value"],
+                         "ms_per_step": fit["ms_per_step"], "kernel_avg_ms": fit["roofline"]["kernel_avg_ms"],
+                         "frac_of_fp32_peak": fit["roofline"]["frac"], "hbm_frac": fit["roofline"]["hbm_frac"]}
         log("best-hit latency")
         result["best_hit"] = best_hit_latency()
         log("serving latency run")
