@@ -516,6 +516,21 @@ __global__ void __launch_bounds__(256) k_index_scatter(const Params P, const Bat
     }
 }
 
+// The blocks of a launch are dealt to the chip's eight XCDs in turn (block b
+// runs on XCD b mod 8), and each XCD has its own L2.  Renumbering them so
+// that every XCD takes one contiguous range of the work keeps what that
+// range reads (the hits of the few events it covers) in that XCD's L2
+// instead of every L2 holding a little of every event.  A bijection of
+// [0, n) for any n; blocks of one XCD keep their dispatch order.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int b, int n)
+{
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // Track building
 
@@ -1235,7 +1250,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     Hist H{s_dyn + wave * per_wave, reinterpret_cast<unsigned char *>(s_dyn + W * per_wave) + wave * per_wave,
            kWave};
     SearchLds<kGeo> &SL = reinterpret_cast<SearchLds<kGeo> *>(s_dyn + search_lds_offset(W, P.n_layers))[wave];
-    int item = blockIdx.x * W + wave;
+    int item = (persistent ? (int)blockIdx.x : xcd_contiguous(blockIdx.x, gridDim.x)) * W + wave;
     for (;;) {
         if (persistent) {
             unsigned v = 0;
@@ -1395,7 +1410,7 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
 template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_fit(const Params P, const BatchArgs B)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= B.total_tracks) return;
     const int e = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
     const DevEvent &E = B.events[e];
@@ -1484,7 +1499,7 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
 template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_refit(const Params P, const BatchArgs B)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= B.total_seeds) return;
     const int e = upper_bound_i32(B.seed_prefix, B.n_events + 1, g) - 1;
     const DevEvent &E = B.events[e];
