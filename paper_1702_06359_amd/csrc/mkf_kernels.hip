@@ -1,4 +1,8 @@
-// HIP kernels of the barrel Kalman-filter track builder (gfx950).
+// HIP kernels of the Kalman-filter track builder and fit (gfx950): the hit
+// index, the batched and the per-layer builders, the fit and the final fit
+// of built tracks, on barrel cylinders or endcap disks, thin or of finite
+// thickness, plus two calibration kernels (a streaming copy, an FP32
+// multiply-add loop).
 //
 // Layout: one lane = one track candidate.  A seed owns G consecutive lanes
 // (G = lanes_per_seed >= max_cands), so a wavefront carries 64/G seeds and a
