@@ -217,6 +217,7 @@ def workload_ckf(args):
     fit_steps = max(1, args.steps // 2)
     fit_elapsed = time_steps(step_fit, fit_steps, 0, sync)
     refit_ms, refit_n = ctx.timer_read(abi.TIMER_FIT)
+    fit_vs_build = fitted_vs_built(ctx, evs[0], handles[0])
     plain_rate = None
     if not args.quick:
         # the plain per-event builder (one launch per layer) on the same events
@@ -236,7 +237,8 @@ def workload_ckf(args):
         "index_build_ms_per_step": round(index_ms / max(index_n, 1), 4),
         "build_and_fit": {"tracks_per_s": round(tracks * fit_steps / fit_elapsed, 1),
                           "ms_per_step": round(fit_elapsed / fit_steps * 1e3, 4),
-                          "final_fit_kernel_ms": round(refit_ms / max(refit_n, 1), 4)},
+                          "final_fit_kernel_ms": round(refit_ms / max(refit_n, 1), 4),
+                          "fitted_vs_built": fit_vs_build},
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:
@@ -306,6 +308,30 @@ def best_hit_latency(reps=10):
     return {"workload": "best-hit building, 1 event x 1,000 tracks, no noise, k=1, plain builder",
             "device_resident_ms_p50": round(float(np.median(dev)) * 1e3, 4),
             "end_to_end_ms_p50": round(float(np.median(e2e)) * 1e3, 4)}
+
+
+def fitted_vs_built(ctx, ev, h):
+    """Final fit against the build's own state on one event (after a build
+    with the final fit chained): on tracks whose every hit is the true one and
+    that reached the last layer, the RMS pulls of q/pT, phi and theta against
+    the true state there, for the built and the fitted parameters, and the
+    RMS of their difference over the built sigma."""
+    built, fitted = ctx.fetch_tracks(h, ev.n_seeds), ctx.fetch_fit(h, ev.n_seeds)
+    good = (built["hits"] == ev.truth_hit).all(1) & (built["status"] == 0) & (fitted["status"] == 0)
+    last = ev.truth_par.shape[1] - 1
+    out = {"tracks": int(good.sum()), "of": int(ev.n_seeds)}
+    for name, d in (("built", built), ("fitted", fitted)):
+        out[name + "_pull_rms"] = {}
+        for i, k in ((3, "q/pT"), (4, "phi"), (5, "theta")):
+            sig = np.sqrt(d["cov"][good, 6 * i - i * (i - 1) // 2])
+            pull = (d["par"][good, i] - ev.truth_par[good, last, i]) / sig
+            out[name + "_pull_rms"][k] = round(float(np.sqrt(np.mean(pull ** 2))), 3)
+    out["diff_over_built_sigma_rms"] = {}
+    for i, k in ((3, "q/pT"), (4, "phi"), (5, "theta")):
+        sig = np.sqrt(built["cov"][good, 6 * i - i * (i - 1) // 2])
+        dd = (fitted["par"][good, i] - built["par"][good, i]) / sig
+        out["diff_over_built_sigma_rms"][k] = round(float(np.sqrt(np.mean(dd ** 2))), 4)
+    return out
 
 
 def host_inclusive(ctx, evs, reps=3):
