@@ -317,6 +317,9 @@ def fitted_vs_built(ctx, ev, h):
     the true state there, for the built and the fitted parameters, and the
     RMS of their difference over the built sigma."""
     built, fitted = ctx.fetch_tracks(h, ev.n_seeds), ctx.fetch_fit(h, ev.n_seeds)
+
+    def wrap(d, i):   # azimuth differences into (-pi, pi]
+        return np.remainder(d + np.pi, 2 * np.pi) - np.pi if i == 4 else d
     good = (built["hits"] == ev.truth_hit).all(1) & (built["status"] == 0) & (fitted["status"] == 0)
     last = ev.truth_par.shape[1] - 1
     out = {"tracks": int(good.sum()), "of": int(ev.n_seeds)}
@@ -324,12 +327,12 @@ def fitted_vs_built(ctx, ev, h):
         out[name + "_pull_rms"] = {}
         for i, k in ((3, "q/pT"), (4, "phi"), (5, "theta")):
             sig = np.sqrt(d["cov"][good, 6 * i - i * (i - 1) // 2])
-            pull = (d["par"][good, i] - ev.truth_par[good, last, i]) / sig
+            pull = wrap(d["par"][good, i] - ev.truth_par[good, last, i], i) / sig
             out[name + "_pull_rms"][k] = round(float(np.sqrt(np.mean(pull ** 2))), 3)
     out["diff_over_built_sigma_rms"] = {}
     for i, k in ((3, "q/pT"), (4, "phi"), (5, "theta")):
         sig = np.sqrt(built["cov"][good, 6 * i - i * (i - 1) // 2])
-        dd = (fitted["par"][good, i] - built["par"][good, i]) / sig
+        dd = wrap(fitted["par"][good, i] - built["par"][good, i], i) / sig
         out["diff_over_built_sigma_rms"][k] = round(float(np.sqrt(np.mean(dd ** 2))), 4)
     return out
 
