@@ -183,12 +183,18 @@ def test_repeat_and_batch_composition_are_deterministic(ctx6):
         print("case determinism 3 events", flush=True)
         all3 = ctx6.build_batch(hs, [e.n_seeds for e in evs])
         again = ctx6.build_batch(hs, [e.n_seeds for e in evs], flags=abi.BATCH_REINDEX)
+        # caller-made output arrays, pre-filled with garbage
+        mine = [abi.TrackArrays(e.n_seeds, 10, empty=lambda shape, dtype: np.full(shape, 77, dtype=dtype))
+                for e in evs]
+        ctx6.build_batch(hs, outs=mine)
+        mine = [o.as_dict() for o in mine]
         rev = ctx6.build_batch(hs[::-1], [e.n_seeds for e in evs[::-1]])[::-1]
         alone = [ctx6.build(h, e.n_seeds) for h, e in zip(hs, evs)]
     finally:
         for h in hs:
             ctx6.unload_event(h)
-    for a, b, c, d in zip(all3, again, rev, alone):
+    for a, b, c, d, m in zip(all3, again, rev, alone, mine):
+        _equal(a, m)
         _equal(a, b)
         _equal(a, c)
         _equal(a, d)
