@@ -20,6 +20,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 MAX_LAYERS = 16
 MAX_CANDS = 16
+MAX_ALT = 4
+CUT_CONSIDER = 0.1      # decisions re-run to test their relevance (see mkf_oracle.h)
+RANK_CONSIDER = 0.01
 
 
 class OrcConfig(C.Structure):
@@ -45,6 +48,9 @@ class OrcTrack(C.Structure):
         ("hits", C.c_int32 * MAX_LAYERS), ("n_hits", C.c_int32), ("n_holes", C.c_int32),
         ("status", C.c_int32), ("n_final", C.c_int32),
         ("m_cut", C.c_double), ("m_rank", C.c_double), ("m_prop", C.c_double),
+        ("m_cut_raw", C.c_double), ("m_rank_raw", C.c_double),
+        ("n_alt", C.c_int32), ("alt_kind", C.c_int32 * MAX_ALT), ("alt_margin", C.c_double * MAX_ALT),
+        ("alt_hits", (C.c_int32 * MAX_LAYERS) * MAX_ALT), ("alt_status", C.c_int32 * MAX_ALT),
         ("n_prop", C.c_int64), ("n_accept", C.c_int64), ("n_update", C.c_int64),
     ]
 
@@ -54,8 +60,11 @@ TRACK_DTYPE = np.dtype([
     ("hits", np.int32, MAX_LAYERS), ("n_hits", np.int32), ("n_holes", np.int32),
     ("status", np.int32), ("n_final", np.int32),
     ("m_cut", np.float64), ("m_rank", np.float64), ("m_prop", np.float64),
+    ("m_cut_raw", np.float64), ("m_rank_raw", np.float64),
+    ("n_alt", np.int32), ("alt_kind", np.int32, MAX_ALT), ("alt_margin", np.float64, MAX_ALT),
+    ("alt_hits", np.int32, (MAX_ALT, MAX_LAYERS)), ("alt_status", np.int32, MAX_ALT),
     ("n_prop", np.int64), ("n_accept", np.int64), ("n_update", np.int64),
-])
+], align=True)
 assert TRACK_DTYPE.itemsize == C.sizeof(OrcTrack)
 
 

@@ -173,56 +173,87 @@ static int helix_to(const double p[6], double s, double bz, int kind, double r, 
     return 0;
 }
 
+/* Intersections of the track's transverse circle with the circle |P| = r.
+ * The track circle passes through p0 = (x, y) with tangent t = (cos phi,
+ * sin phi); its centre is c = p0 + n / w with n = (-sin phi, cos phi) the left
+ * normal, its radius 1/|w|.  Two circles meet on their radical line, the
+ * points with equal power |P|^2 - r^2 = |P - c|^2 - 1/w^2; the 1/w^2 terms
+ * cancel exactly, and multiplied by w the line reads
+ *   P . m = q,   m = w p0 + n,   q = w (|p0|^2 + r^2) / 2 + p0 . n,
+ * which for w = 0 is the track's own straight line (the line-circle case).
+ * The line meets |P| = r at the foot point (q / |m|^2) m plus or minus the
+ * half chord h along m's perpendicular, h^2 = r^2 - q^2 / |m|^2.  Returns the
+ * number of points (0 or 2) and the signed margin r - |q| / |m| (zero at
+ * tangency, negative when the circles do not meet). */
+static int circle_points(const double p[6], double r, double w, double P[2][2], double *margin)
+{
+    const double x = p[0], y = p[1], cph = cos(p[4]), sph = sin(p[4]);
+    const double nx = -sph, ny = cph;
+    const double mx = w * x + nx, my = w * y + ny;
+    const double m2 = mx * mx + my * my;
+    const double q = 0.5 * w * (x * x + y * y + r * r) + (x * nx + y * ny);
+    if (!(m2 > 0.0)) {          /* concentric circles: no crossing point */
+        *margin = 0.0;
+        return 0;
+    }
+    const double mn = sqrt(m2);
+    const double dist = q / mn;
+    *margin = r - fabs(dist);
+    const double h2 = r * r - dist * dist;
+    if (h2 < 0.0) return 0;
+    const double h = sqrt(h2);
+    const double fx = dist * mx / mn, fy = dist * my / mn;    /* foot point */
+    const double ux = -my / mn, uy = mx / mn;                 /* along the line */
+    P[0][0] = fx + h * ux;
+    P[0][1] = fy + h * uy;
+    P[1][0] = fx - h * ux;
+    P[1][1] = fy - h * uy;
+    return 2;
+}
+
+/* Signed transverse path from p0 to a point P of the track circle, with the
+ * turning angle in (-pi, pi]: the displacement d = P - p0 has components
+ * d.t = sin(a) / w and d.n = (1 - cos a) / w for a turn a = w s, so
+ * a = atan2(w d.t, 1 - w d.n); at w = 0 the path is d.t. */
+static double path_to_point(const double p[6], double w, const double P[2], double *turn)
+{
+    const double cph = cos(p[4]), sph = sin(p[4]);
+    const double dx = P[0] - p[0], dy = P[1] - p[1];
+    const double dt = dx * cph + dy * sph, dn = -dx * sph + dy * cph;
+    if (w == 0.0) {
+        *turn = 0.0;
+        return dt;
+    }
+    const double a = atan2(w * dt, 1.0 - w * dn);
+    *turn = a;
+    return a / w;
+}
+
 int orc_propagate(const double p[6], double r, double bz, double out[6], double F[36],
                   double *path, double *margin)
 {
-    const double x = p[0], y = p[1], z = p[2], qpt = p[3], phi = p[4], th = p[5];
-    const double w = -KAPPA * bz * qpt;
-    double s = -1.0, mrg;
-
-    /* Closed form for the path.  After turning by a = w s the chord from the
-     * start is (2/w) sin(d) along phi + d, with d = a/2.  Requiring the end
-     * point on the cylinder and writing T = tan(d)/w gives the quadratic
-     *   alpha T^2 + b T - D/4 = 0,
-     *   b = x cos phi + y sin phi,  e = -x sin phi + y cos phi,
-     *   D = r^2 - (x^2 + y^2),      alpha = 1 + w e - w^2 D / 4,
-     * whose w -> 0 limit is the straight line.  Each root gives d = atan(w T)
-     * or d + pi (the far half of the circle); the path is the smallest
-     * positive s = 2 d / w. */
-    const double b = x * cos(phi) + y * sin(phi);
-    const double e = -x * sin(phi) + y * cos(phi);
-    const double D = r * r - (x * x + y * y);
-    const double alpha = 1.0 + w * e - 0.25 * w * w * D;
-    const double disc = b * b + alpha * D;
-    if (fabs(w) * r > 1e-6) {
-        const double R = 1.0 / fabs(w);
-        const double cx = x - sin(phi) / w, cy = y + cos(phi) / w;
-        mrg = R + hypot(cx, cy) - r;        /* distance to outer tangency */
-    } else {
-        mrg = r - fabs(e);                  /* straight line: distance to tangency */
-    }
-    if (disc >= 0.0) {
-        const double q = sqrt(disc);
-        double roots[2];
-        int nr = 0;
-        if (b + q != 0.0) roots[nr++] = 0.5 * D / (b + q);
-        if (alpha != 0.0) roots[nr++] = -(b + q) / (2.0 * alpha);
-        for (int i = 0; i < nr; ++i) {
-            const double u = w * roots[i];
-            /* s = 2 atan(u) / w, evaluated as 2 T atan(u)/u near u = 0 */
-            double atanc = fabs(u) < 1e-4 ? 1.0 - u * u / 3.0 + u * u * u * u / 5.0 : atan(u) / u;
-            double cand[2];
-            int nc = 0;
-            cand[nc++] = 2.0 * roots[i] * atanc;
-            if (w != 0.0) cand[nc++] = 2.0 * (atan(u) + (w > 0.0 ? PI : -PI)) / w;
-            for (int c = 0; c < nc; ++c)
-                if (cand[c] > 1e-12 * r && (s < 0.0 || cand[c] < s)) s = cand[c];
+    const double w = -KAPPA * bz * p[3];
+    double P[2][2], mrg;
+    const int np = circle_points(p, r, w, P, &mrg);
+    if (margin) *margin = mrg;
+    /* the first crossing ahead: every point is reached after a positive path,
+     * a turn of up to one full revolution in the sense of w */
+    double s = -1.0;
+    int best = -1;
+    for (int i = 0; i < np; ++i) {
+        double a, si = path_to_point(p, w, P[i], &a);
+        if (w > 0.0 && a <= 0.0) si = (a + 2.0 * PI) / w;
+        else if (w < 0.0 && a >= 0.0) si = (a - 2.0 * PI) / w;
+        if (si > 1e-12 * r && (best < 0 || si < s)) {
+            s = si;
+            best = i;
         }
     }
-    if (margin) *margin = mrg;
-    if (!(s > 0.0)) return 1;
-
-    return helix_to(p, s, bz, 0, r, out, F, path);
+    if (best < 0) return 1;
+    helix_to(p, s, bz, 0, r, out, F, path);
+    out[0] = P[best][0];         /* the crossing point itself, on the cylinder */
+    out[1] = P[best][1];
+    return 0;
 }
 
 /* Propagation to the plane z = zd (an endcap disk of the simplified
@@ -245,8 +276,9 @@ int orc_propagate_plane(const double p[6], double zd, double bz, double out[6], 
  * average radius or z to the exact surface of a hit): the crossing of the
  * cylinder of radius `where` (kind 0) or of the plane z = `where` (kind 1)
  * nearest along the helix, ahead of the state or behind it.  On a cylinder,
- * of the two roots of the path quadratic (principal branch, |w s| < pi) the
- * one of smaller |s|.  Returns 1 when the helix never reaches the surface. */
+ * of the two crossing points of the circles, each reached by a turn of at
+ * most half a revolution either way, the one of smaller |s|.  Returns 1 when
+ * the helix never reaches the surface. */
 int orc_step_near(const double p[6], int kind, double where, double bz, double out[6], double F[36],
                   double *path)
 {
@@ -258,33 +290,24 @@ int orc_step_near(const double p[6], int kind, double where, double bz, double o
         out[2] = where;
         return 0;
     }
-    const double x = p[0], y = p[1], qpt = p[3], phi = p[4];
-    const double w = -KAPPA * bz * qpt;
-    const double b = x * cos(phi) + y * sin(phi);
-    const double e = -x * sin(phi) + y * cos(phi);
-    const double D = where * where - (x * x + y * y);
-    const double alpha = 1.0 + w * e - 0.25 * w * w * D;
-    const double disc = b * b + alpha * D;
-    if (!(disc >= 0.0)) return 1;
-    /* roots T = (-b -+ q) / (2 alpha), written without cancellation */
-    const double q = sqrt(disc);
-    const double bq = b >= 0.0 ? b + q : b - q;
-    double roots[2];
-    int nr = 0;
-    if (bq != 0.0) roots[nr++] = 0.5 * D / bq;
-    if (alpha != 0.0 && bq != 0.0) roots[nr++] = -0.5 * bq / alpha;
-    if (nr == 0 && D == 0.0) roots[nr++] = 0.0;
-    int found = 0;
+    const double w = -KAPPA * bz * p[3];
+    double P[2][2], mrg;
+    const int np = circle_points(p, where, w, P, &mrg);
+    int best = -1;
     s = 0.0;
-    for (int i = 0; i < nr; ++i) {
-        const double u = w * roots[i];
-        const double atanc = fabs(u) < 1e-4 ? 1.0 - u * u / 3.0 + u * u * u * u / 5.0 : atan(u) / u;
-        const double si = 2.0 * roots[i] * atanc;
-        if (!found || fabs(si) < fabs(s)) s = si;
-        found = 1;
+    for (int i = 0; i < np; ++i) {
+        double a;
+        const double si = path_to_point(p, w, P[i], &a);    /* principal turn, either sign */
+        if (best < 0 || fabs(si) < fabs(s)) {
+            s = si;
+            best = i;
+        }
     }
-    if (!found) return 1;
-    return helix_to(p, s, bz, 0, where, out, F, path);
+    if (best < 0) return 1;
+    helix_to(p, s, bz, 0, where, out, F, path);
+    out[0] = P[best][0];
+    out[1] = P[best][1];
+    return 0;
 }
 
 void orc_transport(const double F[36], double C[36])
@@ -763,46 +786,82 @@ typedef struct {
     orc_track *beam;    /* optional: [n_sel][max_cands], every rank of the final beam */
 } build_ctx;
 
-static void build_one(void *vctx, int64_t row)
+typedef struct {
+    cand_t c[ORC_MAX_CANDS];
+    int n;
+} beam_t;
+
+/* A decision of the beam search that FP32 arithmetic could take the other
+ * way: kind 0, the cut on hit `hit` for beam candidate `cand` on `layer`;
+ * kind 1, the choice between the k-th and (k+1)-th entries of `layer`;
+ * kind 2, the final choice between ranks 0 and 1. */
+typedef struct {
+    int32_t layer, cand, hit, kind;
+    double margin;
+} decision_t;
+
+/* What the main run of a seed records: margins, counters, the near
+ * decisions and the beam before every layer. */
+typedef struct {
+    double m_cut_raw, m_cut_far, m_rank_raw, m_rank_far, m_prop;
+    int64_t n_prop, n_accept, n_update;
+    decision_t *dec;
+    int n_dec, cap_dec;
+    beam_t *snap;
+} run_log;
+
+static void note_decision(run_log *log, int layer, int cand, int hit, int kind, double margin)
 {
-    const build_ctx *bc = (const build_ctx *)vctx;
+    if (log->n_dec == log->cap_dec) {
+        log->cap_dec = log->cap_dec ? 2 * log->cap_dec : 16;
+        log->dec = (decision_t *)realloc(log->dec, log->cap_dec * sizeof(decision_t));
+    }
+    decision_t *d = &log->dec[log->n_dec++];
+    d->layer = layer;
+    d->cand = cand;
+    d->hit = hit;
+    d->kind = kind;
+    d->margin = margin;
+}
+
+static entry_t *push_entry(entry_t **ent, int *ne, int *cap)
+{
+    if (*ne == *cap) {
+        *cap *= 2;
+        *ent = (entry_t *)realloc(*ent, *cap * sizeof(entry_t));
+    }
+    return &(*ent)[(*ne)++];
+}
+
+/* The beam search over layers L0 .. n_layers-1 from beam b (updated in
+ * place).  `flip` (may be NULL) takes one decision the other way; `log`
+ * (NULL in those re-runs) records margins, counters, near decisions and the
+ * beam before each layer. */
+static void run_layers(const build_ctx *bc, int L0, beam_t *b, const decision_t *flip, run_log *log)
+{
     const orc_config *cfg = bc->cfg;
-    const int nl = cfg->n_layers, nsl = cfg->n_seed_layers;
+    const int nl = cfg->n_layers;
     int k = cfg->max_cands;
     if (k > ORC_MAX_CANDS) k = ORC_MAX_CANDS;
-    const int64_t sid = bc->seed_ids ? bc->seed_ids[row] : row;
-    orc_track *o = &bc->out[row];
-
-    cand_t beam[ORC_MAX_CANDS], next[ORC_MAX_CANDS];
+    cand_t next[ORC_MAX_CANDS];
     double pred_par[ORC_MAX_CANDS][6], pred_C[ORC_MAX_CANDS][36];
-    int nb = 1;
-    memset(&beam[0], 0, sizeof(cand_t));
-    memcpy(beam[0].par, bc->seed_par + 6 * sid, 6 * sizeof(double));
-    unpack21(bc->seed_cov + 21 * sid, beam[0].C);
-    for (int L = 0; L < ORC_MAX_LAYERS; ++L) beam[0].hits[L] = -1;
-    for (int L = 0; L < nsl; ++L) {
-        beam[0].hits[L] = bc->seed_hits[sid * nsl + L];
-        if (beam[0].hits[L] >= 0) beam[0].n_hits++;
-    }
-
-    double m_cut = INFINITY, m_rank = INFINITY, m_prop = INFINITY;
-    int64_t n_prop = 0, n_accept = 0, n_update = 0;
     int cap = 64, ne = 0;
     entry_t *ent = (entry_t *)malloc(cap * sizeof(entry_t));
 
-    for (int L = nsl; L < nl; ++L) {
+    for (int L = L0; L < nl; ++L) {
+        if (log) log->snap[L] = *b;
         ne = 0;
         const double r = cfg->radius[L];
-        for (int c = 0; c < nb; ++c) {
-            cand_t *cd = &beam[c];
+        for (int c = 0; c < b->n; ++c) {
+            cand_t *cd = &b->c[c];
             if (!cd->stopped) {
                 double p[6], C[36], F[36], mrg;
                 memcpy(p, cd->par, sizeof(p));
                 memcpy(C, cd->C, sizeof(C));
                 leave_layer(cfg, L - 1, p, C);
-                ++n_prop;
+                if (log) ++log->n_prop;
                 int fail = to_layer(cfg, L, p, pred_par[c], F, &mrg);
-                if (fabs(mrg) / r < m_prop) m_prop = fabs(mrg) / r;
+                if (log && fabs(mrg) / r < log->m_prop) log->m_prop = fabs(mrg) / r;
                 if (fail) {
                     cd->stopped = 1;
                     cd->status = 2;       /* keeps its state on the previous surface */
@@ -824,14 +883,17 @@ static void build_one(void *vctx, int64_t row)
                         } else {
                             c2 = layer_chi2(cfg, L, pp, pred_C[c], h);
                         }
-                        double dm = fabs(c2 - cfg->chi2_cut);
-                        if (dm < m_cut) m_cut = dm;
-                        if (c2 < cfg->chi2_cut) {
-                            if (ne == cap) {
-                                cap *= 2;
-                                ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
-                            }
-                            entry_t *e = &ent[ne++];
+                        const double dm = fabs(c2 - cfg->chi2_cut);
+                        if (log) {
+                            if (dm < log->m_cut_raw) log->m_cut_raw = dm;
+                            if (dm < ORC_CUT_CONSIDER) note_decision(log, L, c, j, 0, dm);
+                            else if (dm < log->m_cut_far) log->m_cut_far = dm;
+                        }
+                        int accept = c2 < cfg->chi2_cut;
+                        if (flip && flip->kind == 0 && flip->layer == L && flip->cand == c && flip->hit == j)
+                            accept = !accept;
+                        if (accept) {
+                            entry_t *e = push_entry(&ent, &ne, &cap);
                             e->n_hits = cd->n_hits + 1;
                             e->chi2 = cd->chi2 + c2;
                             e->hit_chi2 = c2;
@@ -841,14 +903,10 @@ static void build_one(void *vctx, int64_t row)
                             ++nacc;
                         }
                     }
-                    n_accept += nacc;
+                    if (log) log->n_accept += nacc;
                     if (nacc == 0 || cfg->hole_always) {
                         if (cd->n_holes < cfg->max_holes) {
-                            if (ne == cap) {
-                                cap *= 2;
-                                ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
-                            }
-                            entry_t *e = &ent[ne++];
+                            entry_t *e = push_entry(&ent, &ne, &cap);
                             e->n_hits = cd->n_hits;
                             e->chi2 = cd->chi2;
                             e->hit_chi2 = 0.0;
@@ -866,11 +924,7 @@ static void build_one(void *vctx, int64_t row)
                 }
             }
             if (cd->stopped) {
-                if (ne == cap) {
-                    cap *= 2;
-                    ent = (entry_t *)realloc(ent, cap * sizeof(entry_t));
-                }
-                entry_t *e = &ent[ne++];
+                entry_t *e = push_entry(&ent, &ne, &cap);
                 e->n_hits = cd->n_hits;
                 e->chi2 = cd->chi2;
                 e->hit_chi2 = 0.0;
@@ -881,13 +935,22 @@ static void build_one(void *vctx, int64_t row)
         }
         qsort(ent, ne, sizeof(entry_t), entry_cmp);
         if (ne > k && ent[k - 1].n_hits == ent[k].n_hits) {
-            double gap = (ent[k].chi2 - ent[k - 1].chi2) / (1.0 + ent[k - 1].chi2);
-            if (gap < m_rank) m_rank = gap;
+            const double gap = (ent[k].chi2 - ent[k - 1].chi2) / (1.0 + ent[k - 1].chi2);
+            if (log) {
+                if (gap < log->m_rank_raw) log->m_rank_raw = gap;
+                if (gap < ORC_RANK_CONSIDER) note_decision(log, L, -1, -1, 1, gap);
+                else if (gap < log->m_rank_far) log->m_rank_far = gap;
+            }
+            if (flip && flip->kind == 1 && flip->layer == L) {
+                const entry_t t = ent[k - 1];
+                ent[k - 1] = ent[k];
+                ent[k] = t;
+            }
         }
-        int nn = ne < k ? ne : k;
+        const int nn = ne < k ? ne : k;
         for (int i = 0; i < nn; ++i) {
             const entry_t *e = &ent[i];
-            const cand_t *par = &beam[e->parent];
+            const cand_t *par = &b->c[e->parent];
             cand_t *nc = &next[i];
             *nc = *par;
             if (e->kind == KIND_HIT) {
@@ -902,23 +965,108 @@ static void build_one(void *vctx, int64_t row)
                 nc->chi2 = e->chi2;
                 nc->hits[L] = e->hit;
                 nc->n_hits = e->n_hits;
-                ++n_update;
+                if (log) ++log->n_update;
             } else if (e->kind == KIND_HOLE) {
                 memcpy(nc->par, pred_par[e->parent], sizeof(nc->par));
                 memcpy(nc->C, pred_C[e->parent], sizeof(nc->C));
                 nc->n_holes++;
             }
         }
-        memcpy(beam, next, nn * sizeof(cand_t));
-        nb = nn;
+        memcpy(b->c, next, nn * sizeof(cand_t));
+        b->n = nn;
     }
     free(ent);
+}
 
-    if (nb > 1 && beam[0].n_hits == beam[1].n_hits) {
-        double gap = (beam[1].chi2 - beam[0].chi2) / (1.0 + beam[0].chi2);
-        if (gap < m_rank) m_rank = gap;
+static int same_outcome(const cand_t *a, const cand_t *b, int nl)
+{
+    if (a->status != b->status) return 0;
+    for (int L = 0; L < nl; ++L)
+        if (a->hits[L] != b->hits[L]) return 0;
+    return 1;
+}
+
+static int cmp_decision(const void *va, const void *vb)
+{
+    const decision_t *a = (const decision_t *)va, *b = (const decision_t *)vb;
+    /* in units of each kind's consideration window */
+    const double ra = a->margin / (a->kind == 0 ? ORC_CUT_CONSIDER : ORC_RANK_CONSIDER);
+    const double rb = b->margin / (b->kind == 0 ? ORC_CUT_CONSIDER : ORC_RANK_CONSIDER);
+    return ra < rb ? -1 : (ra > rb ? 1 : 0);
+}
+
+/* re-runs per seed at most; decisions beyond count as relevant */
+#define MAX_RERUNS 24
+
+static void build_one(void *vctx, int64_t row)
+{
+    const build_ctx *bc = (const build_ctx *)vctx;
+    const orc_config *cfg = bc->cfg;
+    const int nl = cfg->n_layers, nsl = cfg->n_seed_layers;
+    int k = cfg->max_cands;
+    if (k > ORC_MAX_CANDS) k = ORC_MAX_CANDS;
+    const int64_t sid = bc->seed_ids ? bc->seed_ids[row] : row;
+    orc_track *o = &bc->out[row];
+
+    beam_t b;
+    memset(&b, 0, sizeof(b));
+    b.n = 1;
+    memcpy(b.c[0].par, bc->seed_par + 6 * sid, 6 * sizeof(double));
+    unpack21(bc->seed_cov + 21 * sid, b.c[0].C);
+    for (int L = 0; L < ORC_MAX_LAYERS; ++L) b.c[0].hits[L] = -1;
+    for (int L = 0; L < nsl; ++L) {
+        b.c[0].hits[L] = bc->seed_hits[sid * nsl + L];
+        if (b.c[0].hits[L] >= 0) b.c[0].n_hits++;
     }
-    const cand_t *best = &beam[0];
+
+    run_log log;
+    memset(&log, 0, sizeof(log));
+    log.m_cut_raw = log.m_cut_far = log.m_rank_raw = log.m_rank_far = log.m_prop = INFINITY;
+    log.snap = (beam_t *)malloc(ORC_MAX_LAYERS * sizeof(beam_t));
+    run_layers(bc, nsl, &b, NULL, &log);
+
+    if (b.n > 1 && b.c[0].n_hits == b.c[1].n_hits) {
+        const double gap = (b.c[1].chi2 - b.c[0].chi2) / (1.0 + b.c[0].chi2);
+        if (gap < log.m_rank_raw) log.m_rank_raw = gap;
+        if (gap < ORC_RANK_CONSIDER) note_decision(&log, nl, -1, -1, 2, gap);
+        else if (gap < log.m_rank_far) log.m_rank_far = gap;
+    }
+
+    /* which near decisions change the output: re-run each one inverted from
+     * the beam before its layer, smallest margins first */
+    double m_cut = log.m_cut_far, m_rank = log.m_rank_far;
+    o->n_alt = 0;
+    qsort(log.dec, log.n_dec, sizeof(decision_t), cmp_decision);
+    for (int d = 0; d < log.n_dec; ++d) {
+        const decision_t *dc = &log.dec[d];
+        cand_t alt;
+        int relevant = 1;
+        if (dc->kind == 2) {
+            alt = b.c[1];
+        } else if (d < MAX_RERUNS) {
+            beam_t rb = log.snap[dc->layer];
+            run_layers(bc, dc->layer, &rb, dc, NULL);
+            alt = rb.c[0];
+            relevant = rb.n > 0 && !same_outcome(&alt, &b.c[0], nl);
+        }
+        if (!relevant) continue;
+        if (dc->kind == 0) {
+            if (dc->margin < m_cut) m_cut = dc->margin;
+        } else if (dc->margin < m_rank) {
+            m_rank = dc->margin;
+        }
+        if ((dc->kind == 2 || d < MAX_RERUNS) && o->n_alt < ORC_MAX_ALT) {
+            const int a = o->n_alt++;
+            o->alt_kind[a] = dc->kind;
+            o->alt_margin[a] = dc->margin;
+            for (int L = 0; L < ORC_MAX_LAYERS; ++L) o->alt_hits[a][L] = L < nl ? alt.hits[L] : -1;
+            o->alt_status[a] = alt.status;
+        }
+    }
+    free(log.dec);
+    free(log.snap);
+
+    const cand_t *best = &b.c[0];
     memcpy(o->par, best->par, sizeof(o->par));
     pack21(best->C, o->cov);
     o->chi2 = best->chi2;
@@ -926,35 +1074,37 @@ static void build_one(void *vctx, int64_t row)
     o->n_hits = best->n_hits;
     o->n_holes = best->n_holes;
     o->status = best->status;
-    o->n_final = nb;
+    o->n_final = b.n;
     o->m_cut = m_cut;
     o->m_rank = m_rank;
-    o->m_prop = m_prop;
-    o->n_prop = n_prop;
-    o->n_accept = n_accept;
-    o->n_update = n_update;
+    o->m_prop = log.m_prop;
+    o->m_cut_raw = log.m_cut_raw;
+    o->m_rank_raw = log.m_rank_raw;
+    o->n_prop = log.n_prop;
+    o->n_accept = log.n_accept;
+    o->n_update = log.n_update;
     if (bc->beam) {
         /* the whole final beam, rank by rank; ranks beyond it are empty (status -1) */
         for (int r = 0; r < k; ++r) {
-            orc_track *b = &bc->beam[row * k + r];
-            *b = *o;
-            if (r >= nb) {
-                memset(b->par, 0, sizeof(b->par));
-                memset(b->cov, 0, sizeof(b->cov));
-                b->chi2 = 0.0;
-                for (int L = 0; L < ORC_MAX_LAYERS; ++L) b->hits[L] = -1;
-                b->n_hits = b->n_holes = 0;
-                b->status = -1;
+            orc_track *t = &bc->beam[row * k + r];
+            *t = *o;
+            if (r >= b.n) {
+                memset(t->par, 0, sizeof(t->par));
+                memset(t->cov, 0, sizeof(t->cov));
+                t->chi2 = 0.0;
+                for (int L = 0; L < ORC_MAX_LAYERS; ++L) t->hits[L] = -1;
+                t->n_hits = t->n_holes = 0;
+                t->status = -1;
                 continue;
             }
-            const cand_t *cd = &beam[r];
-            memcpy(b->par, cd->par, sizeof(b->par));
-            pack21(cd->C, b->cov);
-            b->chi2 = cd->chi2;
-            for (int L = 0; L < ORC_MAX_LAYERS; ++L) b->hits[L] = L < nl ? cd->hits[L] : -1;
-            b->n_hits = cd->n_hits;
-            b->n_holes = cd->n_holes;
-            b->status = cd->status;
+            const cand_t *cd = &b.c[r];
+            memcpy(t->par, cd->par, sizeof(t->par));
+            pack21(cd->C, t->cov);
+            t->chi2 = cd->chi2;
+            for (int L = 0; L < ORC_MAX_LAYERS; ++L) t->hits[L] = L < nl ? cd->hits[L] : -1;
+            t->n_hits = cd->n_hits;
+            t->n_holes = cd->n_holes;
+            t->status = cd->status;
         }
     }
 }

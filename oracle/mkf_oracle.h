@@ -21,6 +21,9 @@ extern "C" {
 
 #define ORC_MAX_LAYERS 16
 #define ORC_MAX_CANDS 16
+#define ORC_MAX_ALT 4
+#define ORC_CUT_CONSIDER 0.1      /* |chi2 - cut| below which a decision is re-run */
+#define ORC_RANK_CONSIDER 0.01    /* relative key gap below which a rank decision is re-run */
 
 typedef struct {
     int32_t n_layers;
@@ -60,10 +63,25 @@ typedef struct {
     int32_t n_holes;
     int32_t status;             /* 0 reached last layer, 1 hole limit, 2 propagation failed */
     int32_t n_final;            /* candidates alive in the final beam */
-    /* decision margins, for the tie protocol of the parity tests */
-    double m_cut;               /* min |chi2 - cut| over all (candidate, hit) chi2 evaluated */
-    double m_rank;              /* min relative key gap at beam boundaries and final choice */
+    /* Decision margins, for the tie protocol of the parity tests.  A
+     * decision is relevant when taking it the other way changes the output
+     * (the rank-0 hit list or status): every decision within ORC_CUT_CONSIDER
+     * of the cut or ORC_RANK_CONSIDER of a rank tie is re-run from the beam
+     * before its layer with the decision inverted.  m_cut and m_rank are the
+     * smallest margins of relevant decisions and of decisions beyond those
+     * windows (not examined); the _raw values count every decision. */
+    double m_cut;               /* |chi2 - cut| */
+    double m_rank;              /* relative key gap at the k/(k+1) boundary or the final rank-0/rank-1 choice */
     double m_prop;              /* min |distance to tangency| / r over propagations */
+    double m_cut_raw;
+    double m_rank_raw;
+    /* outcomes of the relevant decisions of smallest margin, taken the other
+     * way (alt_kind 0 cut, 1 beam boundary, 2 final choice); n_alt of them */
+    int32_t n_alt;
+    int32_t alt_kind[ORC_MAX_ALT];
+    double alt_margin[ORC_MAX_ALT];
+    int32_t alt_hits[ORC_MAX_ALT][ORC_MAX_LAYERS];
+    int32_t alt_status[ORC_MAX_ALT];
     /* counters */
     int64_t n_prop;             /* candidate-layers propagated */
     int64_t n_accept;           /* (candidate, hit) pairs passing the cut */

@@ -412,7 +412,9 @@ def test_full_final_beam_parity(ctx6):
     cfg = oracle.config(ev.geometry, max_cands=6)
     out, ob = oracle.build_beam(cfg, ev.hits, ev.seed_par, ev.seed_cov, ev.seed_hits, n_threads=8)
     tol = TOL["build"]
-    tie = (out["m_cut"] < tol["eps_cut"]) | (out["m_rank"] < tol["eps_rank"]) | (out["m_prop"] < tol["eps_prop"])
+    # every rank counts here, so every near decision does (not only those that
+    # change rank 0)
+    tie = (out["m_cut_raw"] < tol["eps_cut"]) | (out["m_rank_raw"] < tol["eps_rank"]) | (out["m_prop"] < tol["eps_prop"])
     n_checked = n_ranks = 0
     gp, gc, op, oc = [], [], [], []
     for s in np.flatnonzero(~tie):
