@@ -20,7 +20,7 @@
  *  - All host pointers are plain C arrays in the caller's memory, read or
  *    written only during the call unless stated; nothing is retained.
  *  - Every call returns an mkf_status; on error the outputs are untouched and
- *    mkf_last_error() describes the failure.  Argument checks run on the host
+ *    mkf_last_error(ctx) describes the failure.  Argument checks run on the host
  *    before any device work.  No C++ exception crosses this interface.
  *  - One context is used by one host thread at a time, except
  *    mkf_serve_submit / mkf_serve_poll / mkf_serve_cancel, which are
@@ -44,7 +44,7 @@ typedef enum {
     MKF_E_INVALID = -1,   /* bad argument, NaN, count or index out of range */
     MKF_E_NOMEM = -2,     /* device allocation failed or budget too small */
     MKF_E_DEVICE = -3,    /* HIP runtime error */
-    MKF_E_AGAIN = -4,     /* serving queue full: retry later */
+    MKF_E_AGAIN = -4,     /* serving: no in-flight slot or budget free now, retry later */
     MKF_E_NOTFOUND = -5,  /* unknown event handle or ticket */
     MKF_E_STATE = -6      /* call not valid in the current state */
 } mkf_status;
@@ -182,11 +182,14 @@ typedef struct mkf_ctx mkf_ctx;
 /* Library version string, static storage. */
 const char *mkf_version(void);
 
-/* Create a context on the current HIP device.
- * cfg: building parameters (copied).  alloc: may be NULL.  hip_stream: a
- * hipStream_t to run on (NULL = a stream the library creates).  *out
- * receives the context.  Errors: MKF_E_INVALID for an inconsistent config,
- * MKF_E_DEVICE when no gfx950 device is current. */
+/* Create a context on the current HIP device: the detector, field and
+ * building parameters that every later call of the context uses (Section 2:
+ * seeds are propagated outward layer by layer and branch to several
+ * candidates; Section 2.2: the geometry, the uniform field and the hit
+ * resolution).  cfg: building parameters (copied).  alloc: may be NULL.
+ * hip_stream: a hipStream_t to run on (NULL = a stream the library
+ * creates).  *out receives the context.  Errors: MKF_E_INVALID for an
+ * inconsistent config, MKF_E_DEVICE when no gfx950 device is current. */
 mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *hip_stream,
                       mkf_ctx **out);
 
@@ -194,8 +197,11 @@ mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *h
  * for outstanding device work.  NULL is ignored. */
 void mkf_destroy(mkf_ctx *ctx);
 
-/* Message of the last failed call on this thread (static storage). */
-const char *mkf_last_error(void);
+/* Message of the last failed call on this thread (thread-local storage,
+ * valid until the thread's next failing call).  ctx may be NULL: the
+ * message is per thread, so it also covers mkf_create failures, which have
+ * no context yet. */
+const char *mkf_last_error(const mkf_ctx *ctx);
 
 /* 1 when a device error that leaves the GPU's HIP context unusable (a
  * faulting kernel: illegal address, launch failure, ...) was seen on the
@@ -271,6 +277,20 @@ mkf_status mkf_fetch_fit(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
  * MKF_E_STATE (no build of this event kept its beam), MKF_E_DEVICE. */
 mkf_status mkf_fetch_beam(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 
+/* The hit index of one layer of a loaded event, as built on the device for
+ * the current bin grid (Section 3.2.1: the structures that select the hit
+ * candidates of a layer).  bin_off [n_bins + 1]: first position of each bin
+ * in the layer's binned order, bin = i_z * bins_phi + i_phi (i_z over z on a
+ * cylinder, r on a disk), bin_off[n_bins] = the layer's hit count;
+ * bin_of [n_hits of the layer]: the bin of each hit, caller's order;
+ * order [n_hits of the layer]: the caller's index of the hit at each binned
+ * position.  Any pointer may be NULL.  Waits for the stream.  Errors:
+ * MKF_E_INVALID (layer out of range), MKF_E_NOTFOUND, MKF_E_STATE (the
+ * index was built for another grid; the next build rebuilds it),
+ * MKF_E_DEVICE. */
+mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t *bin_off, int32_t *bin_of,
+                           int32_t *order);
+
 /* Work counters of the last build of an event. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out);
 
@@ -306,22 +326,37 @@ mkf_status mkf_sync(mkf_ctx *ctx);
 mkf_status mkf_autotune(mkf_ctx *ctx, const int32_t *handles, int32_t n, mkf_tuning *best);
 
 /* ---- serving (continuous batching) -------------------------------------
- * Events are submitted as they arrive; a scheduler thread admits them while
- * the device-memory budget and the in-flight limit allow, copies and indexes
- * them, and launches batched builds of whatever has been admitted, so new
- * events start while earlier ones are still on the device.  Each event's
- * result does not depend on what it was batched with.  Latency runs from
- * submit until the scheduler observes the event's completion. */
+ * Section 5: on a GPU the total time is dominated by copying the setup data
+ * structures to the device, so events are kept resident there and their
+ * copies overlap the builds of other events.  An event is admitted when it
+ * is submitted - it takes one of max_in_flight slots and reserves its device
+ * footprint (its hits, seeds, outputs and hit index) against the budget -
+ * or the submit returns MKF_E_AGAIN.  A scheduler thread starts whatever has
+ * been admitted on one of four streams, as one batched build (upload, hit
+ * index, build, copy of the tracks back), so events submitted while others
+ * are on the device start as soon as a stream is free.  Each event's result
+ * does not depend on what it was batched with.  The launch shapes are the
+ * context's at mkf_serve_config; a later mkf_set_tuning or mkf_autotune
+ * does not change them for serving.  Latency runs from the entry into
+ * mkf_serve_submit until the scheduler observes the event's completion. */
 
-/* Configure serving: device-memory budget in bytes (reserved at once),
- * events in flight, events per launch (0 = unlimited). */
+/* Configure serving: device-memory budget in bytes (reserved at once, a
+ * slab that admitted events are placed in), events in flight (submitted and
+ * not finished), events per batched build (0 = all that are waiting).  Also
+ * allocates, outside the budget, the batch descriptors of each stream.
+ * Errors: MKF_E_INVALID, MKF_E_NOMEM (the budget cannot be reserved),
+ * MKF_E_STATE (tickets of a previous configuration still in flight),
+ * MKF_E_DEVICE. */
 mkf_status mkf_serve_config(mkf_ctx *ctx, uint64_t hbm_budget_bytes, int32_t max_in_flight,
                             int32_t max_batch_events);
 
-/* Submit an event: validated and copied into host staging before return
- * (the event arrays may be freed); `out` must stay valid until the ticket is
- * done.  MKF_E_AGAIN when the submission queue is full, MKF_E_NOMEM when the
- * event can never fit the budget, MKF_E_STATE before mkf_serve_config. */
+/* Submit an event: validated and copied into pinned host staging before
+ * return (the event arrays may be freed); `out` must stay valid until the
+ * ticket is done.  MKF_E_AGAIN when all in-flight slots are taken or the
+ * budget held by the events in flight leaves no room for this one (retry
+ * once a ticket has finished), MKF_E_NOMEM when the event can never fit the
+ * budget, MKF_E_STATE before mkf_serve_config, MKF_E_INVALID for a bad
+ * event. */
 mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, uint64_t *ticket);
 
 /* Poll a ticket: *done = 1 once finished; *ticket_status is its mkf_status;
@@ -330,7 +365,8 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
 mkf_status mkf_serve_poll(mkf_ctx *ctx, uint64_t ticket, int32_t *done, int32_t *ticket_status,
                           double *latency_s);
 
-/* Cancel a ticket not yet admitted (MKF_E_STATE once running). */
+/* Cancel a ticket that has not started (MKF_E_STATE once started); its slot
+ * and budget are released. */
 mkf_status mkf_serve_cancel(mkf_ctx *ctx, uint64_t ticket);
 
 /* Block until every submitted ticket has finished. */

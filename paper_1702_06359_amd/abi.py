@@ -102,7 +102,7 @@ _PROTOS = {
     "mkf_version": (C.c_char_p, []),
     "mkf_create": (C.c_int, [_P(Config), _P(Allocator), C.c_void_p, _P(C.c_void_p)]),
     "mkf_destroy": (None, [_ctx_p]),
-    "mkf_last_error": (C.c_char_p, []),
+    "mkf_last_error": (C.c_char_p, [_ctx_p]),
     "mkf_set_tuning": (C.c_int, [_ctx_p, _P(Tuning)]),
     "mkf_get_tuning": (C.c_int, [_ctx_p, _P(Tuning)]),
     "mkf_load_event": (C.c_int, [_ctx_p, _P(Event), _P(C.c_int32)]),
@@ -114,6 +114,7 @@ _PROTOS = {
     "mkf_fetch_beam": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_ctx_broken": (C.c_int32, [_ctx_p]),
     "mkf_get_stats": (C.c_int, [_ctx_p, C.c_int32, _P(BuildStats)]),
+    "mkf_fetch_index": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
     "mkf_fit": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_double), _P(C.c_double), _P(C.c_int32),
                           _P(Tracks)]),
     "mkf_fit_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, _P(Tracks)]),
@@ -167,7 +168,8 @@ def lib():
 
 
 def last_error() -> str:
-    return lib().mkf_last_error().decode()
+    """Message of this thread's last failed call (the library keeps one per thread)."""
+    return lib().mkf_last_error(None).decode()
 
 
 def check(status: int):
@@ -409,6 +411,15 @@ class Context:
         check(lib().mkf_fetch_beam(self.h, int(handle), C.byref(out.tracks)))
         return {name: v.reshape((n_seeds, k) + v.shape[1:]) for name, v in out.as_dict().items()}
 
+    def fetch_index(self, handle: int, layer: int, n_hits: int):
+        """(bin_off, bin_of, order) of one layer's device hit index."""
+        t = self.get_tuning()
+        off = np.zeros(t.bins_phi * t.bins_z + 1, dtype=np.int32)
+        bin_of = np.zeros(n_hits, dtype=np.int32)
+        order = np.zeros(n_hits, dtype=np.int32)
+        check(lib().mkf_fetch_index(self.h, int(handle), int(layer), _ip(off), _ip(bin_of), _ip(order)))
+        return off, bin_of, order
+
     def get_stats(self, handle: int) -> Dict[str, int]:
         s = BuildStats()
         check(lib().mkf_get_stats(self.h, int(handle), C.byref(s)))
@@ -453,7 +464,8 @@ class Context:
         check(lib().mkf_serve_config(self.h, int(hbm_budget_bytes), int(max_in_flight), int(max_batch_events)))
 
     def serve_submit(self, ev, ea: Optional[EventArrays] = None):
-        """Returns (ticket, TrackArrays) or (None, None) when the queue is full."""
+        """Returns (ticket, TrackArrays), or (None, None) when no in-flight slot
+        or budget is free (MKF_E_AGAIN: submit again later)."""
         ea = ea or (ev if isinstance(ev, EventArrays) else EventArrays.from_synth(ev))
         out = TrackArrays(int(ea.event.n_seeds), self.n_layers)
         t = C.c_uint64()

@@ -607,7 +607,11 @@ mkf_status ensure_beam(mkf_ctx *ctx, EventRec *rec)
 // set when the tables were (re)allocated and the index must be built.
 mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s)
 {
-    const int bp = ctx->tuning.bins_phi, bz = ctx->tuning.bins_z;
+    return ensure_index_grid(ctx, rec, ctx->tuning.bins_phi, ctx->tuning.bins_z, rebuilt, s);
+}
+
+mkf_status ensure_index_grid(mkf_ctx *ctx, EventRec *rec, int bp, int bz, bool *rebuilt, hipStream_t s)
+{
     *rebuilt = false;
     if (rec->index && rec->index_bins_phi == bp && rec->index_bins_z == bz) return MKF_OK;
     if (rec->index) MKF_HIP(hipStreamSynchronize(ctx->stream));   // queued builds may still read it
@@ -628,10 +632,12 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t 
     return MKF_OK;
 }
 
-mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
-                       BatchArgs *args, hipStream_t s, bool beam)
+// Lays out the batch descriptors of recs[0..n) - the event views, the work,
+// hit, track and seed prefixes and the work-queue counter - into `image`
+// (batch_scratch_bytes(n) bytes, all written) and points `args` at the same
+// layout starting at device address `dev`.  Allocates nothing.
+mkf_status compose_batch(EventRec *const *recs, int n, int spi, bool beam, char *image, char *dev, BatchArgs *args)
 {
-    const int n = (int)recs.size();
     size_t off = 0;
     auto place = [&](size_t bytes) {
         const size_t o = off;
@@ -644,8 +650,8 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     const size_t o_trk = place((size_t)(n + 1) * sizeof(int));
     const size_t o_seed = place((size_t)(n + 1) * sizeof(int));
     const size_t o_q = place(sizeof(unsigned));
-    std::vector<char> image(off, 0);
-    char *h = image.data();
+    std::memset(image, 0, off);
+    char *h = image;
     DevEvent *ev = reinterpret_cast<DevEvent *>(h + o_ev);
     int *ip = reinterpret_cast<int *>(h + o_item);
     int *hp = reinterpret_cast<int *>(h + o_hit);
@@ -682,31 +688,12 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     hp[n] = (int)hits;
     tp[n] = (int)trks;
     sp[n] = (int)seeds;
-    *reinterpret_cast<unsigned *>(h + o_q) = 0;
-    // The context's own buffer keeps the last image: an identical batch (same
-    // events, views and tuning) is not copied again.  Its pinned staging
-    // buffer is rewritten only once the previous copy out of it has run.
-    const bool own = dev == ctx->batch_dev;
-    if (!own || image != ctx->staged_image) {
-        if (host == ctx->batch_host && ctx->stage_pending) {
-            MKF_HIP(hipEventSynchronize(ctx->stage_done));
-            ctx->stage_pending = false;
-        }
-        std::memcpy(host, image.data(), off);
-        MKF_HIP(hipMemcpyAsync(dev, host, off, hipMemcpyHostToDevice, s));
-        if (host == ctx->batch_host) {
-            MKF_HIP(hipEventRecord(ctx->stage_done, s));
-            ctx->stage_pending = true;
-        }
-        if (own) ctx->staged_image.swap(image);
-    }
-    char *d = static_cast<char *>(dev);
-    args->events = reinterpret_cast<const DevEvent *>(d + o_ev);
-    args->item_prefix = reinterpret_cast<const int *>(d + o_item);
-    args->hit_prefix = reinterpret_cast<const int *>(d + o_hit);
-    args->track_prefix = reinterpret_cast<const int *>(d + o_trk);
-    args->seed_prefix = reinterpret_cast<const int *>(d + o_seed);
-    args->queue = reinterpret_cast<unsigned *>(d + o_q);
+    args->events = reinterpret_cast<const DevEvent *>(dev + o_ev);
+    args->item_prefix = reinterpret_cast<const int *>(dev + o_item);
+    args->hit_prefix = reinterpret_cast<const int *>(dev + o_hit);
+    args->track_prefix = reinterpret_cast<const int *>(dev + o_trk);
+    args->seed_prefix = reinterpret_cast<const int *>(dev + o_seed);
+    args->queue = reinterpret_cast<unsigned *>(dev + o_q);
     args->n_events = n;
     args->total_items = (int)items;
     args->total_hits = (int)hits;
@@ -717,13 +704,45 @@ mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *
     return MKF_OK;
 }
 
+mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
+                       BatchArgs *args, hipStream_t s, bool beam)
+{
+    const int n = (int)recs.size();
+    std::vector<char> image(batch_scratch_bytes(n));
+    mkf_status st = compose_batch(recs.data(), n, spi, beam, image.data(), static_cast<char *>(dev), args);
+    if (st != MKF_OK) return st;
+    // The context's own buffer keeps the last image: an identical batch (same
+    // events, views and tuning) is not copied again.  Its pinned staging
+    // buffer is rewritten only once the previous copy out of it has run.
+    const bool own = dev == ctx->batch_dev;
+    if (!own || image != ctx->staged_image) {
+        if (host == ctx->batch_host && ctx->stage_pending) {
+            MKF_HIP(hipEventSynchronize(ctx->stage_done));
+            ctx->stage_pending = false;
+        }
+        std::memcpy(host, image.data(), image.size());
+        MKF_HIP(hipMemcpyAsync(dev, host, image.size(), hipMemcpyHostToDevice, s));
+        if (host == ctx->batch_host) {
+            MKF_HIP(hipEventRecord(ctx->stage_done, s));
+            ctx->stage_pending = true;
+        }
+        if (own) ctx->staged_image.swap(image);
+    }
+    return MKF_OK;
+}
+
 // The batched pipeline on stream s: optional counter reset and re-index,
 // then the build kernel.
 mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<EventRec *> &recs, uint32_t flags,
                         bool timed, hipStream_t s)
 {
     (void)recs;
-    const Params &P = ctx->params;
+    return run_pipeline_with(ctx, ctx->params, ctx->tuning, args, flags, timed, s);
+}
+
+mkf_status run_pipeline_with(mkf_ctx *ctx, const Params &P, const mkf_tuning &t, const BatchArgs &args,
+                             uint32_t flags, bool timed, hipStream_t s)
+{
     const bool stats = flags & MKF_BATCH_STATS, reindex = flags & MKF_BATCH_REINDEX;
     // bin counts are left at zero by every index build; fresh tables are
     // cleared when they are allocated
@@ -733,7 +752,6 @@ mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<E
         MKF_HIP(launch_index(P, args, s));
         if (timed) timer_end(ctx, 1, s, 1);   // one index build of the batch
     }
-    const mkf_tuning &t = ctx->tuning;
     if (t.persistent) MKF_HIP(launch_fill_i32(reinterpret_cast<int *>(args.queue), 0, 1, s));
     if (timed) timer_begin(ctx, 0, s);
     MKF_HIP(launch_build_batch(P, args, t.lanes_per_seed, t.waves_per_block, t.persistent,
@@ -797,7 +815,11 @@ extern "C" {
 
 const char *mkf_version(void) { return "mkf 0.1 (gfx950, FP32 Kalman filter)"; }
 
-const char *mkf_last_error(void) { return g_err; }
+const char *mkf_last_error(const mkf_ctx *ctx)
+{
+    (void)ctx;   // the message is per thread
+    return g_err;
+}
 
 int32_t mkf_ctx_broken(const mkf_ctx *ctx) { return ctx && device_broken(ctx->device) ? 1 : 0; }
 
@@ -1165,6 +1187,38 @@ mkf_status mkf_fetch_beam(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
     MKF_HIP(hipStreamSynchronize(ctx->stream));
     if (out->ndof)
         for (size_t i = 0; i < n; ++i) out->ndof[i] = out->status && out->status[i] < 0 ? 0 : 2 * out->ndof[i] - 5;
+    return MKF_OK;
+}
+
+mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t *bin_off, int32_t *bin_of,
+                           int32_t *order)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    if (layer < 0 || layer >= rec->shape.n_layers) return fail(MKF_E_INVALID, "layer %d out of range", layer);
+    if (!rec->index || rec->index_bins_phi != ctx->tuning.bins_phi || rec->index_bins_z != ctx->tuning.bins_z)
+        return fail(MKF_E_STATE, "the index was built for another bin grid");
+    const int nb = ctx->tuning.bins_phi * ctx->tuning.bins_z;
+    const int h0 = rec->shape.layer_off[layer], n = rec->shape.layer_off[layer + 1] - h0;
+    const DevEvent &v = rec->view;
+    std::vector<int32_t> off(bin_off ? nb + 1 : 0);
+    std::vector<float4> binned(order ? n : 0);
+    hipStream_t s = ctx->stream;
+    if (bin_off) MKF_HIP(hipMemcpyAsync(off.data(), v.bin_off + (size_t)layer * (nb + 1), 4 * (size_t)(nb + 1),
+                                        hipMemcpyDeviceToHost, s));
+    if (bin_of && n) MKF_HIP(hipMemcpyAsync(bin_of, v.bin_of + h0, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
+    if (order && n) MKF_HIP(hipMemcpyAsync(binned.data(), v.binned + h0, sizeof(float4) * (size_t)n,
+                                           hipMemcpyDeviceToHost, s));
+    MKF_HIP(hipStreamSynchronize(s));
+    if (bin_off)
+        for (int i = 0; i <= nb; ++i) bin_off[i] = off[i] - h0;
+    if (order)
+        for (int i = 0; i < n; ++i) {
+            int32_t id;
+            std::memcpy(&id, &binned[i].w, 4);
+            order[i] = id;
+        }
     return MKF_OK;
 }
 

@@ -161,6 +161,8 @@ mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap,
 mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s);
 void destroy_event(mkf_ctx *ctx, EventRec *rec);
 mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s);
+mkf_status ensure_index_grid(mkf_ctx *ctx, EventRec *rec, int bins_phi, int bins_z, bool *rebuilt, hipStream_t s);
+mkf_status compose_batch(EventRec *const *recs, int n, int spi, bool beam, char *image, char *dev, BatchArgs *args);
 mkf_status stage_batch(mkf_ctx *ctx, const std::vector<EventRec *> &recs, void *dev, void *host, int spi,
                        BatchArgs *args, hipStream_t s, bool beam = false);
 mkf_status ensure_beam(mkf_ctx *ctx, EventRec *rec);
@@ -169,6 +171,9 @@ int resolve_lanes(const mkf_ctx *ctx);
 int seeds_per_item(int G);
 mkf_status run_pipeline(mkf_ctx *ctx, const BatchArgs &args, const std::vector<EventRec *> &recs, uint32_t flags,
                         bool timed, hipStream_t s);
+// the same with explicit parameters and launch shapes (serving keeps its own)
+mkf_status run_pipeline_with(mkf_ctx *ctx, const Params &P, const mkf_tuning &t, const BatchArgs &args,
+                             uint32_t flags, bool timed, hipStream_t s);
 mkf_status copy_tracks_out(mkf_ctx *ctx, const EventRec *rec, const mkf_tracks *out, hipStream_t s);
 void shutdown_server(mkf_ctx *ctx);
 

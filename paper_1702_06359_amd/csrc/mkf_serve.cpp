@@ -1,15 +1,20 @@
 // Serving: continuous batching of events as they arrive.
 //
-// Submit copies an event into pinned host staging and queues a ticket.  A
-// scheduler thread admits queued tickets in arrival order while the device
-// budget (a slab reserved once, sub-allocated first-fit) and the in-flight
-// limit allow, uploads them, builds their hit indices and runs one batched
-// build for everything admitted together, on one of several streams, so that
-// batches admitted later overlap the ones still on the device.  Results come
-// back through pinned staging; the scheduler marks a ticket done when it
-// observes its batch's completion event.
+// An event is admitted when it is submitted: it takes one of the in-flight
+// slots and reserves its device footprint against the budget (a slab
+// reserved once, sub-allocated first-fit), or the submit returns
+// MKF_E_AGAIN.  Its arrays are copied into pinned host staging.  A scheduler
+// thread gives each free stream whatever has been admitted and not yet
+// started: it uploads those events, builds their hit indices and runs one
+// batched build for all of them, so events submitted later start while
+// earlier ones are still on the device.  Results come back through pinned
+// staging; the scheduler marks a ticket done when it observes its batch's
+// completion event.  The launch shapes and parameters are the context's at
+// mkf_serve_config, kept by the server, so later tuning changes of the
+// context do not reach events in flight.
 #include "mkf_runtime.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -19,6 +24,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr int kStreams = 4;
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Reuses pinned host buffers by power-of-two size class.
 class PinnedPool {
@@ -66,9 +73,9 @@ struct Ticket {
     size_t in_cls = 0;
     void *out_pin = nullptr;
     size_t out_cls = 0;
-    size_t dev_bytes = 0;
+    size_t reserved = 0;          // budget bytes held from submit to completion
     Clock::time_point t_submit, t_done;
-    int state = 0;    // 0 queued, 1 running, 2 done
+    int state = 0;                // 0 admitted, 1 running, 2 done
     mkf_status status = MKF_OK;
     std::unique_ptr<EventRec> rec;
 };
@@ -84,7 +91,7 @@ InLayout in_layout(const EventShape &s)
     size_t off = 0;
     auto take = [&](size_t b) {
         const size_t o = off;
-        off = (off + b + 255) & ~size_t(255);
+        off = round256(off + b);
         return o;
     };
     l.hits = take(24 * (size_t)s.n_hits());
@@ -106,7 +113,7 @@ OutLayout out_layout(const EventShape &s)
     const size_t n = (size_t)s.n_seeds;
     auto take = [&](size_t b) {
         const size_t o = off;
-        off = (off + b + 255) & ~size_t(255);
+        off = round256(off + b);
         return o;
     };
     l.par = take(48 * n);
@@ -124,35 +131,66 @@ struct Running {
     std::vector<Ticket *> tickets;
     int stream = 0;
     hipEvent_t done = nullptr;
-    void *scratch_dev = nullptr;
-    void *scratch_host = nullptr;
-    size_t scratch_cls = 0;
 };
 
 }  // namespace
 
 struct Server {
     mkf_ctx *ctx = nullptr;
+    Params params{};              // the context's parameters and launch shapes at configuration
+    mkf_tuning tuning{};
     void *slab_base = nullptr;
     std::unique_ptr<SlabHeap> slab;
     int max_in_flight = 0;
     int max_batch = 0;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Ticket *> pending;
+    std::deque<Ticket *> admitted;   // submitted, not yet started
     std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
     std::vector<Running> running;
-    int in_flight = 0;
+    int in_flight = 0;               // submitted and not finished
+    size_t reserved = 0;             // budget promised to those tickets
     bool stop = false;
     uint64_t next_id = 1;
     hipStream_t streams[kStreams] = {};
     bool stream_busy[kStreams] = {};
+    // per-stream batch descriptors (device and pinned host), sized for the
+    // largest batch at configuration, outside the event budget
+    void *scratch_dev[kStreams] = {};
+    void *scratch_host[kStreams] = {};
     PinnedPool pinned;
     std::thread thr;
 
+    // device bytes of one event: its data and its hit index, as the slab
+    // rounds them
     size_t footprint(const EventShape &s) const
     {
-        return event_data_bytes(s) + event_index_bytes(s, ctx->tuning.bins_phi * ctx->tuning.bins_z) + 4096;
+        return round256(event_data_bytes(s)) + round256(event_index_bytes(s, tuning.bins_phi * tuning.bins_z));
+    }
+
+    void release_ticket_resources(Ticket *t)
+    {
+        if (t->rec) destroy_event(ctx, t->rec.get());
+        t->rec.reset();
+        pinned.put(t->in_pin, t->in_cls);
+        pinned.put(t->out_pin, t->out_cls);
+        t->in_pin = t->out_pin = nullptr;
+    }
+
+    // marks tickets done (under the lock) and frees their slots and budget
+    void complete(const std::vector<Ticket *> &ts, mkf_status st)
+    {
+        const auto now = Clock::now();
+        std::lock_guard<std::mutex> lk(mu);
+        for (Ticket *t : ts) {
+            t->status = st;
+            t->t_done = now;
+            t->state = 2;
+            reserved -= t->reserved;
+            t->reserved = 0;
+        }
+        in_flight -= (int)ts.size();
+        cv.notify_all();
     }
 
     void finish_batch(Running &b)
@@ -172,47 +210,22 @@ struct Server {
                 const int *nh = reinterpret_cast<const int *>(o + ol.nhits);
                 for (size_t i = 0; i < n; ++i) t->out.ndof[i] = 2 * nh[i] - 5;
             }
-            destroy_event(ctx, t->rec.get());
-            t->rec.reset();
-            pinned.put(t->in_pin, t->in_cls);
-            pinned.put(t->out_pin, t->out_cls);
-            t->in_pin = t->out_pin = nullptr;
+            release_ticket_resources(t);
         }
-        slab->release(b.scratch_dev);
-        pinned.put(b.scratch_host, b.scratch_cls);
         (void)hipEventDestroy(b.done);
         stream_busy[b.stream] = false;
-        const auto now = Clock::now();
-        std::lock_guard<std::mutex> lk(mu);
-        for (Ticket *t : b.tickets) {
-            t->t_done = now;
-            t->state = 2;
-        }
-        in_flight -= (int)b.tickets.size();
-        cv.notify_all();
+        complete(b.tickets, MKF_OK);
     }
 
-    void fail_batch(std::vector<Ticket *> &batch, mkf_status st)
+    void fail_batch(const std::vector<Ticket *> &batch, int si, mkf_status st)
     {
-        const auto now = Clock::now();
-        for (Ticket *t : batch) {
-            if (t->rec) destroy_event(ctx, t->rec.get());
-            t->rec.reset();
-            pinned.put(t->in_pin, t->in_cls);
-            pinned.put(t->out_pin, t->out_cls);
-            t->in_pin = t->out_pin = nullptr;
-        }
-        std::lock_guard<std::mutex> lk(mu);
-        for (Ticket *t : batch) {
-            t->status = st;
-            t->t_done = now;
-            t->state = 2;
-        }
-        in_flight -= (int)batch.size();
-        cv.notify_all();
+        (void)hipStreamSynchronize(streams[si]);   // nothing queued may still use the buffers
+        for (Ticket *t : batch) release_ticket_resources(t);
+        stream_busy[si] = false;
+        complete(batch, st);
     }
 
-    // Upload, index and build one admitted batch on stream si.
+    // Upload, index and build one batch on stream si.
     mkf_status launch(std::vector<Ticket *> &batch, int si, Running *run)
     {
         hipStream_t s = streams[si];
@@ -235,16 +248,11 @@ struct Server {
             }
             recs.push_back(t->rec.get());
         }
-        const size_t sb = batch_scratch_bytes((int)batch.size());
-        run->scratch_dev = slab->alloc(sb);
-        if (!run->scratch_dev) return fail(MKF_E_NOMEM, "batch scratch");
-        run->scratch_host = pinned.get(sb, &run->scratch_cls);
-        if (!run->scratch_host) return fail(MKF_E_NOMEM, "pinned batch scratch");
         BatchArgs args{};
-        mkf_status st = stage_batch(ctx, recs, run->scratch_dev, run->scratch_host,
-                                    seeds_per_item(ctx->tuning.lanes_per_seed), &args, s);
+        mkf_status st = stage_batch(ctx, recs, scratch_dev[si], scratch_host[si],
+                                    seeds_per_item(tuning.lanes_per_seed), &args, s);
         if (st != MKF_OK) return st;
-        if ((st = run_pipeline(ctx, args, recs, MKF_BATCH_REINDEX, false, s)) != MKF_OK) return st;
+        if ((st = run_pipeline_with(ctx, params, tuning, args, MKF_BATCH_REINDEX, false, s)) != MKF_OK) return st;
         for (Ticket *t : batch) {
             const OutLayout ol = out_layout(t->shape);
             char *o = static_cast<char *>(t->out_pin);
@@ -271,17 +279,25 @@ struct Server {
         (void)hipSetDevice(ctx->device);
         for (;;) {
             bool progress = false;
-            // completions
+            // completions; an error other than "not ready" fails the batch
             for (size_t i = 0; i < running.size();) {
-                if (hipEventQuery(running[i].done) == hipSuccess) {
-                    finish_batch(running[i]);
-                    running.erase(running.begin() + i);
-                    progress = true;
-                } else {
+                const hipError_t q = hipEventQuery(running[i].done);
+                if (q == hipErrorNotReady) {
                     ++i;
+                    continue;
                 }
+                if (q == hipSuccess) {
+                    finish_batch(running[i]);
+                } else {
+                    note_device_error(q);
+                    (void)hipEventDestroy(running[i].done);
+                    fail_batch(running[i].tickets, running[i].stream, MKF_E_DEVICE);
+                }
+                running.erase(running.begin() + i);
+                progress = true;
             }
-            // admission, in arrival order, while memory, slots and a stream are free
+            // start whatever is admitted on a free stream, in submission order,
+            // while the slab can place the events
             int si = -1;
             for (int k = 0; k < kStreams; ++k)
                 if (!stream_busy[k]) {
@@ -291,22 +307,21 @@ struct Server {
             std::vector<Ticket *> batch;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                if (stop && pending.empty() && running.empty()) return;
-                while (si >= 0 && !pending.empty() && in_flight < max_in_flight &&
-                       (max_batch == 0 || (int)batch.size() < max_batch)) {
-                    Ticket *t = pending.front();
+                if (stop && admitted.empty() && running.empty()) return;
+                while (si >= 0 && !admitted.empty() && (max_batch == 0 || (int)batch.size() < max_batch)) {
+                    Ticket *t = admitted.front();
                     std::unique_ptr<EventRec> rec;
-                    if (create_event(ctx, t->shape, slab.get(), &rec) != MKF_OK) break;
+                    if (create_event(ctx, t->shape, slab.get(), &rec) != MKF_OK) break;   // wait for memory
                     bool rebuilt = false;
-                    if (ensure_index(ctx, rec.get(), &rebuilt, streams[si]) != MKF_OK) {
+                    if (ensure_index_grid(ctx, rec.get(), tuning.bins_phi, tuning.bins_z, &rebuilt, streams[si]) !=
+                        MKF_OK) {
                         destroy_event(ctx, rec.get());
                         break;
                     }
                     t->rec = std::move(rec);
                     t->state = 1;
-                    pending.pop_front();
+                    admitted.pop_front();
                     batch.push_back(t);
-                    ++in_flight;
                 }
                 if (batch.empty() && !progress) {
                     cv.wait_for(lk, std::chrono::microseconds(50));
@@ -314,16 +329,13 @@ struct Server {
                 }
             }
             if (!batch.empty()) {
+                stream_busy[si] = true;
                 Running run;
-                mkf_status st = launch(batch, si, &run);
+                const mkf_status st = launch(batch, si, &run);
                 if (st != MKF_OK) {
-                    (void)hipStreamSynchronize(streams[si]);
-                    slab->release(run.scratch_dev);
-                    pinned.put(run.scratch_host, run.scratch_cls);
                     if (run.done) (void)hipEventDestroy(run.done);
-                    fail_batch(batch, st);
+                    fail_batch(batch, si, st);
                 } else {
-                    stream_busy[si] = true;
                     running.push_back(run);
                 }
             }
@@ -340,13 +352,13 @@ void shutdown_server(mkf_ctx *ctx)
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
-        // queued tickets are abandoned
-        for (Ticket *t : sv->pending) {
+        // tickets not started are abandoned
+        for (Ticket *t : sv->admitted) {
             sv->pinned.put(t->in_pin, t->in_cls);
             sv->pinned.put(t->out_pin, t->out_cls);
             t->in_pin = t->out_pin = nullptr;
         }
-        sv->pending.clear();
+        sv->admitted.clear();
         sv->cv.notify_all();
     }
     if (sv->thr.joinable()) sv->thr.join();
@@ -355,6 +367,10 @@ void shutdown_server(mkf_ctx *ctx)
             (void)hipStreamSynchronize(s);
             (void)hipStreamDestroy(s);
         }
+    for (int k = 0; k < kStreams; ++k) {
+        ctx->heap.release(sv->scratch_dev[k]);
+        if (sv->scratch_host[k]) (void)hipHostFree(sv->scratch_host[k]);
+    }
     sv->tickets.clear();
     sv->slab.reset();
     ctx->heap.release(sv->slab_base);
@@ -374,22 +390,39 @@ mkf_status mkf_serve_config(mkf_ctx *ctx, uint64_t hbm_budget_bytes, int32_t max
         return fail(MKF_E_INVALID, "budget >= 1 MiB, max_in_flight >= 1, max_batch_events >= 0");
     if (ctx->server) {
         std::lock_guard<std::mutex> lk(ctx->server->mu);
-        if (!ctx->server->pending.empty() || ctx->server->in_flight > 0)
+        if (!ctx->server->admitted.empty() || ctx->server->in_flight > 0)
             return fail(MKF_E_STATE, "serving has tickets in flight");
     }
     shutdown_server(ctx);
     std::unique_ptr<Server, ServerDeleter> sv(new Server());
     sv->ctx = ctx;
+    sv->params = ctx->params;
+    sv->tuning = ctx->tuning;
+    sv->max_in_flight = max_in_flight;
+    sv->max_batch = max_batch_events;
+    auto undo = [&](mkf_status st) {
+        for (int k = 0; k < kStreams; ++k) {
+            if (sv->streams[k]) (void)hipStreamDestroy(sv->streams[k]);
+            ctx->heap.release(sv->scratch_dev[k]);
+            if (sv->scratch_host[k]) (void)hipHostFree(sv->scratch_host[k]);
+        }
+        ctx->heap.release(sv->slab_base);
+        return st;
+    };
     sv->slab_base = ctx->heap.alloc(hbm_budget_bytes);
     if (!sv->slab_base) return fail(MKF_E_NOMEM, "cannot reserve %llu bytes", (unsigned long long)hbm_budget_bytes);
     sv->slab = std::make_unique<SlabHeap>(static_cast<char *>(sv->slab_base), hbm_budget_bytes);
-    sv->max_in_flight = max_in_flight;
-    sv->max_batch = max_batch_events;
-    for (auto &s : sv->streams) {
-        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    const int largest = max_batch_events > 0 ? std::min(max_batch_events, max_in_flight) : max_in_flight;
+    const size_t sb = batch_scratch_bytes(largest);
+    for (int k = 0; k < kStreams; ++k) {
+        hipError_t e = hipStreamCreateWithFlags(&sv->streams[k], hipStreamNonBlocking);
+        if (e != hipSuccess) return undo(fail(MKF_E_DEVICE, "stream: %s", hipGetErrorString(e)));
+        sv->scratch_dev[k] = ctx->heap.alloc(sb);
+        if (!sv->scratch_dev[k]) return undo(fail(MKF_E_NOMEM, "batch descriptors: %zu bytes", sb));
+        e = hipHostMalloc(&sv->scratch_host[k], sb, hipHostMallocDefault);
         if (e != hipSuccess) {
-            ctx->heap.release(sv->slab_base);
-            return fail(MKF_E_DEVICE, "stream: %s", hipGetErrorString(e));
+            sv->scratch_host[k] = nullptr;
+            return undo(fail(MKF_E_NOMEM, "pinned batch descriptors: %s", hipGetErrorString(e)));
         }
     }
     ctx->server = std::move(sv);
@@ -400,6 +433,7 @@ mkf_status mkf_serve_config(mkf_ctx *ctx, uint64_t hbm_budget_bytes, int32_t max
 
 mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, uint64_t *ticket)
 {
+    const auto t_entry = Clock::now();
     if (!ctx || !out || !ticket) return fail(MKF_E_INVALID, "NULL argument");
     Server *sv = ctx->server.get();
     if (!sv) return fail(MKF_E_STATE, "serving is not configured");
@@ -408,15 +442,29 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
     if (st != MKF_OK) return st;
     if (out->n != shape.n_seeds) return fail(MKF_E_INVALID, "output has %d rows, need %d", out->n, shape.n_seeds);
     shape.n_tracks = 0;   // serving builds; tracks for fitting are not staged
-    const size_t need = sv->footprint(shape) + batch_scratch_bytes(1);
+    const size_t need = sv->footprint(shape);
     if (need > sv->slab->capacity()) return fail(MKF_E_NOMEM, "event needs %zu bytes, budget %zu", need, sv->slab->capacity());
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->pending.size() >= 65536) return fail(MKF_E_AGAIN, "submission queue full");
-    }
     auto t = std::make_unique<Ticket>();
+    t->t_submit = t_entry;
     t->shape = shape;
     t->out = *out;
+    t->reserved = need;
+    {   // admission: a free in-flight slot and room in the budget
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) return fail(MKF_E_STATE, "serving is shutting down");
+        if (sv->in_flight >= sv->max_in_flight) return fail(MKF_E_AGAIN, "all %d in-flight slots are taken", sv->max_in_flight);
+        if (sv->reserved + need > sv->slab->capacity())
+            return fail(MKF_E_AGAIN, "budget: %zu of %zu bytes held, event needs %zu", sv->reserved,
+                        sv->slab->capacity(), need);
+        ++sv->in_flight;
+        sv->reserved += need;
+    }
+    auto unreserve = [&]() {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        --sv->in_flight;
+        sv->reserved -= need;
+        sv->cv.notify_all();
+    };
     const InLayout il = in_layout(shape);
     const OutLayout ol = out_layout(shape);
     t->in_pin = sv->pinned.get(il.total, &t->in_cls);
@@ -424,6 +472,7 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
     if (!t->in_pin || !t->out_pin) {
         sv->pinned.put(t->in_pin, t->in_cls);
         sv->pinned.put(t->out_pin, t->out_cls);
+        unreserve();
         return fail(MKF_E_NOMEM, "pinned staging");
     }
     char *in = static_cast<char *>(t->in_pin);
@@ -435,11 +484,10 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
         std::memcpy(in + il.seed_cov, ev->seed_cov, 168 * ns);
         std::memcpy(in + il.seed_hits, ev->seed_hits, 4 * (size_t)shape.n_seed_layers * ns);
     }
-    t->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
     t->id = sv->next_id++;
     *ticket = t->id;
-    sv->pending.push_back(t.get());
+    sv->admitted.push_back(t.get());
     sv->tickets[t->id] = std::move(t);
     sv->cv.notify_all();
     return MKF_OK;
@@ -472,11 +520,14 @@ mkf_status mkf_serve_cancel(mkf_ctx *ctx, uint64_t ticket)
     auto it = sv->tickets.find(ticket);
     if (it == sv->tickets.end()) return fail(MKF_E_NOTFOUND, "unknown ticket");
     Ticket *t = it->second.get();
-    if (t->state != 0) return fail(MKF_E_STATE, "ticket already admitted");
-    sv->pending.erase(std::find(sv->pending.begin(), sv->pending.end(), t));
+    if (t->state != 0) return fail(MKF_E_STATE, "ticket already started");
+    sv->admitted.erase(std::find(sv->admitted.begin(), sv->admitted.end(), t));
     sv->pinned.put(t->in_pin, t->in_cls);
     sv->pinned.put(t->out_pin, t->out_cls);
+    --sv->in_flight;
+    sv->reserved -= t->reserved;
     sv->tickets.erase(it);
+    sv->cv.notify_all();
     return MKF_OK;
 }
 
@@ -486,7 +537,7 @@ mkf_status mkf_serve_drain(mkf_ctx *ctx)
     Server *sv = ctx->server.get();
     if (!sv) return fail(MKF_E_STATE, "serving is not configured");
     std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv.wait(lk, [sv] { return sv->pending.empty() && sv->in_flight == 0; });
+    sv->cv.wait(lk, [sv] { return sv->admitted.empty() && sv->in_flight == 0; });
     return MKF_OK;
 }
 

@@ -1,0 +1,87 @@
+"""The device hit index, checked as integer work (Section 3.2.1: the
+structures that select the hit candidates of a layer).
+
+For every layer: the bin the device gave each hit equals the bin computed on
+the host from the caller's FP64 coordinates, except for hits within a
+rounding error of a bin edge (there either side is correct; such hits are
+counted and must be rare); the bin offsets equal a host counting sort of the
+device's bin ids, bit for bit; and each bin of the binned order holds
+exactly the hits with that bin id (compared as sets: the order inside a bin
+is free)."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import report
+from paper_1702_06359_amd import abi, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def host_bins(hits, L, geometry, bins_phi, bins_z):
+    """Bin of each hit from its FP64 coordinates, and its distance to the
+    nearest bin edge in units of a bin (in phi or in the second coordinate)."""
+    x, y, z = hits[:, 0], hits[:, 1], hits[:, 2]
+    phi = np.arctan2(y, x)
+    fp = (phi + math.pi) * bins_phi / (2 * math.pi)
+    if geometry.is_disk:
+        g2, lo, ext = np.hypot(x, y), geometry.disk_rmin, geometry.radii[L] - geometry.disk_rmin
+    else:
+        hz = geometry.half_z()[L]
+        g2, lo, ext = z, -hz, 2 * hz
+    fz = (g2 - lo) * bins_z / ext
+    ip = np.clip(np.floor(fp), 0, bins_phi - 1).astype(np.int64)
+    iz = np.clip(np.floor(fz), 0, bins_z - 1).astype(np.int64)
+    edge = np.minimum(np.abs(fp - np.round(fp)), np.where((fz > 0) & (fz < bins_z), np.abs(fz - np.round(fz)), 1.0))
+    return (iz * bins_phi + ip).astype(np.int32), edge
+
+
+def check_layer(off, bin_of, order, ref_bins, edge):
+    n = len(bin_of)
+    nb = len(off) - 1
+    # offsets: exactly the counting sort of the device's bin ids
+    want = np.zeros(nb + 1, dtype=np.int64)
+    want[1:] = np.cumsum(np.bincount(bin_of, minlength=nb))
+    assert np.array_equal(off, want)
+    # every bin holds exactly its hits
+    assert np.array_equal(np.sort(order), np.arange(n))
+    in_bin = np.repeat(np.arange(nb), np.diff(off))
+    assert np.array_equal(bin_of[order], in_bin)
+    # device bins equal the host's FP64 bins away from the edges
+    diff = bin_of != ref_bins
+    assert (edge[diff] < 1e-4).all(), (np.flatnonzero(diff)[:5], edge[diff][:5])
+    return int(diff.sum())
+
+
+@pytest.mark.parametrize("case", ["barrel_one_event", "barrel_batch", "endcap", "coarse"])
+def test_index_is_the_counting_sort_of_the_bins(gpu_required, case):
+    g = synth.Geometry.endcap() if case == "endcap" else synth.Geometry()
+    if case == "barrel_batch":
+        # enough (event, layer) pairs for the one-block-per-layer form
+        evs = [synth.make_event(n, cfg=230, event=i, noise=0.3) for i, n in enumerate((20000, 3000, 777, 9000,
+                                                                                       40, 12000, 500))]
+    else:
+        evs = [synth.make_event(20000 if case != "endcap" else 10000, cfg=231, event=0, noise=0.1, geometry=g)]
+    tuning = dict(bins_phi=97, bins_z=13) if case == "coarse" else {}
+    c = abi.Context(abi.config_from_geometry(g, max_cands=6))
+    try:
+        if tuning:
+            c.set_tuning(**tuning)
+        hs = [c.load_event(e) for e in evs]
+        if case == "barrel_batch":
+            print(f"case index {case}: batch re-index of {len(evs)} events", flush=True)
+            c.build_batch(hs, None, flags=abi.BATCH_REINDEX)
+        t = c.get_tuning()
+        n_edge = n_hits = 0
+        for e, h in zip(evs, hs):
+            for L in range(g.n_layers):
+                print(f"case index {case}: layer {L}", flush=True)
+                off, bin_of, order = c.fetch_index(h, L, len(e.hits[L]))
+                ref, edge = host_bins(e.hits[L], L, g, t.bins_phi, t.bins_z)
+                n_edge += check_layer(off, bin_of, order, ref, edge)
+                n_hits += len(bin_of)
+    finally:
+        c.close()
+    report(f"index_{case}", dict(hits=n_hits, edge_differences=n_edge))
+    assert n_edge <= 1e-4 * n_hits + 2
