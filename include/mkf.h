@@ -251,6 +251,25 @@ mkf_status mkf_build(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags,
                            mkf_tracks *outs);
 
+/* mkf_build_batch without any allocation, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The batch descriptors (the
+ * events' device views, the work, hit, track and seed prefixes and the
+ * work-queue counter) go to a fixed array in device memory that the library
+ * holds per GPU for the life of the process, instead of memory allocated by
+ * the call; the host image of them is a fixed array too.  Inputs and outputs
+ * are as in mkf_build_batch.  Limits: at most 256 events (MKF_E_INVALID
+ * beyond), flags MKF_BATCH_REINDEX, _STATS, _ASYNC and _FIT only (the graph
+ * and the final beam allocate; MKF_E_INVALID), and every event must hold an
+ * index for the current bin grid - it has one from mkf_load_event or any
+ * mkf_build_batch since the last grid change - or MKF_E_STATE.  The call
+ * waits for the context stream before it rewrites the array, so the calls
+ * of one context are ordered; every context on one GPU shares the array,
+ * so calls of different contexts that overlap on one GPU race and must not
+ * be issued together. */
+mkf_status mkf_build_batch_noalloc(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags,
+                                   mkf_tracks *outs);
+
 /* Copy the last build results of an event to the host. */
 mkf_status mkf_fetch_tracks(mkf_ctx *ctx, int32_t handle, mkf_tracks *out);
 

@@ -109,6 +109,7 @@ _PROTOS = {
     "mkf_unload_event": (C.c_int, [_ctx_p, C.c_int32]),
     "mkf_build": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_build_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
+    "mkf_build_batch_noalloc": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
     "mkf_fetch_tracks": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_fetch_fit": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_fetch_beam": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
@@ -386,6 +387,17 @@ class Context:
             outs = [TrackArrays(int(n), self.n_layers) for n in n_seeds]
         tarr = (Tracks * len(outs))(*[o.tracks for o in outs])
         check(lib().mkf_build_batch(self.h, _ip(arr), len(arr), flags, tarr))
+        return [o.as_dict() for o in outs]
+
+    def build_batch_noalloc(self, handles: Sequence[int], n_seeds: Optional[Sequence[int]] = None, flags: int = 0):
+        """mkf_build_batch_noalloc: the batched build with no allocation in the call."""
+        arr = np.ascontiguousarray(handles, dtype=np.int32)
+        if n_seeds is None:
+            check(lib().mkf_build_batch_noalloc(self.h, _ip(arr), len(arr), flags, None))
+            return None
+        outs = [TrackArrays(int(n), self.n_layers) for n in n_seeds]
+        tarr = (Tracks * len(outs))(*[o.tracks for o in outs])
+        check(lib().mkf_build_batch_noalloc(self.h, _ip(arr), len(arr), flags, tarr))
         return [o.as_dict() for o in outs]
 
     def fetch_tracks(self, handle: int, n_seeds: int):

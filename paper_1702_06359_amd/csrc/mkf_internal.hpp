@@ -129,6 +129,15 @@ struct BatchArgs {
     int max_layer_hits;          // largest layer of any event (index launch shape)
 };
 
+// Batch descriptors of the no-allocation builder: a fixed device array per
+// GPU (mkf_kernels.hip), as laid out for up to kNoAllocMaxEvents events.
+constexpr int kNoAllocMaxEvents = 256;
+constexpr size_t round_up_256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNoAllocScratchBytes =
+    round_up_256(kNoAllocMaxEvents * sizeof(DevEvent)) + 4 * round_up_256((kNoAllocMaxEvents + 1) * sizeof(int)) + 256;
+hipError_t noalloc_scratch_init(int device);   // with `device` current; once per device
+void *noalloc_scratch(int device);              // its device address (null before init)
+
 // Launch helpers implemented in mkf_kernels.hip.
 size_t build_lds_bytes(int geo, int n_layers, int waves_per_block);   // dynamic LDS of a batched build block
 hipError_t launch_fill_i32(int *ptr, int value, int n, hipStream_t s);

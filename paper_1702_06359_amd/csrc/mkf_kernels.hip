@@ -1529,6 +1529,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
 }
 
 // ---------------------------------------------------------------------------
+// The no-allocation builder's batch descriptors: one fixed array in device
+// memory per GPU, kept until the process ends.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::atomic<void *> g_scratch_addr[64];
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (g_scratch_addr[device & 63].load()) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device & 63].store(p);
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device) { return g_scratch_addr[device & 63].load(); }
+
+// ---------------------------------------------------------------------------
 // launchers
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }

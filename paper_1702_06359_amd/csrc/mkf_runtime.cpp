@@ -859,6 +859,9 @@ mkf_status mkf_create(const mkf_config *cfg, const mkf_allocator *alloc, void *h
             MKF_HIP(hipEventCreate(&t.stop[i]));
         }
     MKF_HIP(hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming));
+    // device address of this GPU's fixed batch-descriptor array (the
+    // no-allocation builder); looked up once per device
+    MKF_HIP(noalloc_scratch_init(dev));
     *out = ctx.release();
     return MKF_OK;
 }
@@ -1114,6 +1117,66 @@ mkf_status mkf_build_batch(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint
             return st;
         if ((st = run_pipeline(ctx, args, recs, flags, true, ctx->stream)) != MKF_OK) return st;
     }
+    if (async) {
+        timers_collect(ctx, false);
+        return MKF_OK;
+    }
+    if (outs)
+        for (int i = 0; i < n; ++i)
+            if ((st = copy_tracks_out(ctx, recs[i], &outs[i], ctx->stream)) != MKF_OK) return st;
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    timers_collect(ctx, true);
+    if (outs)
+        for (int i = 0; i < n; ++i) finish_ndof(&outs[i]);
+    return MKF_OK;
+}
+
+mkf_status mkf_build_batch_noalloc(mkf_ctx *ctx, const int32_t *handles, int32_t n, uint32_t flags,
+                                   mkf_tracks *outs)
+{
+    if (!ctx) return fail(MKF_E_INVALID, "NULL context");
+    if (flags & ~(MKF_BATCH_REINDEX | MKF_BATCH_STATS | MKF_BATCH_ASYNC | MKF_BATCH_FIT))
+        return fail(MKF_E_INVALID, "only MKF_BATCH_REINDEX, _STATS, _ASYNC and _FIT build without allocating");
+    const bool async = flags & MKF_BATCH_ASYNC;
+    flags &= ~MKF_BATCH_ASYNC;
+    if (async && outs) return fail(MKF_E_INVALID, "an asynchronous batch returns no host outputs (outs must be NULL)");
+    if (n < 0 || (n > 0 && !handles)) return fail(MKF_E_INVALID, "bad handle list");
+    if (n > kNoAllocMaxEvents)
+        return fail(MKF_E_INVALID, "%d events: the no-allocation builder takes at most %d", n, kNoAllocMaxEvents);
+    if ((long long)n * ctx->cfg.n_layers > 65535)
+        return fail(MKF_E_INVALID, "at most %d events per batch", 65535 / ctx->cfg.n_layers);
+    char *dev = static_cast<char *>(noalloc_scratch(ctx->device));
+    if (!dev) return fail(MKF_E_DEVICE, "no descriptor array on device %d", ctx->device);
+    EventRec *recs[kNoAllocMaxEvents];
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(MKF_E_INVALID, "an event appears twice in the batch");
+        recs[i] = find_event(ctx, handles[i]);
+        if (!recs[i]) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handles[i]);
+        if (!recs[i]->index || recs[i]->index_bins_phi != ctx->tuning.bins_phi ||
+            recs[i]->index_bins_z != ctx->tuning.bins_z)
+            return fail(MKF_E_STATE, "event %d has no index for the current bin grid (mkf_build_batch makes one)",
+                        handles[i]);
+        if (outs && outs[i].n != recs[i]->shape.n_seeds)
+            return fail(MKF_E_INVALID, "build_batch_noalloc: output has %d rows, need %d", outs[i].n,
+                        recs[i]->shape.n_seeds);
+    }
+    if (n == 0) return MKF_OK;
+    // the descriptors go through one host image and the device array of this
+    // GPU; earlier work of this context may still read the array
+    static std::mutex image_mu;
+    static char image[kNoAllocScratchBytes];
+    MKF_HIP(hipStreamSynchronize(ctx->stream));
+    BatchArgs args{};
+    {
+        std::lock_guard<std::mutex> lk(image_mu);
+        mkf_status st = compose_batch(recs, n, seeds_per_item(ctx->tuning.lanes_per_seed), false, image, dev, &args);
+        if (st != MKF_OK) return st;
+        MKF_HIP(hipMemcpyAsync(dev, image, batch_scratch_bytes(n), hipMemcpyHostToDevice, ctx->stream));
+        MKF_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    mkf_status st = run_pipeline_with(ctx, ctx->params, ctx->tuning, args, flags, true, ctx->stream);
+    if (st != MKF_OK) return st;
     if (async) {
         timers_collect(ctx, false);
         return MKF_OK;
