@@ -35,7 +35,8 @@ FLOP_WINDOW = 37              # search window and bin range
 FLOP_PER_CAND_LAYER = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT + FLOP_WINDOW   # 509
 FLOP_PER_CHI2 = 39            # window tests, tangent-plane residual, 2x2 innovation, chi2
 FLOP_PER_UPDATE = 187         # gain, state and covariance update
-FLOP_PER_UPDATE_JOSEPH = 445  # fit update in Joseph form
+FLOP_PER_UPDATE_JOSEPH = 445  # fit update in Joseph form (the first JOSEPH_UPDATES of a fit)
+JOSEPH_UPDATES = 3
 FLOP_PER_FIT_STEP = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT   # 472, layers 1..9 of a fit
 BYTES_PER_FIT_TRACK = 216 + 40 + 10 * 16 + 232   # prior (f64), hit ids, hits (float4), fit result
 BYTES_PER_SEED_IO = 228 + 276     # seed in (f64 state, cov, hit ids) + track out
@@ -76,6 +77,16 @@ def measured_traffic(kernel):
         return int(round(rec["kernels"][kernel]["bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(*a):
@@ -124,41 +135,178 @@ def cpu_baseline_build(ev, k, target_cpu_s=15.0):
     t0 = time.perf_counter()
     oracle.build_tracks(cfg, hs, ev.seed_par, ev.seed_cov, ev.seed_hits, seed_ids=rows, n_threads=threads)
     wall = time.perf_counter() - t0
-    return {"value": n / wall, "unit": "tracks/s", "cores": threads, "kind": "oracle",
+    return {"value": n / wall, "unit": "tracks/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "single_thread_value": 1.0 / per_seed,
             "sample": f"{n} seeds of one 20,000-track event (FP64 oracle, brute-force hit search), "
                       f"{wall:.1f} s wall on {threads} threads; single-thread rate from the first "
                       f"{len(probe)} seeds"}
 
 
-def serve_latency(ctx, pool, n_submit, rate_hz, seed=0):
-    """Poisson arrivals at rate_hz from a pool of events; returns latencies (s)."""
-    from paper_1702_06359_amd import abi
+def _poisson_arrivals(n, rate_hz, seed):
     rng = np.random.default_rng(seed)
-    arrays = [abi.EventArrays.from_synth(e) for e in pool]
-    gaps = rng.exponential(1.0 / rate_hz, n_submit)
-    order = rng.integers(0, len(pool), n_submit)
-    pending, lat = [], []
-    t_next = time.perf_counter()
-    i = 0
-    while i < n_submit or pending:
-        now = time.perf_counter()
-        if i < n_submit and now >= t_next:
-            t, _ = ctx.serve_submit(None, ea=arrays[order[i]])
-            if t is not None:
-                pending.append(t)
-                i += 1
-                t_next += gaps[i - 1]
-        still = []
-        for t in pending:
-            r = ctx.serve_poll(t)
-            if r is None:
-                still.append(t)
-            else:
+    gaps = rng.exponential(1.0 / rate_hz, n)
+    return np.cumsum(gaps) - gaps[0], rng.integers(0, 1 << 30, n)
+
+
+def serve_run(ctx, arrays, sizes, arrivals, picks):
+    """Serve events arriving at `arrivals` (seconds from the start; picks[i]
+    indexes `arrays`).  One thread submits each event at its arrival time
+    (again and again while the server answers MKF_E_AGAIN: no slot or budget
+    free); another polls.  Latency of an event = the wait from its scheduled
+    arrival to its accepted submit plus the library's own submit-to-completion
+    time.  Returns (latencies in s, wall time from the first arrival to the
+    last completion)."""
+    import threading
+    from paper_1702_06359_amd import abi
+    n = len(arrivals)
+    pending = {}
+    lat = np.zeros(n)
+    lock = threading.Lock()
+    done_all = threading.Event()
+    t_last = [0.0]
+
+    def poller():
+        left = n
+        while left:
+            with lock:
+                items = list(pending.items())
+            for t, (i, waited) in items:
+                r = ctx.serve_poll(t)
+                if r is None:
+                    continue
                 assert r[0] == abi.OK, r[0]
-                lat.append(r[1])
-        pending = still
-    return np.array(lat)
+                lat[i] = waited + r[1]
+                t_last[0] = time.perf_counter()
+                with lock:
+                    del pending[t]
+                left -= 1
+            time.sleep(0.0001)
+        done_all.set()
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(n):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        ea = arrays[picks[i]]
+        out = abi.TrackArrays(int(ea.event.n_seeds), len(ea.hits))
+        while True:
+            t_call = time.perf_counter()
+            t, _ = ctx.serve_submit(None, ea=ea, out=out)
+            if t is not None:
+                break
+        with lock:
+            pending[t] = (i, t_call - t0 - arrivals[i])
+    done_all.wait()
+    th.join()
+    return lat, t_last[0] - t0
+
+
+def plain_run(ctx, arrays, n_seeds, arrivals, picks, max_events):
+    """The plain per-event builder on the same arrivals, one event at a time
+    (load: copy and index; build; tracks to the host; unload).  Latency from
+    the scheduled arrival to the event's tracks on the host."""
+    from paper_1702_06359_amd import abi
+    n = min(len(arrivals), max_events)
+    lat = np.zeros(n)
+    t0 = time.perf_counter()
+    for i in range(n):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        h = ctx.load_event(arrays[picks[i]])
+        ctx.build(h, n_seeds[picks[i]])
+        ctx.unload_event(h)
+        lat[i] = time.perf_counter() - t0 - arrivals[i]
+    return lat, time.perf_counter() - t0
+
+
+def serving_leg(args, n_events=2048, n_plain=384, budget=16 << 30):
+    """Served building (Poisson arrivals, tracks log-uniform in [500, 50,000],
+    30 % noise, k = 6) against the plain per-event builder on the same
+    arrivals, at 0.5 and 0.8 of the served saturated rate."""
+    from paper_1702_06359_amd import abi, synth
+    n_pool = 32
+    sizes = synth.loguniform_sizes(n_pool, 500, 50000, cfg=4)
+    log(f"serving: generating a pool of {n_pool} events")
+    pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(sizes)]
+    arrays = [abi.EventArrays.from_synth(e) for e in pool]
+    n_seeds = [e.n_seeds for e in pool]
+    ctx = make_ctx(6, args.tuning)
+    ctx.serve_config(budget, max_in_flight=64)
+    # saturated: every event arrives at once, the server admits as slots and
+    # budget free up
+    arr0, pick0 = _poisson_arrivals(256, 1e12, seed=3)
+    serve_run(ctx, arrays, sizes, np.zeros(64), pick0[:64] % n_pool)                 # warm-up
+    n_sat = 1024
+    arr_s, pick_s = _poisson_arrivals(n_sat, 1e12, seed=4)
+    _, wall = serve_run(ctx, arrays, sizes, np.zeros(n_sat), pick_s % n_pool)
+    sat = n_sat / wall
+    mean_tracks = float(np.mean(sizes[pick_s % n_pool]))
+    out = {"workload": "served building, Poisson arrivals, tracks log-uniform in [500, 50000] (pool of 32 events), "
+                       "30% noise, k=6, 16 GiB budget, 64 events in flight",
+           "saturated_events_per_s": round(sat, 1), "saturated_tracks_per_s": round(sat * mean_tracks, 1),
+           "hbm_budget_bytes": budget, "rates": []}
+    for frac in (0.5, 0.8):
+        rate = frac * sat
+        arr, pick = _poisson_arrivals(n_events, rate, seed=int(frac * 10))
+        pick = pick % n_pool
+        log(f"serving: {n_events} events at {rate:.0f} events/s")
+        lat, wall = serve_run(ctx, arrays, sizes, arr, pick)
+        tracks = float(sizes[pick].sum())
+        log(f"plain builder: first {n_plain} of the same arrivals")
+        plat, pwall = plain_run(ctx, arrays, n_seeds, arr, pick, n_plain)
+        ptracks = float(sizes[pick[:n_plain]].sum())
+        out["rates"].append({
+            "load": frac, "rate_events_per_s": round(rate, 1), "events": n_events,
+            "events_per_s": round(n_events / wall, 1), "tracks_per_s": round(tracks / wall, 1),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "plain": {"events": n_plain, "events_per_s": round(n_plain / pwall, 1),
+                      "tracks_per_s": round(ptracks / pwall, 1),
+                      "latency_p50_ms": round(float(np.percentile(plat, 50)) * 1e3, 3),
+                      "latency_p99_ms": round(float(np.percentile(plat, 99)) * 1e3, 3)}})
+    ctx.close()
+    return out
+
+
+def batched_leg(args, steps=10):
+    """256 uneven events (tracks log-uniform in [500, 20,000], noise
+    U[0.1, 0.5] per event and layer), indexed and built in one batched launch
+    per step with the launch shapes mkf_autotune picks on them, against the
+    plain per-event builder on the same resident events."""
+    import torch
+    from paper_1702_06359_amd import abi, synth
+    log("batched: generating 256 uneven events")
+    evs = synth.batched_events(256, 500, 20000)
+    ctx = make_ctx(6, args.tuning)
+    handles = [ctx.load_event(e) for e in evs]
+    log("batched: autotune")
+    tuned = ctx.autotune(handles).as_dict()
+
+    def sync():
+        ctx.sync()
+        torch.cuda.synchronize()
+    tracks = int(sum(e.n_seeds for e in evs))
+    step = lambda: ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC)
+    step()
+    sync()
+    ctx.timer_reset()
+    t_batch = time_steps(step, steps, 0, sync)
+    build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
+    index_ms, index_n = ctx.timer_read(abi.TIMER_INDEX)
+    n_plain = max(1, steps // 5)
+    t_plain = time_steps(lambda: [lib_build_plain(ctx, h) for h in handles], n_plain, 1, sync)
+    ctx.close()
+    rate = tracks * steps / t_batch
+    prate = tracks * n_plain / t_plain
+    return {"workload": "256 events, tracks log-uniform in [500, 20000], noise U[0.1,0.5] per event and layer, "
+                        "k=6, index + one batched build per step",
+            "tracks": tracks, "tuning": tuned, "tracks_per_s": round(rate, 1),
+            "ms_per_step": round(t_batch / steps * 1e3, 4),
+            "build_kernel_ms": round(build_ms / max(build_n, 1), 4),
+            "index_ms": round(index_ms / max(index_n, 1), 4),
+            "plain_builder_tracks_per_s": round(prate, 1), "speedup_vs_plain": round(rate / prate, 3)}
 
 
 def workload_ckf(args):
@@ -255,26 +403,10 @@ def workload_ckf(args):
                          "frac_of_fp32_peak": fit["roofline"]["frac"], "hbm_frac": fit["roofline"]["hbm_frac"]}
         log("best-hit latency")
         result["best_hit"] = best_hit_latency()
-        log("serving latency run")
-        pool_sizes = synth.loguniform_sizes(16, 500, 50000, cfg=4)
-        pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(pool_sizes)]
-        budget = 16 << 30
-        ctx.serve_config(budget, max_in_flight=64)
-        # saturated rate: everything submitted at once
-        t0 = time.perf_counter()
-        serve_latency(ctx, pool, 96, 1e9)
-        sat = 96 / (time.perf_counter() - t0)
-        rates = []
-        for frac in (0.5, 0.8):
-            serve_latency(ctx, pool, 256, frac * sat, seed=2)            # warm-up
-            lat = serve_latency(ctx, pool, 4096, frac * sat, seed=1)
-            rates.append({"load": frac, "rate_events_per_s": round(frac * sat, 1), "events": 4096,
-                          "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                          "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)})
-        result["serving"] = {"saturated_events_per_s": round(sat, 1), "hbm_budget_bytes": budget,
-                             "tracks_per_event_mean": float(np.mean(pool_sizes)),
-                             "latency_p50_ms": rates[0]["latency_p50_ms"],
-                             "latency_p99_ms": rates[0]["latency_p99_ms"], "rates": rates}
+        log("batched workload")
+        result["batched"] = batched_leg(args)
+        log("serving workload")
+        result["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline_build(evs[0], k, args.cpu_seconds)
@@ -450,8 +582,10 @@ def workload_fit(args):
     elapsed = time_steps(lambda: ctx.fit_batch(handles), args.steps, 0, sync)
     fit_ms, fit_n = ctx.timer_read(abi.TIMER_FIT)
     n = int(sizes.sum())
-    hits = int(sum((e.truth_hit >= 0).sum() for e in evs))
-    flops = n * 9 * FLOP_PER_FIT_STEP + hits * FLOP_PER_UPDATE_JOSEPH
+    per_track = np.concatenate([(e.truth_hit >= 0).sum(1) for e in evs])
+    joseph = int(np.minimum(per_track, JOSEPH_UPDATES).sum())       # the first updates of each track
+    plain = int(per_track.sum()) - joseph
+    flops = n * 9 * FLOP_PER_FIT_STEP + joseph * FLOP_PER_UPDATE_JOSEPH + plain * FLOP_PER_UPDATE
     avg_ms = fit_ms / max(fit_n, 1)
     achieved = flops / (avg_ms * 1e-3) / 1e12
     bytes_ = n * BYTES_PER_FIT_TRACK
@@ -483,93 +617,21 @@ def workload_fit(args):
 
 def workload_batched(args):
     """256 uneven events in one batched launch vs the plain per-event builder."""
-    import torch
-    from paper_1702_06359_amd import abi, synth
-    log("generating 256 uneven events")
-    evs = synth.batched_events(256, 500, 20000)
-    ctx = make_ctx(6, args.tuning)
-    handles = [ctx.load_event(e) for e in evs]
-    if args.tune:
-        log("autotuned:", ctx.autotune(handles).as_dict())
-    sync = torch.cuda.synchronize
-    tracks = int(sum(e.n_seeds for e in evs))
-    for _ in range(args.warmup):
-        ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX)
-    sync()
-    ctx.timer_reset()
-    t_batch = time_steps(lambda: ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX), args.steps, 0, sync)
-    build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
-    n_plain = max(1, args.steps // 5)
-    t_plain = time_steps(lambda: [lib_build_plain(ctx, h) for h in handles], n_plain, 1, sync)
-    res = {
-        "metric": "tracks built/sec, 256 uneven events in one batched launch",
-        "value": round(tracks * args.steps / t_batch, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(t_batch / args.steps * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "256 events, tracks log-uniform in [500, 20000], noise U[0.1,0.5] per layer, k=6",
-                   "tracks": tracks, "tuning": ctx.get_tuning().as_dict()},
-        "build_kernel_avg_ms": round(build_ms / max(build_n, 1), 4),
-        "plain_builder_tracks_per_s": round(tracks * n_plain / t_plain, 1),
-        "speedup_vs_plain": round((tracks * args.steps / t_batch) / (tracks * n_plain / t_plain), 3),
-    }
-    ctx.close()
-    return res
+    r = batched_leg(args, steps=args.steps)
+    return {"metric": "tracks built/sec, 256 uneven events in one batched launch", "value": r["tracks_per_s"],
+            "unit": "tracks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic", "config": {"workload": r["workload"]}, "batched": r}
 
 
 def workload_serve(args):
     """Poisson arrivals of events (500-50,000 tracks, 30 % noise), served with
-    continuous batching; latency p50/p99 against the plain builder serving the
-    same arrivals one event at a time."""
-    import torch
-    from paper_1702_06359_amd import abi, synth
-    n_pool = 48
-    sizes = synth.loguniform_sizes(n_pool, 500, 50000, cfg=4)
-    log(f"generating a pool of {n_pool} events")
-    pool = [synth.make_event(int(n), cfg=4, event=i, noise=0.3) for i, n in enumerate(sizes)]
-    ctx = make_ctx(6, args.tuning)
-    ctx.serve_config(16 << 30, max_in_flight=64)
-    serve_latency(ctx, pool, 64, 1e9)                 # warm-up
-    t0 = time.perf_counter()
-    serve_latency(ctx, pool, 256, 1e9)
-    sat = 256 / (time.perf_counter() - t0)
-    out = {"metric": "served events/sec and p50/p99 latency (Poisson arrivals)", "unit": "events/s",
-           "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
-           "config": {"workload": "events with tracks log-uniform in [500, 50000], 30% noise, k=6, budget 16 GiB",
-                      "pool": n_pool, "mean_tracks": float(sizes.mean())},
-           "saturated_events_per_s": round(sat, 1), "rates": []}
-    for frac in (0.5, 0.8):
-        rate = frac * sat
-        n = args.serve_events
-        t0 = time.perf_counter()
-        lat = serve_latency(ctx, pool, n, rate, seed=int(frac * 10))
-        wall = time.perf_counter() - t0
-        # the plain builder on the same arrival process, one event at a time
-        rng = np.random.default_rng(int(frac * 10))
-        gaps = rng.exponential(1.0 / rate, n)
-        order = rng.integers(0, len(pool), n)
-        arr = np.cumsum(gaps) - gaps[0]
-        plain_lat = []
-        t_start = time.perf_counter()
-        arrays = [abi.EventArrays.from_synth(e) for e in pool]
-        for j in range(min(n, args.serve_events)):
-            while time.perf_counter() - t_start < arr[j]:
-                pass
-            e = pool[order[j]]
-            h = ctx.load_event(arrays[order[j]])
-            ctx.build(h, e.n_seeds)
-            ctx.unload_event(h)
-            plain_lat.append(time.perf_counter() - t_start - arr[j])
-        plain_lat = np.array(plain_lat)
-        out["rates"].append({"rate_events_per_s": round(rate, 1), "events": n,
-                             "events_per_s": round(n / wall, 1),
-                             "tracks_per_s": round(float(sizes.mean()) * n / wall, 1),
-                             "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                             "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                             "plain_latency_p50_ms": round(float(np.percentile(plain_lat, 50)) * 1e3, 3),
-                             "plain_latency_p99_ms": round(float(np.percentile(plain_lat, 99)) * 1e3, 3)})
-    out["value"] = out["rates"][-1]["events_per_s"]
-    ctx.close()
-    return out
+    continuous batching; p50/p99 latency against the plain builder serving
+    the same arrivals one event at a time."""
+    r = serving_leg(args, n_events=args.serve_events)
+    return {"metric": "served events/sec and p50/p99 latency (Poisson arrivals)", "unit": "events/s",
+            "value": r["rates"][-1]["events_per_s"], "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic", "vs_baseline": None, "config": {"workload": r["workload"]}, "serving": r}
 
 
 def workload_calib(args):
@@ -600,7 +662,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ckf",
                     choices=["ckf", "endcap", "two_step", "fit", "batched", "serve", "calib"])
-    ap.add_argument("--serve-events", type=int, default=1024)
+    ap.add_argument("--serve-events", type=int, default=2048)
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--quick", action="store_true", help="headline number only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -475,11 +475,12 @@ class Context:
     def serve_config(self, hbm_budget_bytes: int, max_in_flight: int, max_batch_events: int = 0):
         check(lib().mkf_serve_config(self.h, int(hbm_budget_bytes), int(max_in_flight), int(max_batch_events)))
 
-    def serve_submit(self, ev, ea: Optional[EventArrays] = None):
+    def serve_submit(self, ev, ea: Optional[EventArrays] = None, out: Optional[TrackArrays] = None):
         """Returns (ticket, TrackArrays), or (None, None) when no in-flight slot
-        or budget is free (MKF_E_AGAIN: submit again later)."""
+        or budget is free (MKF_E_AGAIN: submit again later).  out: the arrays
+        to fill (made here if None)."""
         ea = ea or (ev if isinstance(ev, EventArrays) else EventArrays.from_synth(ev))
-        out = TrackArrays(int(ea.event.n_seeds), self.n_layers)
+        out = out or TrackArrays(int(ea.event.n_seeds), self.n_layers)
         t = C.c_uint64()
         st = lib().mkf_serve_submit(self.h, C.byref(ea.event), C.byref(out.tracks), C.byref(t))
         if st == E_AGAIN:

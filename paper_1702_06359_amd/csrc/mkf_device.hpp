@@ -82,9 +82,10 @@ __device__ __forceinline__ float4 load_global(const float4 *p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-// atan2 to ~2e-7 rad: octant reduction and an odd degree-15 polynomial
-// (least-squares fit to atan on [0, 1], max error 1.1e-7 in FP32).  Used only
-// for the search-window centre, whose bins are padded well beyond this error.
+// atan2 to 3.8e-7 rad: octant reduction and an odd degree-15 polynomial
+// (least-squares fit to atan on [0, 1], max error 1.1e-7 in FP32; the
+// rounding of results near pi dominates the total).  Used only for the
+// search-window centre, whose azimuth range is padded by 1e-5 rad.
 __device__ __forceinline__ float fast_atan2(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);

@@ -1335,6 +1335,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     flush_counts<kStats>(cnt, E, lane);
 }
 
+// Updates of a fit taken in Joseph form: three hits (six measured
+// coordinates) determine the five track parameters.
+constexpr int kJosephUpdates = 3;
+
 // ---------------------------------------------------------------------------
 // KF fit over a fixed hit list: from the prior (p, c) on layer 0, for each
 // layer the scattering of the previous one, propagation, transport, and the
@@ -1397,10 +1401,18 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
                 sh = hv.y;
                 g2h = hv.z;
             }
-            // Joseph form: a fit starts from a wide prior, where the plain
-            // form C - K H C would lose FP32 digits
-            if (kFit3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
-            else chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
+            // A fit starts from a wide prior: until a few hits have pinned
+            // the five parameters, C - K H C subtracts nearly equal numbers
+            // and would lose FP32 digits, so those updates take the Joseph
+            // form; after them the prediction is about as precise as a hit
+            // and the plain form keeps its digits.
+            if (nupd < kJosephUpdates) {
+                if (kFit3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+                else chi2 += kf_update_joseph<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
+            } else {
+                if (kFit3d) chi2 += kf_update_3d<false>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+                else chi2 += kf_update<kDisk>(p, c, tg, ch, sh, g2h, P.var_u, kDisk ? P.var_r : P.var_z);
+            }
             ++nupd;
 #pragma unroll
             for (int i = 0; i < 6; ++i) op[i] = p[i];

@@ -458,7 +458,7 @@ int seeds_per_item(int G) { return kWave / G; }
 
 // ---------------------------------------------------------------- events
 
-mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape)
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape, bool contents)
 {
     const mkf_config &c = ctx->cfg;
     if (!ev) return fail(MKF_E_INVALID, "event is NULL");
@@ -476,7 +476,7 @@ mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *s
         if (n < 0 || n > kMaxHitsPerLayer) return fail(MKF_E_INVALID, "layer %d: %d hits out of range", L, n);
         if (n > 0 && !ev->hit_xyz[L]) return fail(MKF_E_INVALID, "layer %d: hit_xyz is NULL", L);
         const double *h = ev->hit_xyz[L];
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; contents && i < n; ++i) {
             const double x = h[3 * i], y = h[3 * i + 1], z = h[3 * i + 2];
             if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z) || !(x * x + y * y > 0))
                 return fail(MKF_E_INVALID, "layer %d hit %d: not finite or on the axis", L, i);
@@ -489,9 +489,10 @@ mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *s
     const int nsl = c.n_seed_layers;
     if (ev->n_seeds > 0) {
         if (!ev->seed_par || !ev->seed_cov || !ev->seed_hits) return fail(MKF_E_INVALID, "seed arrays are NULL");
-        if (!finite_all(ev->seed_par, 6 * (size_t)ev->n_seeds) || !finite_all(ev->seed_cov, 21 * (size_t)ev->n_seeds))
+        if (contents && (!finite_all(ev->seed_par, 6 * (size_t)ev->n_seeds) ||
+                         !finite_all(ev->seed_cov, 21 * (size_t)ev->n_seeds)))
             return fail(MKF_E_INVALID, "seed state or covariance not finite");
-        for (int i = 0; i < ev->n_seeds; ++i) {
+        for (int i = 0; contents && i < ev->n_seeds; ++i) {
             const double *p = ev->seed_par + 6 * (size_t)i;
             if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
                 return fail(MKF_E_INVALID, "seed %d: theta outside (0, pi) or position on the axis", i);
@@ -503,10 +504,10 @@ mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *s
     }
     if (ev->n_tracks > 0) {
         if (!ev->track_par || !ev->track_cov || !ev->track_hits) return fail(MKF_E_INVALID, "track arrays are NULL");
-        if (!finite_all(ev->track_par, 6 * (size_t)ev->n_tracks) ||
-            !finite_all(ev->track_cov, 21 * (size_t)ev->n_tracks))
+        if (contents && (!finite_all(ev->track_par, 6 * (size_t)ev->n_tracks) ||
+                         !finite_all(ev->track_cov, 21 * (size_t)ev->n_tracks)))
             return fail(MKF_E_INVALID, "track state or covariance not finite");
-        for (int i = 0; i < ev->n_tracks; ++i) {
+        for (int i = 0; contents && i < ev->n_tracks; ++i) {
             const double *p = ev->track_par + 6 * (size_t)i;
             if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
                 return fail(MKF_E_INVALID, "track %d: theta outside (0, pi) or position on the axis", i);

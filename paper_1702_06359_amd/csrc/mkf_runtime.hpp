@@ -156,7 +156,8 @@ struct mkf_ctx {
 namespace mkf {
 
 // context-level helpers used by the ABI and the scheduler
-mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape);
+// contents = false checks the counts and pointers only (the shape), not the values
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape, bool contents = true);
 mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap, std::unique_ptr<EventRec> *out);
 mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s);
 void destroy_event(mkf_ctx *ctx, EventRec *rec);

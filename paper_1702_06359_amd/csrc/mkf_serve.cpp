@@ -437,8 +437,10 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
     if (!ctx || !out || !ticket) return fail(MKF_E_INVALID, "NULL argument");
     Server *sv = ctx->server.get();
     if (!sv) return fail(MKF_E_STATE, "serving is not configured");
+    // the shape first (cheap), so that a submit refused for want of a slot
+    // or budget costs little; the values once admitted
     EventShape shape;
-    mkf_status st = validate_event(ctx, ev, &shape);
+    mkf_status st = validate_event(ctx, ev, &shape, false);
     if (st != MKF_OK) return st;
     if (out->n != shape.n_seeds) return fail(MKF_E_INVALID, "output has %d rows, need %d", out->n, shape.n_seeds);
     shape.n_tracks = 0;   // serving builds; tracks for fitting are not staged
@@ -465,6 +467,13 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
         sv->reserved -= need;
         sv->cv.notify_all();
     };
+    {
+        EventShape full;
+        if ((st = validate_event(ctx, ev, &full)) != MKF_OK) {
+            unreserve();
+            return st;
+        }
+    }
     const InLayout il = in_layout(shape);
     const OutLayout ol = out_layout(shape);
     t->in_pin = sv->pinned.get(il.total, &t->in_cls);
