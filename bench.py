@@ -38,8 +38,8 @@ FLOP_PER_UPDATE = 187         # gain, state and covariance update
 FLOP_PER_UPDATE_JOSEPH = 445  # fit update in Joseph form (the first JOSEPH_UPDATES of a fit)
 JOSEPH_UPDATES = 3
 FLOP_PER_FIT_STEP = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT   # 472, layers 1..9 of a fit
-BYTES_PER_FIT_TRACK = 216 + 40 + 10 * 16 + 232   # prior (f64), hit ids, hits (float4), fit result
-BYTES_PER_SEED_IO = 228 + 276     # seed in (f64 state, cov, hit ids) + track out
+BYTES_PER_FIT_TRACK = 108 + 40 + 10 * 16 + 232   # prior (f32), hit ids, hits (float4), fit result (f64)
+BYTES_PER_SEED_IO = 120 + 276     # seed in (f32 state, cov, hit ids) + track out (f64)
 BYTES_PER_HIT = 16                # binned hit read once
 BYTES_PER_BIN = 4                 # bin offset read once
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
@@ -470,8 +470,9 @@ def fitted_vs_built(ctx, ev, h):
 
 
 def host_inclusive(ctx, evs, reps=3):
-    """The headline workload from host buffers to host buffers: load every
-    event (copies of its FP64 hits and seeds, its hit index), one batched
+    """The headline workload from host buffers to host buffers: load the
+    events in one call (their FP64 hits and seeds checked and narrowed to
+    FP32 on host threads, one copy per event, every hit index), one batched
     build, copy of every track to the host, unload.  Median wall time of
     `reps` steps after one warm-up step, with the caller's buffers in
     ordinary (pageable) numpy arrays made per step, and in page-locked
@@ -492,7 +493,7 @@ def host_inclusive(ctx, evs, reps=3):
         times = []
         for _ in range(reps + 1):
             t0 = time.perf_counter()
-            hs = [ctx.load_event(a) for a in arrays]
+            hs = ctx.load_events(arrays)
             if outs is None:
                 ctx.build_batch(hs, counts)
             else:
@@ -507,7 +508,8 @@ def host_inclusive(ctx, evs, reps=3):
                               pin_copy(e.seed_par), pin_copy(e.seed_cov), pin_copy(e.seed_hits)) for e in evs]
     pin_out = [abi.TrackArrays(n, len(evs[0].hits), empty=pinned) for n in counts]
     t_pin = run(pin_in, pin_out)
-    return {"step": "load (host FP64 hits and seeds, index) + batched build + tracks to host + unload",
+    return {"step": "load of all events (FP64 hits and seeds narrowed to FP32 on the host, copies, index) + "
+                    "batched build + tracks to host + unload",
             "tracks_per_s": round(sum(counts) / t_page, 1), "ms_per_step": round(t_page * 1e3, 3),
             "pinned_reused_buffers": {"tracks_per_s": round(sum(counts) / t_pin, 1),
                                       "ms_per_step": round(t_pin * 1e3, 3)}}

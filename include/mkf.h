@@ -215,13 +215,23 @@ int32_t mkf_ctx_broken(const mkf_ctx *ctx);
 mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t);
 mkf_status mkf_get_tuning(const mkf_ctx *ctx, mkf_tuning *t);
 
-/* Load an event: validate on the host, copy hits, seeds and tracks to the
- * device and build its (eta, phi)-binned hit index there (Section 3.2.1: the
- * data structures used to select hit candidates).  Synchronous: the host
- * arrays may be freed on return.  *handle identifies the event until
+/* Load an event: validate on the host while narrowing its coordinates,
+ * states and covariances to FP32, copy hits, seeds and tracks to the device
+ * and build its (eta, phi)-binned hit index there (Section 3.2.1: the data
+ * structures used to select hit candidates).  Synchronous: the host arrays
+ * may be freed on return.  *handle identifies the event until
  * mkf_unload_event.  Errors: MKF_E_INVALID (counts, NaN or hit index out of
  * range), MKF_E_NOMEM, MKF_E_DEVICE. */
 mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle);
+
+/* Load n events at once: as mkf_load_event for each, with their copies and
+ * their hit indices in one pass and one wait (Section 5: on a GPU the setup
+ * copies dominate).  The inputs are checked and narrowed to FP32 on up to
+ * 16 host threads into pinned staging (12 bytes per hit, 120 per seed),
+ * then copied in one piece per event.  handles[n] receives the handles.  On
+ * error nothing is loaded and the message names the failing event.  At most
+ * 65,535 / n_layers events per call. */
+mkf_status mkf_load_events(mkf_ctx *ctx, const mkf_event *evs, int32_t n, int32_t *handles);
 mkf_status mkf_unload_event(mkf_ctx *ctx, int32_t handle);
 
 /* Plain builder: one event, one kernel launch per layer with the candidate

@@ -107,6 +107,7 @@ _PROTOS = {
     "mkf_get_tuning": (C.c_int, [_ctx_p, _P(Tuning)]),
     "mkf_load_event": (C.c_int, [_ctx_p, _P(Event), _P(C.c_int32)]),
     "mkf_unload_event": (C.c_int, [_ctx_p, C.c_int32]),
+    "mkf_load_events": (C.c_int, [_ctx_p, _P(Event), C.c_int32, _P(C.c_int32)]),
     "mkf_build": (C.c_int, [_ctx_p, C.c_int32, _P(Tracks)]),
     "mkf_build_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
     "mkf_build_batch_noalloc": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, C.c_uint32, _P(Tracks)]),
@@ -366,6 +367,14 @@ class Context:
         h = C.c_int32()
         check(lib().mkf_load_event(self.h, C.byref(ea.event), C.byref(h)))
         return int(h.value)
+
+    def load_events(self, evs) -> List[int]:
+        """mkf_load_events: several events in one pass; returns their handles."""
+        eas = [e if isinstance(e, EventArrays) else EventArrays.from_synth(e, with_tracks=True) for e in evs]
+        arr = (Event * len(eas))(*[ea.event for ea in eas])
+        hs = np.zeros(len(eas), dtype=np.int32)
+        check(lib().mkf_load_events(self.h, arr, len(eas), _ip(hs)))
+        return [int(h) for h in hs]
 
     def unload_event(self, handle: int):
         check(lib().mkf_unload_event(self.h, int(handle)))

@@ -82,6 +82,15 @@ __device__ __forceinline__ float4 load_global(const float4 *p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// An event descriptor as the kernels read it.  No kernel writes the
+// descriptors, so they are read through the constant address space: with a
+// wave-uniform event its fields become scalar loads into SGPRs, taken once,
+// instead of vector loads that every global store would force the compiler
+// to repeat.
+typedef const __attribute__((address_space(4))) DevEvent CEvent;
+
+__device__ __forceinline__ CEvent &event_desc(const DevEvent *events, int e) { return *(CEvent *)(events + e); }
+
 // atan2 to 3.8e-7 rad: octant reduction and an odd degree-15 polynomial
 // (least-squares fit to atan on [0, 1], max error 1.1e-7 in FP32; the
 // rounding of results near pi dominates the total).  Used only for the

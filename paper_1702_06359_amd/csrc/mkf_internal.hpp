@@ -59,18 +59,19 @@ struct DevEvent {
     int n_tracks;
     int n_hits;                          // all layers
     int layer_off[kMaxLayers + 1];       // first hit of each layer in the flat hit arrays
-    const double *raw_xyz;               // [n_hits][3] caller order
-    float4 *hits;                        // [n_hits] caller order: (cos phi_h, sin phi_h, z or r, 0)
+    const float4 *hits;                  // [n_hits] caller order, packed by the host from the FP64 input:
+                                         // (cos phi_h, sin phi_h, z, r) on a cylinder, (cos, sin, r, z) on a
+                                         // disk; (x, y, z, 0) for thick layers and the 3x3 measurement
     float4 *binned;                      // [n_hits] grouped by layer then bin: (c, s, z or r, id bits)
     int *bin_of;                         // [n_hits] bin of each caller-order hit
     int *bin_rank;                       // [n_hits] position of the hit inside its bin
     int *bin_count;                      // [n_layers][n_bins] counts (zero between index builds)
     int *bin_off;                        // [n_layers][n_bins + 1] absolute index into `binned`
-    const double *seed_par;              // [n_seeds][6]
-    const double *seed_cov;              // [n_seeds][21]
+    const float *seed_par;               // [n_seeds][6]
+    const float *seed_cov;               // [n_seeds][21]
     const int *seed_hits;                // [n_seeds][n_seed_layers]
-    const double *track_par;             // [n_tracks][6]
-    const double *track_cov;             // [n_tracks][21]
+    const float *track_par;              // [n_tracks][6]
+    const float *track_cov;              // [n_tracks][21]
     const int *track_hits;               // [n_tracks][n_layers]
     // build outputs
     double *out_par;                     // [n_seeds][6]

@@ -155,39 +155,38 @@ constexpr bool geo_xyz(int geo) { return (geo & 2) != 0; }
 // or (r, phi): bin = iz * bins_phi + iphi.  A counting sort over all events
 // of a batch at once.
 
-// A caller-order hit as (cos phi, sin phi, z or r, 0) - on a layer of finite
-// thickness (x, y, z, 0), whose own surface the second propagation step
-// needs - and its (row, phi) bin.
-__device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const double *xyz, float4 *out)
+// The bin of a hit as the host packed it: (cos phi_h, sin phi_h, g2, -) with
+// g2 = z on a cylinder and r on a disk, or, on layers of finite thickness and
+// for the 3x3 measurement, (x, y, z, 0), whose own surface the second
+// propagation step needs.  bin = row * bins_phi + (phi bin).
+__device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const float4 v)
 {
-    const double x = xyz[0], y = xyz[1];
-    const double rr = sqrt(x * x + y * y);
-    const double ir = 1.0 / rr;
-    const float c = (float)(x * ir), s = (float)(y * ir);
-    const float g2 = lp.kind ? (float)rr : (float)xyz[2];
-    const float phi = atan2f(s, c);
+    float phi, g2;
+    if (geo_xyz(P.geo)) {
+        phi = atan2f(v.y, v.x);
+        g2 = lp.kind ? sqrtf(fmaf(v.x, v.x, v.y * v.y)) : v.z;
+    } else {
+        phi = atan2f(v.y, v.x);
+        g2 = v.z;
+    }
     int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
     int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
     ip = min(max(ip, 0), P.bins_phi - 1);
     iz = min(max(iz, 0), P.bins_z - 1);
-    *out = geo_xyz(P.geo) ? make_float4((float)x, (float)y, (float)xyz[2], 0.f) : make_float4(c, s, g2, 0.f);
     return iz * P.bins_phi + ip;
 }
 
-// Conversion and binning of every hit of a batch, no atomics: grid
-// (chunks, event x layer).  Precedes k_index_lds.
+// Binning of every hit of a batch, no atomics: grid (chunks, event x
+// layer).  Precedes k_index_lds / k_index_layer.
 __global__ void __launch_bounds__(256) k_index_bin(const Params P, const BatchArgs B)
 {
     const int e = blockIdx.y / P.n_layers;
     const int L = blockIdx.y - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const LayerParam lp = P.layer[L];
-    for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
-        float4 v;
-        store_global(E.bin_of + h, bin_hit(P, lp, E.raw_xyz + 3 * (size_t)h, &v));
-        store_global(E.hits + h, v);
-    }
+    for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x)
+        store_global(E.bin_of + h, bin_hit(P, lp, load_global(E.hits + h)));
 }
 
 // Bin counters in LDS: one 32-bit counter per bin, or two 16-bit counters per
@@ -302,7 +301,7 @@ __global__ void __launch_bounds__(1024) k_index_lds(const Params P, const BatchA
     const int el = blockIdx.x / nsplit;
     const int e = el / P.n_layers;
     const int L = el - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const int nb = P.bins_phi * P.bins_z;
     int *off = E.bin_off + L * (nb + 1);
@@ -366,7 +365,7 @@ __global__ void __launch_bounds__(1024) k_index_layer(const Params P, const Batc
     __shared__ int s_wave[16];
     const int e = blockIdx.x / P.n_layers;
     const int L = blockIdx.x - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const int nb = P.bins_phi * P.bins_z;
     int *off = E.bin_off + L * (nb + 1);
@@ -407,20 +406,18 @@ __global__ void __launch_bounds__(1024) k_index_layer(const Params P, const Batc
     }
 }
 
-// Pass 1: convert each caller-order hit to (cos phi, sin phi, z), bin it and
-// take its position in the bin.  Grid (chunks, event x layer).
+// Pass 1: bin each caller-order hit and take its position in the bin.  Grid
+// (chunks, event x layer).
 __global__ void __launch_bounds__(256) k_index_prep(const Params P, const BatchArgs B)
 {
     const int e = blockIdx.y / P.n_layers;
     const int L = blockIdx.y - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const LayerParam lp = P.layer[L];
     int *cnt = E.bin_count + L * P.bins_phi * P.bins_z;
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
-        float4 v;
-        const int bin = bin_hit(P, lp, E.raw_xyz + 3 * (size_t)h, &v);
-        E.hits[h] = v;
+        const int bin = bin_hit(P, lp, load_global(E.hits + h));
         E.bin_of[h] = bin;
         E.bin_rank[h] = atomicAdd(&cnt[bin], 1);
     }
@@ -436,7 +433,7 @@ __global__ void __launch_bounds__(1024) k_index_scan(const Params P, const Batch
     __shared__ int s_wave[16];
     const int e = blockIdx.x / P.n_layers;
     const int L = blockIdx.x - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int nb = P.bins_phi * P.bins_z;
     int *cnt = E.bin_count + L * nb;
     int *off = E.bin_off + L * (nb + 1);
@@ -509,7 +506,7 @@ __global__ void __launch_bounds__(256) k_index_scatter(const Params P, const Bat
 {
     const int e = blockIdx.y / P.n_layers;
     const int L = blockIdx.y - e * P.n_layers;
-    const DevEvent &E = B.events[e];
+    CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const int nb = P.bins_phi * P.bins_z;
     const int *off = E.bin_off + L * (nb + 1);
@@ -867,7 +864,7 @@ __device__ __forceinline__ float dphi_of(float xr)
 template <int K, bool kStats, int kGeo>
 __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], const Trig &tg, float chi2,
                                             bool predicted, int L, const LayerParam &lp, const Params &P,
-                                            const DevEvent &E, int lane, SearchLds<kGeo> &W,
+                                            CEvent &E, int lane, SearchLds<kGeo> &W,
                                             unsigned long long (&lk)[K], Count &cnt)
 {
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
@@ -987,7 +984,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     return ws.n_mine;
 }
 
-__device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Params &P, int seed, bool first_slot)
+__device__ __forceinline__ void init_lane(Lane &S, CEvent &E, const Params &P, int seed, bool first_slot)
 {
     S.live = first_slot ? 1 : 0;
     S.stopped = 0;
@@ -1002,9 +999,9 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
     for (int i = 0; i < 21; ++i) S.c[i] = 0.f;
     if (!first_slot) return;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) S.p[i] = (float)load_global(E.seed_par + 6 * (size_t)seed + i);
+    for (int i = 0; i < 6; ++i) S.p[i] = load_global(E.seed_par + 6 * (size_t)seed + i);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) S.c[i] = (float)load_global(E.seed_cov + 21 * (size_t)seed + i);
+    for (int i = 0; i < 21; ++i) S.c[i] = load_global(E.seed_cov + 21 * (size_t)seed + i);
     for (int L = 0; L < P.n_seed_layers; ++L) S.n_hits += load_global(E.seed_hits + (size_t)seed * P.n_seed_layers + L) >= 0;
     S.tg = trig_of(S.p);
 }
@@ -1013,7 +1010,7 @@ __device__ __forceinline__ void init_lane(Lane &S, const DevEvent &E, const Para
 // candidate to the next layer, collect compatible hits, branch; Section
 // 3.2.1: re-rank and prune to max_cands per seed).
 template <int G, bool kStats, int kGeo>
-__device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, const DevEvent &E,
+__device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P, CEvent &E,
                                            const int lane, const Hist &H, SearchLds<kGeo> &W, Count &cnt)
 {
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
@@ -1173,7 +1170,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
 // Rank-0 candidate of each seed to the output arrays, hit list unwound
 // through the per-layer records.
 template <int G>
-__device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, const DevEvent &E, int lane,
+__device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, CEvent &E, int lane,
                                               int seed, const Hist &H)
 {
     const int gbase = (lane / G) * G;
@@ -1218,7 +1215,7 @@ __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, co
 }
 
 template <bool kStats>
-__device__ __forceinline__ void flush_counts(const Count &cnt, const DevEvent &E, int lane)
+__device__ __forceinline__ void flush_counts(const Count &cnt, CEvent &E, int lane)
 {
     if (!kStats) return;
     unsigned long long v[5] = {cnt.prop, cnt.chi2, cnt.acc, cnt.upd, cnt.scan};
@@ -1264,7 +1261,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
         item = uniform(item);
         if (item >= B.total_items) break;
         const int e = uniform(upper_bound_i32(B.item_prefix, B.n_events + 1, item) - 1);
-        const DevEvent &E = B.events[e];
+        CEvent &E = event_desc(B.events, e);
         const int seed = (item - B.item_prefix[e]) * B.seeds_per_item + lane / G;
         const bool valid = lane < (kWave / G) * G && seed < E.n_seeds;
         Lane S;
@@ -1282,7 +1279,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
 template <int G, bool kStats, int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_build_layer(const Params P, const DevEvent *__restrict__ Ep, int L)
 {
-    const DevEvent &E = *Ep;
+    CEvent &E = event_desc(Ep, 0);
     const int lane = threadIdx.x & (kWave - 1);
     const int item = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     constexpr int kSeedsPerWave = kWave / G;
@@ -1345,7 +1342,7 @@ constexpr int kJosephUpdates = 3;
 // update with that layer's hit if it has one (hit_of(L) >= 0).  (op, oc) is
 // the state after the last update.
 template <int kGeo, class HitOf>
-__device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, float (&p)[6], float (&c)[21],
+__device__ __forceinline__ void fit_track(const Params &P, CEvent &E, float (&p)[6], float (&c)[21],
                                           HitOf hit_of, float (&op)[6], float (&oc)[21], float &chi2, int &nupd,
                                           int &status)
 {
@@ -1422,21 +1419,16 @@ __device__ __forceinline__ void fit_track(const Params &P, const DevEvent &E, fl
     }
 }
 
-// Fit with known hits: one lane per track, no branching beyond skipped layers.
+// One track of a fit with known hits.
 template <int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_fit(const Params P, const BatchArgs B)
+__device__ __forceinline__ void fit_known(const Params &P, CEvent &E, const size_t t)
 {
-    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (g >= B.total_tracks) return;
-    const int e = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
-    const DevEvent &E = B.events[e];
-    const size_t t = (size_t)(g - B.track_prefix[e]);
     float p[6], c[21], op[6], oc[21], chi2;
     int nupd, status;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) p[i] = (float)load_global(E.track_par + 6 * t + i);
+    for (int i = 0; i < 6; ++i) p[i] = load_global(E.track_par + 6 * t + i);
 #pragma unroll
-    for (int i = 0; i < 21; ++i) c[i] = (float)load_global(E.track_cov + 21 * t + i);
+    for (int i = 0; i < 21; ++i) c[i] = load_global(E.track_cov + 21 * t + i);
     fit_track<kGeo>(P, E, p, c, [&](int L) { return load_global(E.track_hits + t * P.n_layers + L); }, op, oc,
                     chi2, nupd, status);
 #pragma unroll
@@ -1448,61 +1440,88 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     store_global(E.fit_status + t, status);
 }
 
+// Fit with known hits: one lane per track, no branching beyond skipped layers.
+template <int kGeo>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_fit(const Params P, const BatchArgs B)
+{
+    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (g >= B.total_tracks) return;
+    const int e_lane = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
+    // one pass per batch the wave's lanes cover (two where a batch boundary
+    // falls inside the wave), each with a wave-uniform descriptor
+    for (;;) {
+        const int e = uniform(e_lane);
+        if (e_lane != e) continue;
+        CEvent &E = event_desc(B.events, e);
+        fit_known<kGeo>(P, E, (size_t)(g - load_global(B.track_prefix + e)));
+        break;
+    }
+}
+
 // Prior of the final fit of a built track: the helix through its hits on
 // layers 0, 1 and 2 (the transverse circle through the three points; z
 // linear in the arc length), at the first hit, with a loose diagonal
 // covariance in the frame (u, z, q/pT, phi, theta) of the layer tangent at
 // that hit, (u, r, q/pT, phi, theta) on a disk: sigma = (1 cm, 10 cm,
-// 1 / GeV, 0.1, 0.1).  Computed in double from the caller's coordinates;
-// false without three usable points.
+// 1 / GeV, 0.1, 0.1).  FP32 from the event's packed hits; false without
+// three usable points.
 template <bool kDisk>
-__device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params &P, const int *hits, float (&p)[6],
+__device__ __forceinline__ bool final_fit_prior(CEvent &E, const Params &P, const int *hits, float (&p)[6],
                                                 float (&c)[21])
 {
-    double q[3][3];
+    float q[3][3];
     for (int L = 0; L < 3; ++L) {
         const int h = hits[L];
         if (h < 0) return false;
-        const double *x = E.raw_xyz + 3 * (size_t)(E.layer_off[L] + h);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) q[L][j] = load_global(x + j);
+        // the hit's position from its packed form: (x, y, z, -), or
+        // (cos, sin, z, r) on a cylinder and (cos, sin, r, z) on a disk
+        const float4 v = load_global(E.hits + E.layer_off[L] + h);
+        if (geo_xyz(P.geo)) {
+            q[L][0] = v.x;
+            q[L][1] = v.y;
+            q[L][2] = v.z;
+        } else {
+            const float r = kDisk ? v.z : v.w;
+            q[L][0] = r * v.x;
+            q[L][1] = r * v.y;
+            q[L][2] = kDisk ? v.w : v.z;
+        }
     }
-    const double d1x = q[1][0] - q[0][0], d1y = q[1][1] - q[0][1];   // first to second
-    const double d3x = q[2][0] - q[0][0], d3y = q[2][1] - q[0][1];   // first to third
-    const double l1 = sqrt(d1x * d1x + d1y * d1y), l3 = sqrt(d3x * d3x + d3y * d3y);
-    const double ex = q[2][0] - q[1][0], ey = q[2][1] - q[1][1];
-    const double l2 = sqrt(ex * ex + ey * ey);
-    const double twice_area = d1x * d3y - d1y * d3x;
-    if (!(l1 > 0.0 && l2 > 0.0 && l3 > 0.0) || twice_area == 0.0) return false;
-    const double curv = 2.0 * twice_area / (l1 * l2 * l3);           // > 0 turning counter-clockwise
+    const float d1x = q[1][0] - q[0][0], d1y = q[1][1] - q[0][1];   // first to second
+    const float d3x = q[2][0] - q[0][0], d3y = q[2][1] - q[0][1];   // first to third
+    const float ex = q[2][0] - q[1][0], ey = q[2][1] - q[1][1];
+    const float l1 = sqrtf(fmaf(d1x, d1x, d1y * d1y)), l3 = sqrtf(fmaf(d3x, d3x, d3y * d3y));
+    const float l2 = sqrtf(fmaf(ex, ex, ey * ey));
+    const float twice_area = fmaf(d1x, d3y, -d1y * d3x);
+    if (!(l1 > 0.f && l2 > 0.f && l3 > 0.f) || twice_area == 0.f) return false;
+    const float curv = 2.f * twice_area / (l1 * l2 * l3);           // > 0 turning counter-clockwise
     // tangent at the first point: the chord to the second point, turned back
     // by half the angle the arc between them sweeps
-    const double half = asin(fmin(1.0, fmax(-1.0, 0.5 * curv * l1)));
-    double phi = atan2(d1y, d1x) - half;
-    constexpr double kPiD = 3.14159265358979323846;
-    phi = phi > kPiD ? phi - 2.0 * kPiD : (phi <= -kPiD ? phi + 2.0 * kPiD : phi);
-    const double u3 = 0.5 * curv * l3;
-    const double arc3 = fabs(u3) < 1e-12 ? l3 : 2.0 * asin(fmin(1.0, fmax(-1.0, u3))) / curv;
-    const double theta = 0.5 * kPiD - atan((q[2][2] - q[0][2]) / arc3);
-    p[0] = (float)q[0][0];
-    p[1] = (float)q[0][1];
-    p[2] = (float)q[0][2];
-    p[3] = (float)(curv / (double)P.w_per_qpt);
-    p[4] = (float)phi;
-    p[5] = (float)theta;
-    const double a = atan2(q[0][1], q[0][0]);
-    const double sa = sin(a), ca = cos(a);
+    const float half = asinf(fminf(1.f, fmaxf(-1.f, 0.5f * curv * l1)));
+    const float phi = wrap_pi(atan2f(d1y, d1x) - half);
+    const float u3 = 0.5f * curv * l3;
+    const float arc3 = fabsf(u3) < 1e-4f ? l3 * fmaf(u3 * u3, 1.f / 6.f, 1.f)
+                                         : 2.f * asinf(fminf(1.f, fmaxf(-1.f, u3))) / curv;
+    const float theta = 0.5f * kPi - atanf((q[2][2] - q[0][2]) / arc3);
+    p[0] = q[0][0];
+    p[1] = q[0][1];
+    p[2] = q[0][2];
+    p[3] = curv / P.w_per_qpt;
+    p[4] = phi;
+    p[5] = theta;
+    float sa, ca;
+    sincosf(atan2f(q[0][1], q[0][0]), &sa, &ca);
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = 0.f;
     if (!kDisk) {
-        c[sym(0, 0)] = (float)(sa * sa);
-        c[sym(0, 1)] = (float)(-sa * ca);
-        c[sym(1, 1)] = (float)(ca * ca);
+        c[sym(0, 0)] = sa * sa;
+        c[sym(0, 1)] = -sa * ca;
+        c[sym(1, 1)] = ca * ca;
         c[sym(2, 2)] = 100.f;
     } else {
-        c[sym(0, 0)] = (float)(sa * sa + 100.0 * ca * ca);
-        c[sym(0, 1)] = (float)(99.0 * sa * ca);
-        c[sym(1, 1)] = (float)(ca * ca + 100.0 * sa * sa);
+        c[sym(0, 0)] = fmaf(100.f * ca, ca, sa * sa);
+        c[sym(0, 1)] = 99.f * sa * ca;
+        c[sym(1, 1)] = fmaf(100.f * sa, sa, ca * ca);
     }
     c[sym(3, 3)] = 1.f;
     c[sym(4, 4)] = 0.01f;
@@ -1510,16 +1529,10 @@ __device__ __forceinline__ bool final_fit_prior(const DevEvent &E, const Params 
     return true;
 }
 
-// Final fit of every built track of a batch (after the build): one lane per
-// seed, hits from the build's output.
+// Final fit of one built track, its hits from the build's output.
 template <int kGeo>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_refit(const Params P, const BatchArgs B)
+__device__ __forceinline__ void refit_built(const Params &P, CEvent &E, const size_t t)
 {
-    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (g >= B.total_seeds) return;
-    const int e = upper_bound_i32(B.seed_prefix, B.n_events + 1, g) - 1;
-    const DevEvent &E = B.events[e];
-    const size_t t = (size_t)(g - B.seed_prefix[e]);
     const int *hits = E.out_hits + t * P.n_layers;
     float p[6], c[21], op[6], oc[21], chi2 = 0.f;
     int nupd = 0, status = 3;
@@ -1538,6 +1551,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     store_global(E.rf_chi2 + t, (double)chi2);
     store_global(E.rf_nupd + t, nupd);
     store_global(E.rf_status + t, status);
+}
+
+// Final fit of every built track of a batch (after the build): one lane per
+// seed.
+template <int kGeo>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_refit(const Params P, const BatchArgs B)
+{
+    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (g >= B.total_seeds) return;
+    const int e_lane = upper_bound_i32(B.seed_prefix, B.n_events + 1, g) - 1;
+    // one pass per event the wave's lanes cover, as in k_fit
+    for (;;) {
+        const int e = uniform(e_lane);
+        if (e_lane != e) continue;
+        CEvent &E = event_desc(B.events, e);
+        refit_built<kGeo>(P, E, (size_t)(g - load_global(B.seed_prefix + e)));
+        break;
+    }
 }
 
 // ---------------------------------------------------------------------------

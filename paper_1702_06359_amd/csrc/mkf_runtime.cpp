@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 
 namespace mkf {
 
@@ -122,21 +123,23 @@ struct Carver {
     }
 };
 
-size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_view)
+// The event's inputs come first (hits, seeds, tracks, as the host packs
+// them: one copy moves them all), then the index, outputs and descriptor.
+size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_view, size_t *input_end = nullptr)
 {
     Carver c(base);
     const size_t n = (size_t)s.n_hits(), ns = (size_t)s.n_seeds, nt = (size_t)s.n_tracks, nl = (size_t)s.n_layers;
-    v->raw_xyz = c.take<double>(3 * n);
     v->hits = c.take<float4>(n);
+    v->seed_par = c.take<float>(6 * ns);
+    v->seed_cov = c.take<float>(21 * ns);
+    v->seed_hits = c.take<int>((size_t)s.n_seed_layers * ns);
+    v->track_par = c.take<float>(6 * nt);
+    v->track_cov = c.take<float>(21 * nt);
+    v->track_hits = c.take<int>(nl * nt);
+    if (input_end) *input_end = c.off;
     v->binned = c.take<float4>(n);
     v->bin_of = c.take<int>(n);
     v->bin_rank = c.take<int>(n);
-    v->seed_par = c.take<double>(6 * ns);
-    v->seed_cov = c.take<double>(21 * ns);
-    v->seed_hits = c.take<int>((size_t)s.n_seed_layers * ns);
-    v->track_par = c.take<double>(6 * nt);
-    v->track_cov = c.take<double>(21 * nt);
-    v->track_hits = c.take<int>(nl * nt);
     v->out_par = c.take<double>(6 * ns);
     v->out_cov = c.take<double>(21 * ns);
     v->out_hits = c.take<int>(nl * ns);
@@ -195,6 +198,121 @@ bool finite_all(const double *p, size_t n)
         if (!std::isfinite(p[i])) return false;
     return true;
 }
+
+// FP64 -> FP32 with the check that the value is, and stays, finite.
+bool narrow(const double *src, float *dst, size_t n)
+{
+    bool ok = true;
+    for (size_t i = 0; i < n; ++i) {
+        const float f = (float)src[i];
+        dst[i] = f;
+        ok &= std::isfinite(f);
+    }
+    return ok;
+}
+
+// Host threads that pack inputs, started on first use and kept for the life
+// of the process.  A caller posts a job (n tasks, at most `threads` workers
+// including itself), takes tasks itself and waits until every task is done;
+// jobs of concurrent callers share the workers.
+class HostPool {
+  public:
+    static HostPool &get()
+    {
+        static HostPool *pool = new HostPool();   // never destroyed: workers may outlive static destructors
+        return *pool;
+    }
+
+    void run(int n_tasks, int threads, const std::function<void(int)> &f)
+    {
+        Job job;
+        job.f = &f;
+        job.n = n_tasks;
+        job.helpers = std::min(threads, n_tasks) - 1;
+        if (job.helpers > 0 && !workers_.empty()) {
+            std::lock_guard<std::mutex> lk(mu_);
+            jobs_.push_back(&job);
+            cv_.notify_all();
+        }
+        work(job);
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = std::find(jobs_.begin(), jobs_.end(), &job);
+        if (it != jobs_.end()) jobs_.erase(it);
+        done_cv_.wait(lk, [&] { return job.done.load() == job.n && job.active == 0; });
+    }
+
+  private:
+    struct Job {
+        const std::function<void(int)> *f = nullptr;
+        int n = 0;
+        int helpers = 0;                 // workers still allowed to join (under mu_)
+        int active = 0;                  // workers inside the job (under mu_)
+        std::atomic<int> next{0};
+        std::atomic<int> done{0};
+    };
+
+    HostPool()
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const int n = (int)std::min(15u, hw > 1 ? hw - 1 : 0u);
+        for (int i = 0; i < n; ++i) workers_.emplace_back([this] { loop(); });
+        for (auto &t : workers_) t.detach();
+    }
+
+    void work(Job &job)
+    {
+        for (int t = job.next.fetch_add(1); t < job.n; t = job.next.fetch_add(1)) {
+            (*job.f)(t);
+            if (job.done.fetch_add(1) + 1 == job.n) {
+                std::lock_guard<std::mutex> lk(mu_);
+                done_cv_.notify_all();
+            }
+        }
+    }
+
+    void loop()
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            Job *job = nullptr;
+            for (Job *j : jobs_)
+                if (j->helpers > 0 && j->next.load() < j->n) {
+                    job = j;
+                    break;
+                }
+            if (!job) {
+                cv_.wait(lk);
+                continue;
+            }
+            --job->helpers;
+            ++job->active;
+            lk.unlock();
+            work(*job);
+            lk.lock();
+            --job->active;
+            done_cv_.notify_all();
+        }
+    }
+
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Job *> jobs_;
+    std::vector<std::thread> workers_;
+};
+
+// Runs f(task) for task = 0 .. n_tasks-1 on up to `threads` host threads.
+template <class F>
+void run_tasks(int n_tasks, int threads, F f)
+{
+    threads = std::max(1, std::min(threads, n_tasks));
+    if (threads == 1) {
+        for (int t = 0; t < n_tasks; ++t) f(t);
+        return;
+    }
+    const std::function<void(int)> fn = f;
+    HostPool::get().run(n_tasks, threads, fn);
+}
+
 
 void derive_params(mkf_ctx *ctx)
 {
@@ -440,6 +558,21 @@ size_t event_data_bytes(const EventShape &s)
     return carve_data(s, nullptr, &v, nullptr);
 }
 
+int pack_threads(size_t n_values)
+{
+    // a thread per ~100k values of FP64 input, up to 16
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    return (int)std::min<size_t>({(size_t)16, (size_t)hw, 1 + n_values / 100000});
+}
+
+size_t event_input_bytes(const EventShape &s)
+{
+    DevEvent v{};
+    size_t end = 0;
+    carve_data(s, nullptr, &v, nullptr, &end);
+    return end;
+}
+
 size_t event_index_bytes(const EventShape &s, int nb)
 {
     DevEvent v{};
@@ -458,7 +591,9 @@ int seeds_per_item(int G) { return kWave / G; }
 
 // ---------------------------------------------------------------- events
 
-mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape, bool contents)
+// Counts and pointers of an event: its shape.  The values are checked while
+// they are packed (pack_event).
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape)
 {
     const mkf_config &c = ctx->cfg;
     if (!ev) return fail(MKF_E_INVALID, "event is NULL");
@@ -475,49 +610,115 @@ mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *s
         const int n = ev->n_hits[L];
         if (n < 0 || n > kMaxHitsPerLayer) return fail(MKF_E_INVALID, "layer %d: %d hits out of range", L, n);
         if (n > 0 && !ev->hit_xyz[L]) return fail(MKF_E_INVALID, "layer %d: hit_xyz is NULL", L);
-        const double *h = ev->hit_xyz[L];
-        for (int i = 0; contents && i < n; ++i) {
-            const double x = h[3 * i], y = h[3 * i + 1], z = h[3 * i + 2];
-            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z) || !(x * x + y * y > 0))
-                return fail(MKF_E_INVALID, "layer %d hit %d: not finite or on the axis", L, i);
-        }
         s.layer_off[L] = (int)tot;
         tot += n;
         if (tot > (1LL << 30)) return fail(MKF_E_INVALID, "too many hits in one event");
     }
     s.layer_off[c.n_layers] = (int)tot;
-    const int nsl = c.n_seed_layers;
-    if (ev->n_seeds > 0) {
-        if (!ev->seed_par || !ev->seed_cov || !ev->seed_hits) return fail(MKF_E_INVALID, "seed arrays are NULL");
-        if (contents && (!finite_all(ev->seed_par, 6 * (size_t)ev->n_seeds) ||
-                         !finite_all(ev->seed_cov, 21 * (size_t)ev->n_seeds)))
-            return fail(MKF_E_INVALID, "seed state or covariance not finite");
-        for (int i = 0; contents && i < ev->n_seeds; ++i) {
-            const double *p = ev->seed_par + 6 * (size_t)i;
-            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
-                return fail(MKF_E_INVALID, "seed %d: theta outside (0, pi) or position on the axis", i);
-            for (int L = 0; L < nsl; ++L) {
-                const int h = ev->seed_hits[(size_t)i * nsl + L];
-                if (h < -1 || h >= ev->n_hits[L]) return fail(MKF_E_INVALID, "seed %d: hit index out of range", i);
-            }
-        }
-    }
-    if (ev->n_tracks > 0) {
-        if (!ev->track_par || !ev->track_cov || !ev->track_hits) return fail(MKF_E_INVALID, "track arrays are NULL");
-        if (contents && (!finite_all(ev->track_par, 6 * (size_t)ev->n_tracks) ||
-                         !finite_all(ev->track_cov, 21 * (size_t)ev->n_tracks)))
-            return fail(MKF_E_INVALID, "track state or covariance not finite");
-        for (int i = 0; contents && i < ev->n_tracks; ++i) {
-            const double *p = ev->track_par + 6 * (size_t)i;
-            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
-                return fail(MKF_E_INVALID, "track %d: theta outside (0, pi) or position on the axis", i);
-            for (int L = 0; L < c.n_layers; ++L) {
-                const int h = ev->track_hits[(size_t)i * c.n_layers + L];
-                if (h < -1 || h >= ev->n_hits[L]) return fail(MKF_E_INVALID, "track %d: hit index out of range", i);
-            }
-        }
-    }
+    if (ev->n_seeds > 0 && (!ev->seed_par || !ev->seed_cov || !ev->seed_hits))
+        return fail(MKF_E_INVALID, "seed arrays are NULL");
+    if (ev->n_tracks > 0 && (!ev->track_par || !ev->track_cov || !ev->track_hits))
+        return fail(MKF_E_INVALID, "track arrays are NULL");
     *shape = s;
+    return MKF_OK;
+}
+
+// Checks a state (finite, theta in (0, pi), off the axis) and the hit
+// indices of one seed or track; writes its FP32 state and covariance.
+static bool pack_state(const double *par, const double *cov, float *fpar, float *fcov, const int32_t *hits,
+                       int32_t *ohits, int n_hit_layers, const int32_t *n_hits, int *bad_hit)
+{
+    if (!narrow(par, fpar, 6) || !narrow(cov, fcov, 21)) return false;
+    if (!(par[5] > 0 && par[5] < M_PI) || !(par[0] * par[0] + par[1] * par[1] > 0)) return false;
+    for (int L = 0; L < n_hit_layers; ++L) {
+        const int32_t h = hits[L];
+        if (h < -1 || h >= n_hits[L]) {
+            *bad_hit = 1;
+            return false;
+        }
+        ohits[L] = h;
+    }
+    return true;
+}
+
+// Packs an event's inputs into `image` in the device layout of its data
+// block (carve_data) and checks every value on the way: each hit becomes
+// the FP32 form the kernels read (geo: bit 0 disks, bit 1 layers of finite
+// thickness or the 3x3 measurement), computed in FP64; seeds and tracks
+// FP32 states and covariances, finite, theta in (0, pi), hit indices in
+// range.  The layers and the seeds are packed in parallel for large events.
+mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *image, int threads, std::string *why)
+{
+    DevEvent v{};
+    carve_data(sh, image, &v, nullptr);
+    const int nl = sh.n_layers, nsl = sh.n_seed_layers;
+    const int chunk = 4096;
+    const int seed_tasks = (sh.n_seeds + chunk - 1) / chunk, track_tasks = (sh.n_tracks + chunk - 1) / chunk;
+    const int n_tasks = nl + seed_tasks + track_tasks;
+    // first failure of each task: (index, kind), index -1 for none
+    std::vector<int> bad(n_tasks, -1), kind(n_tasks, 0);
+    run_tasks(n_tasks, threads, [&](int t) {
+        if (t < nl) {
+            // a hit as the kernels read it: its direction and second grid
+            // coordinate computed here in FP64 and rounded once
+            const int n = ev->n_hits[t];
+            const double *h = ev->hit_xyz[t];
+            float4 *o = const_cast<float4 *>(v.hits) + sh.layer_off[t];
+            const bool xyz = (geo & 2) != 0, disk = (geo & 1) != 0;
+            for (int i = 0; i < n; ++i) {
+                const double x = h[3 * i], y = h[3 * i + 1], z = h[3 * i + 2];
+                const double r = std::sqrt(x * x + y * y);
+                float4 f;
+                if (xyz) f = make_float4((float)x, (float)y, (float)z, 0.f);
+                else if (disk) f = make_float4((float)(x / r), (float)(y / r), (float)r, (float)z);
+                else f = make_float4((float)(x / r), (float)(y / r), (float)z, (float)r);
+                o[i] = f;
+                if (!(r > 0) || !std::isfinite(f.x) || !std::isfinite(f.y) || !std::isfinite(f.z) ||
+                    !std::isfinite(f.w) || (xyz && !((double)f.x * f.x + (double)f.y * f.y > 0))) {
+                    bad[t] = i;
+                    return;
+                }
+            }
+            return;
+        }
+        const bool seeds = t < nl + seed_tasks;
+        const int i0 = (seeds ? t - nl : t - nl - seed_tasks) * chunk;
+        const int i1 = std::min(i0 + chunk, seeds ? sh.n_seeds : sh.n_tracks);
+        for (int i = i0; i < i1; ++i) {
+            int bad_hit = 0;
+            const bool ok = seeds ? pack_state(ev->seed_par + 6 * (size_t)i, ev->seed_cov + 21 * (size_t)i,
+                                               const_cast<float *>(v.seed_par) + 6 * (size_t)i,
+                                               const_cast<float *>(v.seed_cov) + 21 * (size_t)i,
+                                               ev->seed_hits + (size_t)i * nsl,
+                                               const_cast<int *>(v.seed_hits) + (size_t)i * nsl, nsl, ev->n_hits,
+                                               &bad_hit)
+                                  : pack_state(ev->track_par + 6 * (size_t)i, ev->track_cov + 21 * (size_t)i,
+                                               const_cast<float *>(v.track_par) + 6 * (size_t)i,
+                                               const_cast<float *>(v.track_cov) + 21 * (size_t)i,
+                                               ev->track_hits + (size_t)i * nl,
+                                               const_cast<int *>(v.track_hits) + (size_t)i * nl, nl, ev->n_hits,
+                                               &bad_hit);
+            if (!ok) {
+                bad[t] = i;
+                kind[t] = bad_hit;
+                return;
+            }
+        }
+    });
+    for (int t = 0; t < n_tasks; ++t) {
+        if (bad[t] < 0) continue;
+        char msg[200];
+        if (t < nl) {
+            std::snprintf(msg, sizeof(msg), "layer %d hit %d: not finite (in FP32) or on the axis", t, bad[t]);
+        } else {
+            const char *what = t < nl + seed_tasks ? "seed" : "track";
+            if (kind[t]) std::snprintf(msg, sizeof(msg), "%s %d: hit index out of range", what, bad[t]);
+            else std::snprintf(msg, sizeof(msg), "%s %d: state or covariance not finite (in FP32), theta outside "
+                                                 "(0, pi) or position on the axis", what, bad[t]);
+        }
+        *why = msg;
+        return MKF_E_INVALID;
+    }
     return MKF_OK;
 }
 
@@ -542,30 +743,11 @@ mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap,
     return MKF_OK;
 }
 
-mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s)
+// Copies an event's packed inputs (pack_event) into its device data block.
+mkf_status upload_packed(EventRec *rec, const void *image, hipStream_t s)
 {
-    (void)ctx;
-    const EventShape &sh = rec->shape;
-    DevEvent &v = rec->view;
-    for (int L = 0; L < sh.n_layers; ++L) {
-        const size_t n = (size_t)ev->n_hits[L];
-        if (n)
-            MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.raw_xyz) + 3 * (size_t)sh.layer_off[L], ev->hit_xyz[L],
-                                   3 * n * sizeof(double), hipMemcpyHostToDevice, s));
-    }
-    const size_t ns = (size_t)sh.n_seeds, nt = (size_t)sh.n_tracks;
-    if (ns) {
-        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_par), ev->seed_par, 6 * ns * 8, hipMemcpyHostToDevice, s));
-        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_cov), ev->seed_cov, 21 * ns * 8, hipMemcpyHostToDevice, s));
-        MKF_HIP(hipMemcpyAsync(const_cast<int *>(v.seed_hits), ev->seed_hits, (size_t)sh.n_seed_layers * ns * 4,
-                               hipMemcpyHostToDevice, s));
-    }
-    if (nt) {
-        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.track_par), ev->track_par, 6 * nt * 8, hipMemcpyHostToDevice, s));
-        MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.track_cov), ev->track_cov, 21 * nt * 8, hipMemcpyHostToDevice, s));
-        MKF_HIP(hipMemcpyAsync(const_cast<int *>(v.track_hits), ev->track_hits, (size_t)sh.n_layers * nt * 4,
-                               hipMemcpyHostToDevice, s));
-    }
+    const size_t bytes = event_input_bytes(rec->shape);
+    if (bytes) MKF_HIP(hipMemcpyAsync(rec->data, image, bytes, hipMemcpyHostToDevice, s));
     return MKF_OK;
 }
 
@@ -877,6 +1059,7 @@ void mkf_destroy(mkf_ctx *ctx)
     ctx->events.clear();
     ctx->heap.release(ctx->batch_dev);
     if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+    if (ctx->load_pin) (void)hipHostFree(ctx->load_pin);
     for (auto &t : ctx->timers)
         for (int i = 0; i < Timer::kRing; ++i) {
             if (t.start[i]) (void)hipEventDestroy(t.start[i]);
@@ -909,40 +1092,87 @@ mkf_status mkf_get_tuning(const mkf_ctx *ctx, mkf_tuning *t)
     return MKF_OK;
 }
 
+mkf_status mkf_load_events(mkf_ctx *ctx, const mkf_event *evs, int32_t n, int32_t *handles)
+{
+    if (!ctx || !handles || n < 0 || (n > 0 && !evs)) return fail(MKF_E_INVALID, "NULL argument");
+    if ((long long)n * ctx->cfg.n_layers > 65535)
+        return fail(MKF_E_INVALID, "at most %d events per call", 65535 / ctx->cfg.n_layers);
+    if (n == 0) return MKF_OK;
+    std::vector<EventShape> shapes(n);
+    std::vector<size_t> off(n + 1, 0);
+    size_t values = 0;
+    for (int i = 0; i < n; ++i) {
+        mkf_status st = validate_event(ctx, &evs[i], &shapes[i]);
+        if (st != MKF_OK) return n == 1 ? st : fail(st, "event %d: %s", i, mkf_last_error(ctx));
+        off[i + 1] = off[i] + ((event_input_bytes(shapes[i]) + 255) & ~size_t(255));
+        values += (size_t)shapes[i].n_hits() * 3 + (size_t)(shapes[i].n_seeds + shapes[i].n_tracks) * 27;
+    }
+    // every load ends waiting for the stream, so the staging is free
+    if (ctx->load_pin_bytes < off[n]) {
+        if (ctx->load_pin) (void)hipHostFree(ctx->load_pin);
+        ctx->load_pin = nullptr;
+        ctx->load_pin_bytes = 0;
+        MKF_HIP(hipHostMalloc(&ctx->load_pin, off[n], hipHostMallocDefault));
+        ctx->load_pin_bytes = off[n];
+    }
+    char *pin = static_cast<char *>(ctx->load_pin);
+    std::vector<mkf_status> sts(n, MKF_OK);
+    std::vector<std::string> why(n);
+    const int threads = pack_threads(values);
+    if (n == 1) {
+        sts[0] = pack_event(&evs[0], shapes[0], ctx->params.geo, pin, threads, &why[0]);
+    } else {
+        run_tasks(n, threads,
+                  [&](int i) { sts[i] = pack_event(&evs[i], shapes[i], ctx->params.geo, pin + off[i], 1, &why[i]); });
+    }
+    for (int i = 0; i < n; ++i)
+        if (sts[i] != MKF_OK) return n == 1 ? fail(sts[i], "%s", why[i].c_str())
+                                            : fail(sts[i], "event %d: %s", i, why[i].c_str());
+    std::vector<std::unique_ptr<EventRec>> recs(n);
+    auto undo = [&](mkf_status st) {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto &r : recs)
+            if (r) destroy_event(ctx, r.get());
+        return st;
+    };
+    hipStream_t s = ctx->stream;
+    mkf_status st;
+    for (int i = 0; i < n; ++i) {
+        bool rebuilt = false;
+        if ((st = create_event(ctx, shapes[i], &ctx->heap, &recs[i])) != MKF_OK ||
+            (st = upload_packed(recs[i].get(), pin + off[i], s)) != MKF_OK ||
+            (st = ensure_index(ctx, recs[i].get(), &rebuilt, s)) != MKF_OK)
+            return undo(st);
+        const hipError_t e = hipMemcpyAsync(recs[i]->dev_view, &recs[i]->view, sizeof(DevEvent),
+                                            hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return undo(fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(e)));
+    }
+    if ((st = ensure_batch_scratch(ctx, n)) != MKF_OK) return undo(st);
+    std::vector<EventRec *> raw(n);
+    for (int i = 0; i < n; ++i) raw[i] = recs[i].get();
+    BatchArgs args{};
+    if ((st = stage_batch(ctx, raw, ctx->batch_dev, ctx->batch_host, seeds_per_item(ctx->tuning.lanes_per_seed),
+                          &args, s)) != MKF_OK)
+        return undo(st);
+    hipError_t e = launch_batch_zero(ctx->params, args, true, false, s);
+    if (e == hipSuccess) e = launch_index(ctx->params, args, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        note_device_error(e);
+        return undo(fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(e)));
+    }
+    for (int i = 0; i < n; ++i) {
+        const int32_t h = ctx->next_handle++;
+        ctx->events[h] = std::move(recs[i]);
+        handles[i] = h;
+    }
+    return MKF_OK;
+}
+
 mkf_status mkf_load_event(mkf_ctx *ctx, const mkf_event *ev, int32_t *handle)
 {
-    if (!ctx || !handle) return fail(MKF_E_INVALID, "NULL argument");
-    EventShape shape;
-    mkf_status st = validate_event(ctx, ev, &shape);
-    if (st != MKF_OK) return st;
-    std::unique_ptr<EventRec> rec;
-    if ((st = create_event(ctx, shape, &ctx->heap, &rec)) != MKF_OK) return st;
-    bool rebuilt = false;
-    if ((st = upload_event(ctx, rec.get(), ev, ctx->stream)) != MKF_OK ||
-        (st = ensure_index(ctx, rec.get(), &rebuilt, ctx->stream)) != MKF_OK ||
-        (st = upload_view(rec.get(), ctx->stream)) != MKF_OK ||
-        (st = ensure_batch_scratch(ctx, 1)) != MKF_OK) {
-        destroy_event(ctx, rec.get());
-        return st;
-    }
-    BatchArgs args{};
-    std::vector<EventRec *> one{rec.get()};
-    if ((st = stage_batch(ctx, one, ctx->batch_dev, ctx->batch_host, seeds_per_item(ctx->tuning.lanes_per_seed),
-                          &args, ctx->stream)) != MKF_OK) {
-        destroy_event(ctx, rec.get());
-        return st;
-    }
-    hipError_t e = launch_batch_zero(ctx->params, args, true, false, ctx->stream);
-    if (e == hipSuccess) e = launch_index(ctx->params, args, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) {
-        destroy_event(ctx, rec.get());
-        return fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(e));
-    }
-    const int32_t h = ctx->next_handle++;
-    ctx->events[h] = std::move(rec);
-    *handle = h;
-    return MKF_OK;
+    if (!ctx || !handle || !ev) return fail(MKF_E_INVALID, "NULL argument");
+    return mkf_load_events(ctx, ev, 1, handle);
 }
 
 mkf_status mkf_unload_event(mkf_ctx *ctx, int32_t handle)
@@ -1362,59 +1592,68 @@ mkf_status mkf_fit(mkf_ctx *ctx, int32_t handle, int32_t n_tracks, const double 
     if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
     mkf_status st = check_tracks(out, n_tracks, "fit");
     if (st != MKF_OK) return st;
-    // validate the tracks against the event's hits
-    std::vector<int32_t> nh(rec->shape.n_layers);
-    for (int L = 0; L < rec->shape.n_layers; ++L) nh[L] = rec->shape.layer_off[L + 1] - rec->shape.layer_off[L];
     if (n_tracks < 0) return fail(MKF_E_INVALID, "negative track count");
-    if (n_tracks > 0) {
-        if (!init_par || !init_cov || !track_hits) return fail(MKF_E_INVALID, "track arrays are NULL");
-        if (!finite_all(init_par, 6 * (size_t)n_tracks) || !finite_all(init_cov, 21 * (size_t)n_tracks))
-            return fail(MKF_E_INVALID, "track state or covariance not finite");
-        for (int i = 0; i < n_tracks; ++i) {
-            const double *p = init_par + 6 * (size_t)i;
-            if (!(p[5] > 0 && p[5] < M_PI) || !(p[0] * p[0] + p[1] * p[1] > 0))
-                return fail(MKF_E_INVALID, "track %d: theta outside (0, pi) or position on the axis", i);
-            for (int L = 0; L < rec->shape.n_layers; ++L) {
-                const int h = track_hits[(size_t)i * rec->shape.n_layers + L];
-                if (h < -1 || h >= nh[L]) return fail(MKF_E_INVALID, "track %d: hit index out of range", i);
-            }
-        }
-    }
+    if (n_tracks > 0 && (!init_par || !init_cov || !track_hits)) return fail(MKF_E_INVALID, "track arrays are NULL");
     if (n_tracks == 0) return MKF_OK;
-    // a temporary event view: the loaded event's hits with these tracks
+    // a temporary event view: the loaded event's hits with these tracks, whose
+    // inputs are checked and narrowed to FP32 in the load staging and copied
+    // in one piece
     EventShape ts = rec->shape;
     ts.n_seeds = 0;
     ts.n_tracks = n_tracks;
     const size_t nt = (size_t)n_tracks, nl = (size_t)ts.n_layers;
-    const size_t bytes = nt * (48 + 168 + 4 * nl + 48 + 168 + 8 + 4 + 4) + 8 * 256 + sizeof(DevEvent);
-    char *buf = static_cast<char *>(ctx->heap.alloc(bytes));
-    if (!buf) return fail(MKF_E_NOMEM, "fit buffers: %zu bytes", bytes);
+    auto layout = [&](char *base, DevEvent *v) {
+        size_t o = 0;
+        auto take = [&](size_t b) {
+            char *p = base + o;
+            o = (o + b + 255) & ~size_t(255);
+            return p;
+        };
+        v->track_par = reinterpret_cast<float *>(take(24 * nt));
+        v->track_cov = reinterpret_cast<float *>(take(84 * nt));
+        v->track_hits = reinterpret_cast<int *>(take(4 * nl * nt));
+        const size_t inputs = o;
+        v->fit_par = reinterpret_cast<double *>(take(48 * nt));
+        v->fit_cov = reinterpret_cast<double *>(take(168 * nt));
+        v->fit_chi2 = reinterpret_cast<double *>(take(8 * nt));
+        v->fit_nupd = reinterpret_cast<int *>(take(4 * nt));
+        v->fit_status = reinterpret_cast<int *>(take(4 * nt));
+        return std::make_pair(inputs, o);
+    };
+    DevEvent hv{};
+    const auto sizes = layout(nullptr, &hv);
+    if (ctx->load_pin_bytes < sizes.first) {
+        if (ctx->load_pin) (void)hipHostFree(ctx->load_pin);
+        ctx->load_pin = nullptr;
+        ctx->load_pin_bytes = 0;
+        MKF_HIP(hipHostMalloc(&ctx->load_pin, sizes.first, hipHostMallocDefault));
+        ctx->load_pin_bytes = sizes.first;
+    }
+    layout(static_cast<char *>(ctx->load_pin), &hv);
+    std::vector<int32_t> nh(nl);
+    for (size_t L = 0; L < nl; ++L) nh[L] = rec->shape.layer_off[L + 1] - rec->shape.layer_off[L];
+    for (int i = 0; i < n_tracks; ++i) {
+        int bad_hit = 0;
+        if (!pack_state(init_par + 6 * (size_t)i, init_cov + 21 * (size_t)i, const_cast<float *>(hv.track_par) + 6 * (size_t)i,
+                        const_cast<float *>(hv.track_cov) + 21 * (size_t)i, track_hits + (size_t)i * nl,
+                        const_cast<int *>(hv.track_hits) + (size_t)i * nl, (int)nl, nh.data(), &bad_hit))
+            return fail(MKF_E_INVALID, bad_hit ? "track %d: hit index out of range"
+                                               : "track %d: state or covariance not finite (in FP32), theta "
+                                                 "outside (0, pi) or position on the axis", i);
+    }
+    char *buf = static_cast<char *>(ctx->heap.alloc(sizes.second + sizeof(DevEvent) + 256));
+    if (!buf) return fail(MKF_E_NOMEM, "fit buffers: %zu bytes", sizes.second);
     DevEvent v = rec->view;
     v.n_seeds = 0;
     v.n_tracks = n_tracks;
-    size_t off = 0;
-    auto take = [&](size_t b) {
-        char *p = buf + off;
-        off = (off + b + 255) & ~size_t(255);
-        return p;
-    };
-    v.track_par = reinterpret_cast<double *>(take(48 * nt));
-    v.track_cov = reinterpret_cast<double *>(take(168 * nt));
-    v.track_hits = reinterpret_cast<int *>(take(4 * nl * nt));
-    v.fit_par = reinterpret_cast<double *>(take(48 * nt));
-    v.fit_cov = reinterpret_cast<double *>(take(168 * nt));
-    v.fit_chi2 = reinterpret_cast<double *>(take(8 * nt));
-    v.fit_nupd = reinterpret_cast<int *>(take(4 * nt));
-    v.fit_status = reinterpret_cast<int *>(take(4 * nt));
+    layout(buf, &v);
     auto cleanup = [&](mkf_status s) {
         (void)hipStreamSynchronize(ctx->stream);
         ctx->heap.release(buf);
         return s;
     };
     hipStream_t s = ctx->stream;
-    if (hipMemcpyAsync(const_cast<double *>(v.track_par), init_par, 48 * nt, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(const_cast<double *>(v.track_cov), init_cov, 168 * nt, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(const_cast<int *>(v.track_hits), track_hits, 4 * nl * nt, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(buf, ctx->load_pin, sizes.first, hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(MKF_E_DEVICE, "fit upload failed"));
     if ((st = ensure_batch_scratch(ctx, 1)) != MKF_OK) return cleanup(st);
     EventRec tmp;

@@ -73,6 +73,7 @@ struct EventShape {
 };
 
 size_t event_data_bytes(const EventShape &s);
+size_t event_input_bytes(const EventShape &s);   // the packed inputs at the start of the data block
 size_t event_index_bytes(const EventShape &s, int n_bins);
 
 // One loaded event.
@@ -148,6 +149,8 @@ struct mkf_ctx {
     hipEvent_t stage_done = nullptr;    // last copy out of batch_host
     bool stage_pending = false;
     std::vector<char> staged_image;     // what batch_dev holds (empty: unknown)
+    void *load_pin = nullptr;           // pinned staging of the packed inputs of loads and fits
+    size_t load_pin_bytes = 0;
     std::vector<std::unique_ptr<mkf::BatchGraph>> graphs;
     mkf::Timer timers[3];
     std::unique_ptr<mkf::Server, mkf::ServerDeleter> server;
@@ -156,10 +159,15 @@ struct mkf_ctx {
 namespace mkf {
 
 // context-level helpers used by the ABI and the scheduler
-// contents = false checks the counts and pointers only (the shape), not the values
-mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape, bool contents = true);
+// the counts and pointers of an event (its shape); values are checked by pack_event
+mkf_status validate_event(const mkf_ctx *ctx, const mkf_event *ev, EventShape *shape);
+// the event's inputs, checked and narrowed to FP32, in its device layout
+// (event_input_bytes of them)
+mkf_status pack_event(const mkf_event *ev, const EventShape &shape, int geo, void *image, int threads,
+                      std::string *why);
+int pack_threads(size_t n_values);   // host threads worth using for packing that many values
 mkf_status create_event(mkf_ctx *ctx, const EventShape &shape, DeviceHeap *heap, std::unique_ptr<EventRec> *out);
-mkf_status upload_event(mkf_ctx *ctx, EventRec *rec, const mkf_event *ev, hipStream_t s);
+mkf_status upload_packed(EventRec *rec, const void *image, hipStream_t s);
 void destroy_event(mkf_ctx *ctx, EventRec *rec);
 mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t s);
 mkf_status ensure_index_grid(mkf_ctx *ctx, EventRec *rec, int bins_phi, int bins_z, bool *rebuilt, hipStream_t s);

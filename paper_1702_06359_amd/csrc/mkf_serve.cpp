@@ -80,28 +80,6 @@ struct Ticket {
     std::unique_ptr<EventRec> rec;
 };
 
-// byte offsets of one event inside its pinned input staging
-struct InLayout {
-    size_t hits, seed_par, seed_cov, seed_hits, total;
-};
-
-InLayout in_layout(const EventShape &s)
-{
-    InLayout l{};
-    size_t off = 0;
-    auto take = [&](size_t b) {
-        const size_t o = off;
-        off = round256(off + b);
-        return o;
-    };
-    l.hits = take(24 * (size_t)s.n_hits());
-    l.seed_par = take(48 * (size_t)s.n_seeds);
-    l.seed_cov = take(168 * (size_t)s.n_seeds);
-    l.seed_hits = take(4 * (size_t)s.n_seed_layers * s.n_seeds);
-    l.total = off;
-    return l;
-}
-
 struct OutLayout {
     size_t par, cov, hits, nhits, nholes, chi2, status, total;
 };
@@ -231,21 +209,8 @@ struct Server {
         hipStream_t s = streams[si];
         std::vector<EventRec *> recs;
         for (Ticket *t : batch) {
-            const InLayout il = in_layout(t->shape);
-            const char *in = static_cast<const char *>(t->in_pin);
-            DevEvent &v = t->rec->view;
-            if (t->shape.n_hits())
-                MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.raw_xyz), in + il.hits, 24 * (size_t)t->shape.n_hits(),
-                                       hipMemcpyHostToDevice, s));
-            const size_t ns = (size_t)t->shape.n_seeds;
-            if (ns) {
-                MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_par), in + il.seed_par, 48 * ns,
-                                       hipMemcpyHostToDevice, s));
-                MKF_HIP(hipMemcpyAsync(const_cast<double *>(v.seed_cov), in + il.seed_cov, 168 * ns,
-                                       hipMemcpyHostToDevice, s));
-                MKF_HIP(hipMemcpyAsync(const_cast<int *>(v.seed_hits), in + il.seed_hits,
-                                       4 * (size_t)t->shape.n_seed_layers * ns, hipMemcpyHostToDevice, s));
-            }
+            mkf_status st = upload_packed(t->rec.get(), t->in_pin, s);   // hits and seeds, FP32, one copy
+            if (st != MKF_OK) return st;
             recs.push_back(t->rec.get());
         }
         BatchArgs args{};
@@ -440,7 +405,7 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
     // the shape first (cheap), so that a submit refused for want of a slot
     // or budget costs little; the values once admitted
     EventShape shape;
-    mkf_status st = validate_event(ctx, ev, &shape, false);
+    mkf_status st = validate_event(ctx, ev, &shape);
     if (st != MKF_OK) return st;
     if (out->n != shape.n_seeds) return fail(MKF_E_INVALID, "output has %d rows, need %d", out->n, shape.n_seeds);
     shape.n_tracks = 0;   // serving builds; tracks for fitting are not staged
@@ -467,16 +432,8 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
         sv->reserved -= need;
         sv->cv.notify_all();
     };
-    {
-        EventShape full;
-        if ((st = validate_event(ctx, ev, &full)) != MKF_OK) {
-            unreserve();
-            return st;
-        }
-    }
-    const InLayout il = in_layout(shape);
     const OutLayout ol = out_layout(shape);
-    t->in_pin = sv->pinned.get(il.total, &t->in_cls);
+    t->in_pin = sv->pinned.get(event_input_bytes(shape), &t->in_cls);
     t->out_pin = sv->pinned.get(ol.total, &t->out_cls);
     if (!t->in_pin || !t->out_pin) {
         sv->pinned.put(t->in_pin, t->in_cls);
@@ -484,14 +441,16 @@ mkf_status mkf_serve_submit(mkf_ctx *ctx, const mkf_event *ev, mkf_tracks *out, 
         unreserve();
         return fail(MKF_E_NOMEM, "pinned staging");
     }
-    char *in = static_cast<char *>(t->in_pin);
-    for (int L = 0; L < shape.n_layers; ++L)
-        std::memcpy(in + il.hits + 24 * (size_t)shape.layer_off[L], ev->hit_xyz[L], 24 * (size_t)ev->n_hits[L]);
-    const size_t ns = (size_t)shape.n_seeds;
-    if (ns) {
-        std::memcpy(in + il.seed_par, ev->seed_par, 48 * ns);
-        std::memcpy(in + il.seed_cov, ev->seed_cov, 168 * ns);
-        std::memcpy(in + il.seed_hits, ev->seed_hits, 4 * (size_t)shape.n_seed_layers * ns);
+    // the values are checked while they are narrowed to FP32 into the staging
+    mkf_event seeds_only = *ev;
+    seeds_only.n_tracks = 0;   // serving builds; tracks for fitting are not staged
+    std::string why;
+    const size_t values = (size_t)shape.n_hits() * 3 + (size_t)shape.n_seeds * 27;
+    if ((st = pack_event(&seeds_only, shape, sv->params.geo, t->in_pin, pack_threads(values), &why)) != MKF_OK) {
+        sv->pinned.put(t->in_pin, t->in_cls);
+        sv->pinned.put(t->out_pin, t->out_cls);
+        unreserve();
+        return fail(st, "%s", why.c_str());
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     t->id = sv->next_id++;
