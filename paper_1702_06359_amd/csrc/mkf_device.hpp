@@ -74,6 +74,13 @@ __device__ __forceinline__ void store_global(float4 *p, float4 v)
     *(gptr)p = v4{v.x, v.y, v.z, v.w};
 }
 
+__device__ __forceinline__ void store_global(int4 *p, int4 v)
+{
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) v4 *gptr;
+    *(gptr)p = v4{v.x, v.y, v.z, v.w};
+}
+
 __device__ __forceinline__ float4 load_global(const float4 *p)
 {
     typedef float v4 __attribute__((ext_vector_type(4)));

@@ -66,7 +66,8 @@ struct DevEvent {
     int *bin_of;                         // [n_hits] bin of each caller-order hit
     int *bin_rank;                       // [n_hits] position of the hit inside its bin
     int *bin_count;                      // [n_layers][n_bins] counts (zero between index builds)
-    int *bin_off;                        // [n_layers][n_bins + 1] absolute index into `binned`
+    int *bin_off;                        // [n_layers][bin_off_stride(n_bins)]: n_bins + 1 absolute indices into
+                                         // `binned` per layer
     const float *seed_par;               // [n_seeds][6]
     const float *seed_cov;               // [n_seeds][21]
     const int *seed_hits;                // [n_seeds][n_seed_layers]
@@ -129,6 +130,10 @@ struct BatchArgs {
     int seeds_per_item;
     int max_layer_hits;          // largest layer of any event (index launch shape)
 };
+
+// Ints per layer in the bin-offset array: its n_bins + 1 offsets, padded to
+// a multiple of four so that every layer's row starts 16-byte aligned.
+__host__ __device__ constexpr int bin_off_stride(int n_bins) { return (n_bins + 4) & ~3; }
 
 // Batch descriptors of the no-allocation builder: a fixed device array per
 // GPU (mkf_kernels.hip), as laid out for up to kNoAllocMaxEvents events.

@@ -167,7 +167,7 @@ size_t carve_index(const EventShape &s, int nb, void *base, DevEvent *v)
 {
     Carver c(base);
     v->bin_count = c.take<int>((size_t)s.n_layers * nb);
-    v->bin_off = c.take<int>((size_t)s.n_layers * (nb + 1));
+    v->bin_off = c.take<int>((size_t)s.n_layers * bin_off_stride(nb));
     return c.off;
 }
 
@@ -1499,8 +1499,9 @@ mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t 
     std::vector<int32_t> off(bin_off ? nb + 1 : 0);
     std::vector<float4> binned(order ? n : 0);
     hipStream_t s = ctx->stream;
-    if (bin_off) MKF_HIP(hipMemcpyAsync(off.data(), v.bin_off + (size_t)layer * (nb + 1), 4 * (size_t)(nb + 1),
-                                        hipMemcpyDeviceToHost, s));
+    if (bin_off)
+        MKF_HIP(hipMemcpyAsync(off.data(), v.bin_off + (size_t)layer * bin_off_stride(nb), 4 * (size_t)(nb + 1),
+                               hipMemcpyDeviceToHost, s));
     if (bin_of && n) MKF_HIP(hipMemcpyAsync(bin_of, v.bin_of + h0, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
     if (order && n) MKF_HIP(hipMemcpyAsync(binned.data(), v.binned + h0, sizeof(float4) * (size_t)n,
                                            hipMemcpyDeviceToHost, s));
