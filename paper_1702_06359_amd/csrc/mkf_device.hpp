@@ -838,18 +838,25 @@ __device__ __forceinline__ float kf_update_3d(float (&p)[6], float (&c)[21], Tri
 }
 
 // ---- beam ordering ---------------------------------------------------------
-// A child's rank key packs, most significant first: (31 - n_hits), the
-// candidate's summed chi2 (non-negative float bits order like the floats),
-// the parent's rank and the hit index (kHoleId for hole and stopped entries).
-// Smaller key = better; every key of a seed is distinct.
-__device__ __forceinline__ unsigned long long beam_key(int n_hits, float chi2, int parent, unsigned hit)
+// A child's rank key (smaller = better; distinct within a seed), most
+// significant first: 31 - n_hits (5 bits), the candidate's summed chi2 to
+// 2^-15 relative (its float bits 31..8; non-negative float bits order like
+// the floats), the parent's rank (3 bits), the remaining chi2 bits 7..0, the
+// hit index (24 bits; kHoleId for hole and stopped entries).  Children of
+// different parents whose chi2 agree to 2^-15 so rank by parent, and the
+// children of one parent by exact chi2, then hit index.
+__device__ __forceinline__ unsigned long long child_key(int n_hits, unsigned chi2_bits, int parent, unsigned hit)
 {
-    return ((unsigned long long)(31 - n_hits) << 59) | ((unsigned long long)__float_as_uint(chi2) << 27) |
-           ((unsigned long long)parent << 24) | (unsigned long long)(hit & kHoleId);
+    return ((unsigned long long)(31 - n_hits) << 59) | ((unsigned long long)(chi2_bits >> 8) << 35) |
+           ((unsigned long long)parent << 32) | ((unsigned long long)(chi2_bits & 0xFFu) << 24) |
+           (unsigned long long)(hit & kHoleId);
 }
 __device__ __forceinline__ int key_nhits(unsigned long long k) { return 31 - (int)(k >> 59); }
-__device__ __forceinline__ float key_chi2(unsigned long long k) { return __uint_as_float((unsigned)(k >> 27)); }
-__device__ __forceinline__ int key_parent(unsigned long long k) { return (int)((k >> 24) & 7); }
+__device__ __forceinline__ float key_chi2(unsigned long long k)
+{
+    return __uint_as_float((((unsigned)(k >> 35) & 0xFFFFFFu) << 8) | ((unsigned)(k >> 24) & 0xFFu));
+}
+__device__ __forceinline__ int key_parent(unsigned long long k) { return (int)((k >> 32) & 7); }
 __device__ __forceinline__ unsigned key_hit(unsigned long long k) { return (unsigned)(k & kHoleId); }
 
 }  // namespace mkf

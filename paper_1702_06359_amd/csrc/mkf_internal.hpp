@@ -108,8 +108,7 @@ struct DevEvent {
     float *st_trig;                      // [4][slots] sin, cos of phi and theta
     float *st_chi2;                      // [slots]
     int *st_meta;                        // [slots]
-    int *st_hist_hit;                    // [n_layers][slots]
-    unsigned char *st_hist_par;          // [n_layers][slots]
+    int *st_hist;                        // [n_layers][slots] parent rank << 24 | hit (0xFFFFFF: hole)
     int st_slots;
     int pad;
 };

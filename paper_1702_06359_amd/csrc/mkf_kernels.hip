@@ -43,56 +43,6 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src)
-{
-    const unsigned lo = __shfl((unsigned)v, src);
-    const unsigned hi = __shfl((unsigned)(v >> 32), src);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-// Minimum of v over the G lanes of each seed group.  Power-of-two groups
-// use a butterfly; other sizes take the minimum over cyclic windows of
-// 2, 4 and 8 lanes, which covers any G <= 8.
-template <int G>
-__device__ __forceinline__ unsigned long long group_min(unsigned long long v, int gbase, int slot)
-{
-    if constexpr ((G & (G - 1)) == 0) {
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const unsigned long long t = shfl_xor_u64(v, o);
-            v = t < v ? t : v;
-        }
-    } else {
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const int s2 = slot + o >= G ? slot + o - G : slot + o;
-            const unsigned long long t = shfl_u64(v, gbase + s2);
-            v = t < v ? t : v;
-        }
-    }
-    return v;
-}
-
-template <int G>
-__device__ __forceinline__ unsigned group_min32(unsigned v, int gbase, int slot)
-{
-    if constexpr ((G & (G - 1)) == 0) {
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const unsigned t = (unsigned)__shfl_xor((int)v, o);
-            v = t < v ? t : v;
-        }
-    } else {
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const int s2 = slot + o >= G ? slot + o - G : slot + o;
-            const unsigned t = (unsigned)__shfl((int)v, gbase + s2);
-            v = t < v ? t : v;
-        }
-    }
-    return v;
-}
-
 __global__ void k_fill_i32(int *__restrict__ p, int v, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -612,52 +562,44 @@ struct Lane {
     int stopped;
 };
 
-struct Hist {          // per-layer record of every kept candidate: (hit, parent rank)
-    int *hit;
-    unsigned char *par;
+// Per-layer record of every kept candidate: parent rank << 24 | hit index
+// (kHoleId for a hole).
+struct Hist {
+    int *rec;
     int stride;        // elements between layers
     __device__ void put(int L, int lane, int h, int parent) const
     {
-        hit[L * stride + lane] = h;
-        par[L * stride + lane] = (unsigned char)parent;
+        rec[L * stride + lane] = (parent << 24) | (h & (int)kHoleId);
     }
+    __device__ int hit(int L, int lane) const
+    {
+        const int v = rec[L * stride + lane] & (int)kHoleId;
+        return v == (int)kHoleId ? -1 : v;
+    }
+    __device__ int parent(int L, int lane) const { return (int)((unsigned)rec[L * stride + lane] >> 24); }
 };
 
 struct Count {
     unsigned long long prop = 0, chi2 = 0, acc = 0, upd = 0, scan = 0;
 };
 
-// Best-K list of one candidate's hit children, ascending 64-bit keys
-// (accumulated chi2 bits << 32 | hit id; chi2 >= 0 so its bits order as the
-// value, and equal chi2 falls back to the hit id); empty slots hold ~0.
-template <int K>
-__device__ __forceinline__ void list_insert(unsigned long long (&lk)[K], unsigned long long key)
-{
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const unsigned long long t = lk[i];
-        const bool less = key < t;
-        lk[i] = less ? key : t;
-        key = less ? t : key;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Wavefront-cooperative hit search.
+// Wavefront-cooperative hit search and beam selection.
 //
 // Each lane owns one candidate whose window is a few (z row, phi segment)
 // runs of the binned hit array.  The non-empty runs of all lanes are listed
 // in LDS with running offsets; the (candidate, hit) pairs they define are then
 // evaluated 64 at a time, one pair per lane whatever candidate it belongs to,
-// and the accepted ones are linked into per-candidate lists that each owner
-// finally merges into its own best-K list.  A wavefront's work so follows the
-// total number of hits in its windows instead of its largest window, and no
-// lane idles through another lane's chi2 or list insertion.
+// and the accepted ones are appended to an LDS list.  A wavefront's work so
+// follows the total number of hits in its windows instead of its largest
+// window, and no lane idles through another lane's chi2.  The next beam of
+// every seed is then chosen straight from that list (plus each candidate's
+// hole or stop entry) by rounds of LDS atomic minima over the child keys,
+// one rank per round; when the list fills up first, it is cut down to the
+// entries that can still make a beam.
 
-constexpr int kRuns = 128;   // run records held before their pairs are evaluated
-constexpr int kAcc = 128;    // accepted entries held before the owners merge them
-constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
-
+constexpr int kRuns = 128;         // run records held before their pairs are evaluated
+constexpr int kAcc = 2 * kWave;    // accepted entries held (two per lane) before the list is cut down
 
 // kOwn rows of owner data per lane: 3 on thin layers ({x, y, z or r, chi2},
 // {Cxx, Cxy, Cyy, Cxz}, {Cyz, Czz, du, dz}); 8 on thick ones, where every
@@ -668,10 +610,11 @@ constexpr int kEnd = 0xFF;   // end of a per-candidate list (links are one byte)
 template <int kOwn>
 struct SearchLdsT {
     float4 own[kOwn][kWave];
-    int4 run[kRuns];         // {first binned index, first pair index, owner lane, -}
-    int2 acc[kAcc];          // {accumulated chi2 bits, hit id << 8 | next entry}
-    int head[kWave];         // first accepted entry of each owner
-    int mark[kWave];         // run starting at each pair slot of the current round
+    int4 run[kRuns];              // {first binned index, first pair index, owner lane, -}
+    int2 acc[kAcc];               // {accumulated chi2 bits, hit id << 6 | owner lane}
+    unsigned long long best[kWave + 1];   // per seed group: the best child key of the current round; + a sink
+    int tally[kWave];             // per owner: child hit count << 16 | accepted entries
+    int mark[kWave];              // run starting at each pair slot of the current round
 };
 template <int kGeo>
 using SearchLds = SearchLdsT<geo_xyz(kGeo) ? 8 : 3>;
@@ -709,32 +652,114 @@ __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
     return v - x;
 }
 
-template <int K, bool kStats, int kGeo>
+template <int G, bool kStats, int kGeo>
 struct WaveSearch {
     static constexpr bool kDisk = geo_disk(kGeo);
     static constexpr bool kXyz = geo_xyz(kGeo);
+    static_assert(kAcc == 2 * kWave, "two accepted entries per lane");
     SearchLds<kGeo> &W;
     const float4 *bh;
     const Params &P;
     const int lane;
-    unsigned long long (&lk)[K];
     Count &cnt;
-    int n_runs = 0, n_pairs = 0, n_acc = 0, n_mine = 0;
+    int n_runs = 0, n_pairs = 0, n_acc = 0;
 
-    // owners merge their accepted entries into their best-K lists
-    __device__ __forceinline__ void merge()
+    // Child key of accepted entry v and the seed group of its owner (the
+    // owner's child hit count is the high half of its tally).
+    __device__ __forceinline__ unsigned long long entry_key(const int2 v, int &grp) const
+    {
+        const int o = v.y & (kWave - 1);
+        grp = o / G;
+        return child_key(W.tally[o] >> 16, (unsigned)v.x, o - grp * G, (unsigned)v.y >> 6);
+    }
+
+    // Up to max_cands rounds over this lane's items (two adjacent slots of
+    // the accepted list and one more key): round r takes the minimum key of
+    // every seed group with LDS atomics, marks the item that holds it as
+    // taken, and hands it to the group's lane of rank r (`mine`).  The items
+    // of a group are distinct, so each round takes exactly one per group that
+    // has any.  Items out of the round read a sink entry, so that the reads
+    // of a round are issued together outside any branch; of two items of one
+    // group in a lane only the smaller enters the round (the slots hold runs
+    // of one candidate's pairs, so this halves the lanes that meet at one
+    // address).  Program order suffices between the reads and writes of one
+    // round: a wavefront's LDS instructions execute in order.
+    __device__ __forceinline__ void rounds(const unsigned long long (&key)[3], const int (&grp)[3], bool (&live)[3],
+                                           bool (&taken)[3], unsigned long long &mine)
+    {
+        const int my_grp = lane / G, my_rank = lane - my_grp * G;
+        mine = ~0ull;
+        for (int r = 0; r < P.max_cands; ++r) {
+            if (__ballot(live[0] | live[1] | live[2]) == 0) break;
+            // of slots 0 and 1 in one group, the larger waits
+            const bool both = live[0] & live[1] & (grp[0] == grp[1]);
+            const bool in0 = live[0] & !(both & (key[1] < key[0]));
+            const bool in1 = live[1] & !(both & (key[0] < key[1]));
+            const int a0 = in0 ? grp[0] : kWave, a1 = in1 ? grp[1] : kWave, a2 = live[2] ? grp[2] : kWave;
+            if (in0) atomicMin(&W.best[a0], key[0]);
+            if (in1) atomicMin(&W.best[a1], key[1]);
+            if (live[2]) atomicMin(&W.best[a2], key[2]);
+            wave_lds_sync();
+            const unsigned long long b0 = W.best[a0], b1 = W.best[a1], b2 = W.best[a2], bm = W.best[my_grp];
+            const bool w0 = in0 & (b0 == key[0]), w1 = in1 & (b1 == key[1]), w2 = live[2] & (b2 == key[2]);
+            taken[0] |= w0;
+            taken[1] |= w1;
+            taken[2] |= w2;
+            live[0] &= !w0;
+            live[1] &= !w1;
+            live[2] &= !w2;
+            mine = my_rank == r ? bm : mine;
+            wave_lds_sync();
+            if (my_rank == r) W.best[my_grp] = ~0ull;
+            wave_lds_sync();
+        }
+    }
+
+    // The accepted list is full: keep only its entries that are among the
+    // max_cands best of their seed group so far (any other can no longer
+    // make the beam), compacted to the front.
+    __device__ __forceinline__ void prune()
     {
         wave_lds_sync();
-        int e = W.head[lane];
-        while (e != kEnd) {
-            const int2 v = W.acc[e];
-            list_insert<K>(lk, ((unsigned long long)(unsigned)v.x << 32) | ((unsigned)v.y >> 8));
-            ++n_mine;
-            e = v.y & kEnd;
+        int2 v[2];
+        unsigned long long key[3] = {~0ull, ~0ull, ~0ull};
+        int grp[3] = {0, 0, 0};
+        bool live[3] = {false, false, false}, taken[3] = {false, false, false};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int e = 2 * lane + t;
+            live[t] = e < n_acc;
+            v[t] = live[t] ? W.acc[e] : make_int2(0, 0);
+            if (live[t]) key[t] = entry_key(v[t], grp[t]);
         }
-        W.head[lane] = kEnd;
-        n_acc = 0;
+        unsigned long long mine;
+        rounds(key, grp, live, taken, mine);
+        const unsigned long long m0 = __ballot(taken[0]), m1 = __ballot(taken[1]);
+        if (taken[0]) W.acc[lanes_below(m0)] = v[0];
+        if (taken[1]) W.acc[__popcll(m0) + lanes_below(m1)] = v[1];
+        n_acc = __popcll(m0) + __popcll(m1);
         wave_lds_sync();
+    }
+
+    // The next beam: the max_cands best children of every seed group among
+    // its accepted entries and its candidates' own entries (`own_key`, ~0
+    // for none; a hole or a stopped candidate).  Returns this lane's new
+    // entry by its rank in the group (~0: none).
+    __device__ __forceinline__ unsigned long long select(unsigned long long own_key)
+    {
+        wave_lds_sync();
+        unsigned long long key[3] = {~0ull, ~0ull, own_key};
+        int grp[3] = {0, 0, lane / G};
+        bool live[3] = {false, false, own_key != ~0ull}, taken[3] = {false, false, false};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int e = 2 * lane + t;
+            live[t] = e < n_acc;
+            if (live[t]) key[t] = entry_key(W.acc[e], grp[t]);
+        }
+        unsigned long long mine;
+        rounds(key, grp, live, taken, mine);
+        return mine;
     }
 
     // Pair slot t0 + lane of a round: its owner and hit (the load is left in
@@ -837,11 +862,10 @@ struct WaveSearch {
             }
             const unsigned long long am = __ballot(ok);
             const int n_new = __popcll(am);
-            if (n_acc + n_new > kAcc) merge();
+            if (n_acc + n_new > kAcc) prune();   // leaves at most kWave entries
             if (ok) {
-                const int e = n_acc + lanes_below(am);
-                const int next = atomicExch(&W.head[o], e);
-                W.acc[e] = make_int2(__float_as_int(tot), (int)((hid << 8) | (unsigned)next));
+                W.acc[n_acc + lanes_below(am)] = make_int2(__float_as_int(tot), (int)((hid << 6) | (unsigned)o));
+                atomicAdd(&W.tally[o], 1);
             }
             n_acc += n_new;
             valid = valid_next;
@@ -923,15 +947,16 @@ __device__ __forceinline__ float dphi_of(float xr)
 }
 
 // Windowed search of layer L for the predicted state (pp, pc) of every lane
-// with `predicted` set: the best K accepted hits of the lane in (lc, lid),
-// sorted by accumulated chi2 then hit id; returns the lane's accepted count.
-// All lanes of the wavefront must call it together.
-template <int K, bool kStats, int kGeo>
+// with `predicted` set (summed chi2 `chi2`, `n_hits` hits so far): every
+// accepted (candidate, hit) pair ends in the search's accepted list; returns
+// the lane's accepted count.  All lanes of the wavefront must call it
+// together.
+template <int G, bool kStats, int kGeo>
 __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&pc)[21], const Trig &tg, float chi2,
-                                            bool predicted, int L, const LayerParam &lp, const Params &P,
-                                            CEvent &E, int lane, SearchLds<kGeo> &W,
-                                            unsigned long long (&lk)[K], Count &cnt)
+                                            int n_hits, bool predicted, int L, const LayerParam &lp, const Params &P,
+                                            CEvent &E, int lane, WaveSearch<G, kStats, kGeo> &ws)
 {
+    SearchLds<kGeo> &W = ws.W;
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
     int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
     float du = 0.f, dz = 0.f, g2 = pp[2];
@@ -1024,9 +1049,9 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
         for (int i = 0; i < 5; ++i)
             W.own[3 + i][lane] = make_float4(pc[1 + 4 * i], pc[2 + 4 * i], pc[3 + 4 * i], pc[4 + 4 * i]);
     }
-    W.head[lane] = kEnd;
+    W.tally[lane] = (n_hits + 1) << 16;
+    W.best[lane] = ~0ull;
 
-    WaveSearch<K, kStats, kGeo> ws{W, E.binned, P, lane, lk, cnt};
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * bin_off_stride(P.bins_phi * P.bins_z);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
@@ -1045,8 +1070,8 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
         ws.add_run(beg, len);
     }
     ws.evaluate();
-    ws.merge();
-    return ws.n_mine;
+    wave_lds_sync();
+    return W.tally[lane] & 0xFFFF;
 }
 
 __device__ __forceinline__ void init_lane(Lane &S, CEvent &E, const Params &P, int seed, bool first_slot)
@@ -1079,7 +1104,6 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
                                            const int lane, const Hist &H, SearchLds<kGeo> &W, Count &cnt)
 {
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
-    constexpr int K = G;     // a parent contributes at most max_cands <= G children
     const int gbase = (lane / G) * G;
     const int slot = lane - gbase;
     const LayerParam lp = P.layer[L];
@@ -1110,11 +1134,9 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const float (&pp)[6] = S.p;
     const float (&pc)[21] = S.c;
 
-    // 2. windowed hit search: keep this lane's best K hit children
-    unsigned long long lk[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) lk[i] = ~0ull;
-    const int nacc = search_layer<K, kStats, kGeo>(pp, pc, S.tg, S.chi2, predicted, L, lp, P, E, lane, W, lk, cnt);
+    // 2. windowed hit search: every accepted hit child into the search's list
+    WaveSearch<G, kStats, kGeo> ws{W, E.binned, P, lane, cnt};
+    const int nacc = search_layer<G, kStats, kGeo>(pp, pc, S.tg, S.chi2, S.n_hits, predicted, L, lp, P, E, lane, ws);
     if (kStats) cnt.acc += nacc;
 
     // 3. hole child, or stop on this surface (with the prediction as state)
@@ -1124,37 +1146,13 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
         S.stopped = 1;
         S.status = 1;
     }
-    bool tail = S.live && (S.stopped || hole);
-    const unsigned long long tail_key = beam_key(S.n_hits, S.chi2, slot, kHoleId);
-    const int child_hits = S.n_hits + 1;
+    const bool tail = S.live && (S.stopped || hole);
 
-    // 4. keep the max_cands best entries of the seed: repeated group minimum
-    //    over 32-bit keys (n_hits, the accumulated chi2 to 2^-15 relative,
-    //    parent rank; unique within a group, one entry per lane and round);
-    //    each round's winner leaves its full key in the search LDS, free by
-    //    now, for the lane of that rank
-    unsigned long long *sel = reinterpret_cast<unsigned long long *>(W.acc);
-    unsigned filled = 0;
-    for (int r = 0; r < P.max_cands; ++r) {
-        const bool has_hit = S.live && lk[0] != ~0ull;
-        const unsigned long long hk =
-            has_hit ? beam_key(child_hits, __uint_as_float((unsigned)(lk[0] >> 32)), slot, (unsigned)lk[0])
-                    : (tail ? tail_key : ~0ull);
-        if (__ballot(hk != ~0ull) == 0) break;   // every seed of the wavefront is exhausted
-        const unsigned k32 = hk == ~0ull ? ~0u : ((unsigned)(hk >> 32) & ~7u) | (unsigned)slot;
-        const unsigned m = group_min32<G>(k32, gbase, slot);
-        const bool won = (k32 == m) & (m != ~0u);
-        if (won) sel[gbase + r] = hk;
-        filled |= (m != ~0u ? 1u : 0u) << r;
-        const bool pop = won & has_hit;
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) lk[i] = pop ? lk[i + 1] : lk[i];
-        lk[K - 1] = pop ? ~0ull : lk[K - 1];
-        tail = tail & !(won & !has_hit);
-    }
-    wave_lds_sync();
-    unsigned long long mine = (slot < P.max_cands && ((filled >> slot) & 1u)) ? sel[lane] : ~0ull;
-    if (lane >= (kWave / G) * G) mine = ~0ull;   // lanes outside every seed group
+    // 4. keep the max_cands best children of the seed (accepted hits, and
+    //    each candidate's hole or stop entry): the lane of rank r takes the
+    //    r-th best key of its group
+    unsigned long long mine = ws.select(tail ? child_key(S.n_hits, __float_as_uint(S.chi2), slot, kHoleId) : ~0ull);
+    if (slot >= P.max_cands || lane >= (kWave / G) * G) mine = ~0ull;
 
     // 5. each kept entry moves to the lane of its rank: fetch the parent's
     //    state and apply the Kalman update with the entry's hit
@@ -1256,8 +1254,8 @@ __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, CE
             store_global(bh + L, S.live ? load_global(E.seed_hits + (size_t)seed * P.n_seed_layers + L) : -1);
         int cur = r;
         for (int L = P.n_layers - 1; L >= P.n_seed_layers; --L) {
-            store_global(bh + L, S.live ? H.hit[L * H.stride + gbase + cur] : -1);
-            if (S.live) cur = H.par[L * H.stride + gbase + cur];
+            store_global(bh + L, S.live ? H.hit(L, gbase + cur) : -1);
+            if (S.live) cur = H.parent(L, gbase + cur);
         }
     }
     if (lane != gbase || seed >= E.n_seeds) return;
@@ -1274,8 +1272,8 @@ __device__ __forceinline__ void finalize_lane(const Lane &S, const Params &P, CE
     for (int L = 0; L < P.n_seed_layers; ++L) store_global(oh + L, load_global(E.seed_hits + s * P.n_seed_layers + L));
     int cur = 0;
     for (int L = P.n_layers - 1; L >= P.n_seed_layers; --L) {
-        store_global(oh + L, H.hit[L * H.stride + gbase + cur]);
-        cur = H.par[L * H.stride + gbase + cur];
+        store_global(oh + L, H.hit(L, gbase + cur));
+        cur = H.parent(L, gbase + cur);
     }
 }
 
@@ -1296,10 +1294,10 @@ __device__ __forceinline__ void flush_counts(const Count &cnt, CEvent &E, int la
 }
 
 // Dynamic LDS of the batched builder: the per-layer records of every wave
-// (an int and a byte per lane and layer), then one SearchLds per wave.
+// (an int per lane and layer), then one SearchLds per wave.
 __host__ __device__ constexpr int search_lds_offset(int waves, int n_layers)
 {
-    return ((waves * n_layers * kWave * 5 + 15) / 16) * 4;   // in ints, 16-byte aligned
+    return waves * n_layers * kWave;   // in ints (a multiple of 64: 16-byte aligned)
 }
 
 // Batched builder.  Each wavefront takes work items (event, group of 64/G
@@ -1312,9 +1310,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
-    const int per_wave = P.n_layers * kWave;
-    Hist H{s_dyn + wave * per_wave, reinterpret_cast<unsigned char *>(s_dyn + W * per_wave) + wave * per_wave,
-           kWave};
+    Hist H{s_dyn + wave * P.n_layers * kWave, kWave};
     SearchLds<kGeo> &SL = reinterpret_cast<SearchLds<kGeo> *>(s_dyn + search_lds_offset(W, P.n_layers))[wave];
     int item = (persistent ? (int)blockIdx.x : xcd_contiguous(blockIdx.x, gridDim.x)) * W + wave;
     for (;;) {
@@ -1354,7 +1350,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
     const bool valid = lane < kSeedsPerWave * G && seed < E.n_seeds;
     const int ns = E.st_slots;
     const int slot = item * kWave + lane;
-    Hist H{E.st_hist_hit + item * kWave, E.st_hist_par + item * kWave, ns};
+    Hist H{E.st_hist + item * kWave, ns};
     Lane S;
     if (L == P.n_seed_layers) {
         init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);

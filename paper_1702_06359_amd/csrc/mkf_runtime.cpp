@@ -186,8 +186,7 @@ size_t carve_plain(const EventShape &s, int slots, void *base, DevEvent *v)
     v->st_trig = c.take<float>(4 * S);
     v->st_chi2 = c.take<float>(S);
     v->st_meta = c.take<int>(S);
-    v->st_hist_hit = c.take<int>((size_t)s.n_layers * S);
-    v->st_hist_par = c.take<unsigned char>((size_t)s.n_layers * S);
+    v->st_hist = c.take<int>((size_t)s.n_layers * S);
     v->st_slots = slots;
     return c.off;
 }
