@@ -782,95 +782,103 @@ struct WaveSearch {
         const int rr = below ? mk_from : prev;
         const int pair = t0 + lane;
         const bool valid = pair < n_pairs;
-        o = 0;
-        if (valid) {
-            const int4 R = W.run[rr];
-            o = R.z;
-            hv = load_global(bh + R.x + (pair - R.y));
-        }
+        // every lane loads (a slot past the last pair, the first binned hit),
+        // so that the load is issued and waited for outside any branch
+        const int4 R = W.run[valid ? rr : 0];
+        o = valid ? R.z : 0;
+        hv = load_global(bh + (valid ? R.x + (pair - R.y) : 0));
         return valid;
     }
 
+    // test one round's pairs (pair slot of this lane: valid, owner o, hit
+    // hv) and append the accepted ones to the list
+    __device__ __forceinline__ void test_round(const bool valid, const int o, const float4 hv)
+    {
+        bool ok = false;
+        float tot = 0.f;
+        const unsigned hid = (unsigned)__float_as_int(hv.w);   // every lane waits for its load here
+        if (valid) {
+            if constexpr (!kXyz) {
+                const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
+                const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
+                if (kStats) {
+                    cnt.scan++;
+                    if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd)
+                        cnt.chi2++;
+                }
+                const float c2 = kDisk ? hit_chi2_disk(a.x, a.y, b.x, b.y, b.z, hv.x, hv.y, hv.z, P.var_u, P.var_r)
+                                       : hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z,
+                                                  P.var_u, P.var_z);
+                ok = fwd & (c2 < P.chi2_cut);
+                tot = a.w + c2;
+            } else {
+                // two-step: the owner's prediction on the layer's average
+                // surface, carried to this hit's own surface
+                const float4 r0 = W.own[0][o], r1 = W.own[1][o], r2 = W.own[2][o];
+                const bool fwd = fmaf(r0.x, hv.x, r0.y * hv.y) > 0.f;
+                float c[21];
+                c[0] = r2.w;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const float4 v = W.own[3 + i][o];
+                    c[1 + 4 * i] = v.x;
+                    c[2 + 4 * i] = v.y;
+                    c[3 + 4 * i] = v.z;
+                    c[4 + 4 * i] = v.w;
+                }
+                const float p[6] = {r0.x, r0.y, r0.z, r1.x, 0.f, 0.f};
+                const Trig tg{r1.y, r1.z, r1.w, r2.x};
+                const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
+                const float irh = fast_rcp(rh);
+                float np[6], F[6][6], sn, cn, cp[6];
+                const bool reach = kDisk ? step_near_plane(p, tg, hv.z, P.w_per_qpt, np, F, sn, cn)
+                                         : step_near_cyl(p, tg, rh, P.w_per_qpt, np, F, sn, cn);
+                transport_pos<kDisk>(F, c, cp);
+                const float ch = hv.x * irh, sh = hv.y * irh;
+                const float c2 =
+                    P.update3d ? hit_chi2_3d(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], hv.x,
+                                             hv.y, hv.z, P.var_u, P.var_r, P.var_z)
+                    : kDisk    ? hit_chi2_disk(np[0], np[1], cp[0], cp[1], cp[2], ch, sh, rh, P.var_u, P.var_r)
+                               : hit_chi2(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], ch, sh,
+                                          hv.z, P.var_u, P.var_z);
+                if (kStats) {
+                    cnt.scan++;
+                    if (fwd && reach) cnt.chi2++;
+                }
+                ok = fwd & reach & (c2 < P.chi2_cut);
+                tot = r0.w + c2;
+            }
+        }
+        const unsigned long long am = __ballot(ok);
+        const int n_new = __popcll(am);
+        if (n_acc + n_new > kAcc) prune();   // leaves at most kWave entries
+        if (ok) {
+            W.acc[n_acc + lanes_below(am)] = make_int2(__float_as_int(tot), (int)((hid << 6) | (unsigned)o));
+            atomicAdd(&W.tally[o], 1);
+        }
+        n_acc += n_new;
+    }
+
     // evaluate every pair of the listed runs, one per lane and round; the hits
-    // of the next round are loaded while this round's are tested
+    // of the next round are loaded while this round's are tested.  Two rounds
+    // per iteration, in alternating registers, so that the wait for a round's
+    // hits falls after the next round's pair listing.
     __device__ __forceinline__ void evaluate()
     {
-        wave_lds_sync();
-        int first = 0;   // first run not yet started
-        int o = 0;
-        float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
-        bool valid = n_pairs > 0 && fetch_pair(0, first, o, hv);
-        for (int t0 = 0; t0 < n_pairs; t0 += kWave) {
-            int o_next = 0;
-            float4 hv_next = make_float4(1.f, 0.f, 0.f, 0.f);
-            const bool valid_next = t0 + kWave < n_pairs && fetch_pair(t0 + kWave, first, o_next, hv_next);
-            bool ok = false;
-            float tot = 0.f;
-            unsigned hid = 0;
-            if (valid) {
-                if constexpr (!kXyz) {
-                    const float4 a = W.own[0][o], b = W.own[1][o], c = W.own[2][o];
-                    const bool fwd = fmaf(a.x, hv.x, a.y * hv.y) > 0.f;
-                    if (kStats) {
-                        cnt.scan++;
-                        if (fabsf(hv.z - a.z) <= c.w && fabsf(fmaf(a.x, hv.y, -a.y * hv.x)) <= c.z && fwd)
-                            cnt.chi2++;
-                    }
-                    const float c2 = kDisk ? hit_chi2_disk(a.x, a.y, b.x, b.y, b.z, hv.x, hv.y, hv.z, P.var_u, P.var_r)
-                                           : hit_chi2(a.x, a.y, a.z, b.x, b.y, b.z, b.w, c.x, c.y, hv.x, hv.y, hv.z,
-                                                      P.var_u, P.var_z);
-                    ok = fwd & (c2 < P.chi2_cut);
-                    tot = a.w + c2;
-                } else {
-                    // two-step: the owner's prediction on the layer's average
-                    // surface, carried to this hit's own surface
-                    const float4 r0 = W.own[0][o], r1 = W.own[1][o], r2 = W.own[2][o];
-                    const bool fwd = fmaf(r0.x, hv.x, r0.y * hv.y) > 0.f;
-                    float c[21];
-                    c[0] = r2.w;
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) {
-                        const float4 v = W.own[3 + i][o];
-                        c[1 + 4 * i] = v.x;
-                        c[2 + 4 * i] = v.y;
-                        c[3 + 4 * i] = v.z;
-                        c[4 + 4 * i] = v.w;
-                    }
-                    const float p[6] = {r0.x, r0.y, r0.z, r1.x, 0.f, 0.f};
-                    const Trig tg{r1.y, r1.z, r1.w, r2.x};
-                    const float rh = sqrtf(fmaf(hv.x, hv.x, hv.y * hv.y));
-                    const float irh = fast_rcp(rh);
-                    float np[6], F[6][6], sn, cn, cp[6];
-                    const bool reach = kDisk ? step_near_plane(p, tg, hv.z, P.w_per_qpt, np, F, sn, cn)
-                                             : step_near_cyl(p, tg, rh, P.w_per_qpt, np, F, sn, cn);
-                    transport_pos<kDisk>(F, c, cp);
-                    const float ch = hv.x * irh, sh = hv.y * irh;
-                    const float c2 =
-                        P.update3d ? hit_chi2_3d(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], hv.x,
-                                                 hv.y, hv.z, P.var_u, P.var_r, P.var_z)
-                        : kDisk    ? hit_chi2_disk(np[0], np[1], cp[0], cp[1], cp[2], ch, sh, rh, P.var_u, P.var_r)
-                                   : hit_chi2(np[0], np[1], np[2], cp[0], cp[1], cp[2], cp[3], cp[4], cp[5], ch, sh,
-                                              hv.z, P.var_u, P.var_z);
-                    if (kStats) {
-                        cnt.scan++;
-                        if (fwd && reach) cnt.chi2++;
-                    }
-                    ok = fwd & reach & (c2 < P.chi2_cut);
-                    tot = r0.w + c2;
-                }
-                hid = (unsigned)__float_as_int(hv.w);
+        if (n_pairs > 0) {
+            wave_lds_sync();
+            int first = 0;   // first run not yet started
+            int oa, ob;
+            float4 ha, hb;
+            bool va = fetch_pair(0, first, oa, ha);
+            for (int t0 = 0;; t0 += 2 * kWave) {
+                const bool vb = fetch_pair(t0 + kWave, first, ob, hb);
+                test_round(va, oa, ha);
+                if (t0 + kWave >= n_pairs) break;
+                va = fetch_pair(t0 + 2 * kWave, first, oa, ha);
+                test_round(vb, ob, hb);
+                if (t0 + 2 * kWave >= n_pairs) break;
             }
-            const unsigned long long am = __ballot(ok);
-            const int n_new = __popcll(am);
-            if (n_acc + n_new > kAcc) prune();   // leaves at most kWave entries
-            if (ok) {
-                W.acc[n_acc + lanes_below(am)] = make_int2(__float_as_int(tot), (int)((hid << 6) | (unsigned)o));
-                atomicAdd(&W.tally[o], 1);
-            }
-            n_acc += n_new;
-            valid = valid_next;
-            o = o_next;
-            hv = hv_next;
         }
         n_runs = 0;
         n_pairs = 0;
