@@ -1426,6 +1426,58 @@ __device__ __forceinline__ void fit_track(const Params &P, CEvent &E, float (&p)
     // test it at run time)
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo), kFit3d = (kGeo & 4) != 0;
     Trig tg = trig_of(p);
+    if constexpr (!kXyz) {
+        // Thin layers: the hit of layer L + 1 is loaded while layer L is
+        // updated and layer L + 1 propagated to, by every lane (no hit: any
+        // hit of the event, or the first word of its input block when it has
+        // none), so that its latency hides behind that arithmetic.  Two
+        // layers per iteration in alternating registers keep the wait for a
+        // hit next to its use.
+        const int nh1 = max(E.n_hits - 1, 0);
+        auto hit_at = [&](int L, int h) { return load_global(E.hits + min(E.layer_off[L] + max(h, 0), nh1)); };
+        auto step = [&](const int L, const int h, const float4 hv, int &h_next, float4 &hv_next) -> bool {
+            const bool more = L + 1 < P.n_layers;
+            h_next = more ? hit_of(L + 1) : -1;
+            if (L > 0) {
+                float np[6], F[6][6], sn, cn;
+                if (!(kDisk ? propagate_plane(p, tg, P.layer[L].zplane, P.w_per_qpt, np, F, sn, cn)
+                            : propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn))) {
+                    status = 2;
+                    return false;
+                }
+                add_scattering(p, tg, P.layer[L - 1].x0, kDisk, P.mass2, c);
+                tg.sph = sn;
+                tg.cph = cn;
+                transport<kDisk>(F, c);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) p[i] = np[i];
+            }
+            if (more) hv_next = hit_at(L + 1, h_next);
+            if (h >= 0) {
+                // Joseph form for the first updates, as below
+                if (nupd < kJosephUpdates) {
+                    if (kFit3d) chi2 += kf_update_3d<true>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+                    else chi2 += kf_update_joseph<kDisk>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
+                } else {
+                    if (kFit3d) chi2 += kf_update_3d<false>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, P.var_r, P.var_z);
+                    else chi2 += kf_update<kDisk>(p, c, tg, hv.x, hv.y, hv.z, P.var_u, kDisk ? P.var_r : P.var_z);
+                }
+                ++nupd;
+#pragma unroll
+                for (int i = 0; i < 6; ++i) op[i] = p[i];
+#pragma unroll
+                for (int i = 0; i < 21; ++i) oc[i] = c[i];
+            }
+            return true;
+        };
+        int ha = hit_of(0), hb = -1;
+        float4 va = hit_at(0, ha), vb = va;
+        for (int L = 0; L < P.n_layers; L += 2) {
+            if (!step(L, ha, va, hb, vb) || L + 1 >= P.n_layers) break;
+            if (!step(L + 1, hb, vb, ha, va)) break;
+        }
+        return;
+    }
     for (int L = 0; L < P.n_layers; ++L) {
         const int h = hit_of(L);
         float4 hv = make_float4(1.f, 0.f, 0.f, 0.f);
@@ -1488,7 +1540,8 @@ __device__ __forceinline__ void fit_track(const Params &P, CEvent &E, float (&p)
     }
 }
 
-// One track of a fit with known hits.
+// One track of a fit with known hits, prior read and results written per
+// lane.
 template <int kGeo>
 __device__ __forceinline__ void fit_known(const Params &P, CEvent &E, const size_t t)
 {
@@ -1509,11 +1562,63 @@ __device__ __forceinline__ void fit_known(const Params &P, CEvent &E, const size
     store_global(E.fit_status + t, status);
 }
 
-// Fit with known hits: one lane per track, no branching beyond skipped layers.
+// Dynamic LDS of the fit kernel per wavefront: 27 priors or results and the
+// hit indices of 64 tracks.
+__host__ __device__ constexpr int fit_lds_words(int n_layers) { return (27 + n_layers) * kWave; }
+
+// Fit with known hits: one lane per track.  A wavefront whose 64 tracks lie
+// in one batch moves their priors, hit lists and results through LDS, so
+// that every global access of those transfers is one contiguous run (the
+// arrays are track-major: a lane's own words lie 24 to 84 bytes apart from
+// its neighbour's); a wavefront across a batch boundary, or at the end of
+// the grid, takes one pass per batch with per-lane accesses instead.
 template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_fit(const Params P, const BatchArgs B)
 {
-    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    extern __shared__ int s_dyn[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g0 = uniform(xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + (threadIdx.x & ~(kWave - 1)));
+    if (g0 >= B.total_tracks) return;
+    const int g = g0 + lane;
+    const int e0 = uniform(upper_bound_i32(B.track_prefix, B.n_events + 1, g0) - 1);
+    if (g0 + kWave <= load_global(B.track_prefix + e0 + 1)) {
+        CEvent &E = event_desc(B.events, e0);
+        const size_t t0 = (size_t)(g0 - load_global(B.track_prefix + e0));
+        const int nl = P.n_layers;
+        float *sp = reinterpret_cast<float *>(s_dyn + (threadIdx.x >> 6) * fit_lds_words(nl));   // [64][6]
+        float *sc = sp + 6 * kWave;                                                            // [64][21]
+        int *sh = reinterpret_cast<int *>(sc + 21 * kWave);                                    // [64][nl]
+        const float *gp = E.track_par + 6 * t0, *gc = E.track_cov + 21 * t0;
+        const int *gh = E.track_hits + t0 * nl;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sp[k * kWave + lane] = load_global(gp + k * kWave + lane);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) sc[k * kWave + lane] = load_global(gc + k * kWave + lane);
+        for (int k = 0; k < nl; ++k) sh[k * kWave + lane] = load_global(gh + k * kWave + lane);
+        wave_lds_sync();
+        float p[6], c[21], op[6], oc[21], chi2;
+        int nupd, status;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[i] = sp[6 * lane + i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) c[i] = sc[21 * lane + i];
+        fit_track<kGeo>(P, E, p, c, [&](int L) { return sh[nl * lane + L]; }, op, oc, chi2, nupd, status);
+        wave_lds_sync();   // every prior read before the results take its place
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sp[6 * lane + i] = op[i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) sc[21 * lane + i] = oc[i];
+        wave_lds_sync();
+        double *fp = E.fit_par + 6 * t0, *fc = E.fit_cov + 21 * t0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) store_global(fp + k * kWave + lane, (double)sp[k * kWave + lane]);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) store_global(fc + k * kWave + lane, (double)sc[k * kWave + lane]);
+        store_global(E.fit_chi2 + t0 + lane, (double)chi2);
+        store_global(E.fit_nupd + t0 + lane, nupd);
+        store_global(E.fit_status + t0 + lane, status);
+        return;
+    }
     if (g >= B.total_tracks) return;
     const int e_lane = upper_bound_i32(B.track_prefix, B.n_events + 1, g) - 1;
     // one pass per batch the wave's lanes cover (two where a batch boundary
@@ -1883,13 +1988,14 @@ hipError_t launch_fit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_tracks <= 0) return hipSuccess;
     const unsigned grid = blocks_for(b.total_tracks, 256);
+    const size_t lds = 4 * sizeof(int) * (size_t)fit_lds_words(p.n_layers);
     switch (p.geo | (p.update3d ? 4 : 0)) {
-    case 0: k_fit<0><<<grid, 256, 0, s>>>(p, b); break;
-    case 1: k_fit<1><<<grid, 256, 0, s>>>(p, b); break;
-    case 2: k_fit<2><<<grid, 256, 0, s>>>(p, b); break;
-    case 3: k_fit<3><<<grid, 256, 0, s>>>(p, b); break;
-    case 6: k_fit<6><<<grid, 256, 0, s>>>(p, b); break;
-    case 7: k_fit<7><<<grid, 256, 0, s>>>(p, b); break;
+    case 0: k_fit<0><<<grid, 256, lds, s>>>(p, b); break;
+    case 1: k_fit<1><<<grid, 256, lds, s>>>(p, b); break;
+    case 2: k_fit<2><<<grid, 256, lds, s>>>(p, b); break;
+    case 3: k_fit<3><<<grid, 256, lds, s>>>(p, b); break;
+    case 6: k_fit<6><<<grid, 256, lds, s>>>(p, b); break;
+    case 7: k_fit<7><<<grid, 256, lds, s>>>(p, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
