@@ -297,8 +297,112 @@ __device__ __forceinline__ Trig trig_of(const float (&p)[6])
     return t;
 }
 
+// Jacobian of a step to a cylinder in factored form, F = P + v d^T: P the
+// derivative at fixed path (the identity but for six entries), v the
+// derivative of the end point (x, y, z, phi) along the transverse path, and
+// d the change of path with (x, y, q/pT, phi) that keeps the end point on the
+// cylinder.  Rows q/pT and theta are those of the identity.
+struct CylJac {
+    float Pxq, Pxp, Pyq, Pyp, Pzt, Ppq;   // P[0][3], P[0][4], P[1][3], P[1][4], P[2][5], P[4][3]
+    float vx, vy, vz, vp;                 // v[0], v[1], v[2], v[4]
+    float dx, dy, dq, dp;                 // d[0], d[1], d[3], d[4]
+};
+
 __device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, float s, float w_per_qpt,
-                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out);
+                                          float (&o)[6], CylJac &J, float &sn_out, float &cn_out);
+
+// The full 6x6 matrix of a factored cylinder Jacobian.
+__device__ __forceinline__ void cyl_jac_full(const CylJac &J, float (&F)[6][6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) F[i][j] = i == j ? 1.f : 0.f;
+    const float v[4] = {J.vx, J.vy, J.vz, J.vp};
+    const int row[4] = {0, 1, 2, 4};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        F[row[a]][0] = fmaf(v[a], J.dx, F[row[a]][0]);
+        F[row[a]][1] = fmaf(v[a], J.dy, F[row[a]][1]);
+        F[row[a]][3] = fmaf(v[a], J.dq, F[row[a]][3]);
+        F[row[a]][4] = fmaf(v[a], J.dp, F[row[a]][4]);
+    }
+    F[0][3] += J.Pxq;
+    F[0][4] += J.Pxp;
+    F[1][3] += J.Pyq;
+    F[1][4] += J.Pyp;
+    F[2][5] = J.Pzt;
+    F[4][3] += J.Ppq;
+}
+
+// C <- F C F^T for a factored cylinder Jacobian F = P + v d^T:
+// P C P^T + (P u) v^T + v (P u)^T + (d^T u) v v^T with u = C d, about 110
+// multiply-adds where the general sparse product takes about 170.
+__device__ __forceinline__ void transport_cyl(const CylJac &J, float (&c)[21])
+{
+    auto C = [&](int i, int j) { return c[sym(i, j)]; };
+    float u[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        u[i] = fmaf(C(i, 0), J.dx, fmaf(C(i, 1), J.dy, fmaf(C(i, 3), J.dq, C(i, 4) * J.dp)));
+    const float sig = fmaf(J.dx, u[0], fmaf(J.dy, u[1], fmaf(J.dq, u[3], J.dp * u[4])));
+    float Pu[6];
+    Pu[0] = fmaf(J.Pxq, u[3], fmaf(J.Pxp, u[4], u[0]));
+    Pu[1] = fmaf(J.Pyq, u[3], fmaf(J.Pyp, u[4], u[1]));
+    Pu[2] = fmaf(J.Pzt, u[5], u[2]);
+    Pu[3] = u[3];
+    Pu[4] = fmaf(J.Ppq, u[3], u[4]);
+    Pu[5] = u[5];
+    // M = P C: the entries the upper triangle of M P^T needs
+    auto M = [&](int i, int j) {
+        switch (i) {
+        case 0: return fmaf(J.Pxq, C(3, j), fmaf(J.Pxp, C(4, j), C(0, j)));
+        case 1: return fmaf(J.Pyq, C(3, j), fmaf(J.Pyp, C(4, j), C(1, j)));
+        case 2: return fmaf(J.Pzt, C(5, j), C(2, j));
+        case 4: return fmaf(J.Ppq, C(3, j), C(4, j));
+        default: return C(i, j);
+        }
+    };
+    float M3[5], M4[5], M5[6];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        M3[i] = M(i, 3);
+        M4[i] = M(i, 4);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) M5[i] = M(i, 5);
+    float n[21];
+    // column k of N = M P^T for i <= k
+    n[sym(0, 0)] = fmaf(J.Pxq, M3[0], fmaf(J.Pxp, M4[0], M(0, 0)));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) n[sym(i, 1)] = fmaf(J.Pyq, M3[i], fmaf(J.Pyp, M4[i], M(i, 1)));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) n[sym(i, 2)] = fmaf(J.Pzt, M5[i], M(i, 2));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) n[sym(i, 3)] = M3[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) n[sym(i, 4)] = fmaf(J.Ppq, M3[i], M4[i]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) n[sym(i, 5)] = M5[i];
+    // + (P u) v^T + v (P u)^T + sig v v^T, v nonzero in rows 0, 1, 2, 4
+    const float v[6] = {J.vx, J.vy, J.vz, 0.f, J.vp, 0.f};
+    constexpr bool inV[6] = {true, true, true, false, true, false};
+    const float hs = 0.5f * sig;
+    float t[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) t[i] = inV[i] ? fmaf(hs, v[i], Pu[i]) : Pu[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int k = i; k < 6; ++k) {
+            float a = n[sym(i, k)];
+            if (inV[i] && inV[k]) a = fmaf(t[i], v[k], fmaf(v[i], t[k], a));
+            else if (inV[i]) a = fmaf(v[i], Pu[k], a);
+            else if (inV[k]) a = fmaf(Pu[i], v[k], a);
+            c[sym(i, k)] = a;
+        }
+    }
+}
 
 // Propagate state p (with the sines and cosines of its angles in tg) to the
 // cylinder of radius r along the helix of the
@@ -311,7 +415,7 @@ __device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, f
 // end point on the cylinder), and the sine and cosine of the new momentum
 // azimuth.  Returns false when r is never reached.
 __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, float r, float w_per_qpt,
-                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+                                          float (&o)[6], CylJac &J, float &sn_out, float &cn_out)
 {
     const float x = p[0], y = p[1], q = p[3];
     const float sph = tg.sph, cph = tg.cph;
@@ -345,14 +449,14 @@ __device__ __forceinline__ bool propagate(const float (&p)[6], const Trig &tg, f
         }
         if (!(s < kInf)) return false;
     }
-    helix_cyl(p, tg, s, w_per_qpt, o, F, sn_out, cn_out);
+    helix_cyl(p, tg, s, w_per_qpt, o, J, sn_out, cn_out);
     return true;
 }
 
 // The helix step of transverse path s (either sign) from state p, and the
 // Jacobian on the cylinder through the end point (see propagate).
 __device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, float s, float w_per_qpt,
-                                          float (&o)[6], float (&F)[6][6], float &sn_out, float &cn_out)
+                                          float (&o)[6], CylJac &J, float &sn_out, float &cn_out)
 {
     const float x = p[0], y = p[1], z = p[2], q = p[3], phi = p[4];
     const float sph = tg.sph, cph = tg.cph;
@@ -388,27 +492,7 @@ __device__ __forceinline__ void helix_cyl(const float (&p)[6], const Trig &tg, f
     const float dsx = nx * iden, dsy = ny * iden;
     const float dsq = fmaf(nx, Pxq, ny * Pyq) * iden;
     const float dsp = fmaf(nx, Pxp, ny * Pyp) * iden;
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) F[i][j] = 0.f;
-    F[0][0] = fmaf(cn, dsx, 1.f);
-    F[0][1] = cn * dsy;
-    F[0][3] = fmaf(cn, dsq, Pxq);
-    F[0][4] = fmaf(cn, dsp, Pxp);
-    F[1][0] = sn * dsx;
-    F[1][1] = fmaf(sn, dsy, 1.f);
-    F[1][3] = fmaf(sn, dsq, Pyq);
-    F[1][4] = fmaf(sn, dsp, Pyp);
-    F[2][0] = cot * dsx;
-    F[2][1] = cot * dsy;
-    F[2][3] = cot * dsq;
-    F[2][4] = cot * dsp;
-    F[2][5] = Pzt;
-    F[4][0] = w * dsx;
-    F[4][1] = w * dsy;
-    F[4][3] = fmaf(w, dsq, Ppq);
-    F[4][4] = fmaf(w, dsp, 1.f);
+    J = CylJac{Pxq, Pxp, Pyq, Pyp, Pzt, Ppq, cn, sn, cot, w, dsx, dsy, dsq, dsp};
 }
 
 // Second step of the two-step propagation on a layer of finite thickness:
@@ -445,7 +529,9 @@ __device__ __forceinline__ bool step_near_cyl(const float (&p)[6], const Trig &t
         ok = false;
         s = 0.f;
     }
-    helix_cyl(p, tg, s, w_per_qpt, o, F, sn_out, cn_out);
+    CylJac J;
+    helix_cyl(p, tg, s, w_per_qpt, o, J, sn_out, cn_out);
+    cyl_jac_full(J, F);
     return ok;
 }
 
@@ -558,6 +644,28 @@ __device__ __forceinline__ void add_scattering(const float (&p)[6], const Trig &
     c[sym(5, 5)] += v;
     c[sym(3, 3)] += q * q * cot * cot * v;
     c[sym(3, 5)] -= q * cot * v;
+}
+
+// Prediction on the next surface (Section 2: propagate, then add the
+// scattering of the layer left, then transport the covariance): the state
+// np with the sine and cosine of its azimuth, the covariance c updated in
+// place.  False when the helix never reaches the surface (c untouched).
+template <bool kDisk>
+__device__ __forceinline__ bool predict(const float (&p)[6], const Trig &tg, float where, float w_per_qpt, float x0,
+                                        float mass2, float (&np)[6], float &sn, float &cn, float (&c)[21])
+{
+    if constexpr (kDisk) {
+        float F[6][6];
+        if (!propagate_plane(p, tg, where, w_per_qpt, np, F, sn, cn)) return false;
+        add_scattering(p, tg, x0, true, mass2, c);
+        transport<true>(F, c);
+    } else {
+        CylJac J;
+        if (!propagate(p, tg, where, w_per_qpt, np, J, sn, cn)) return false;
+        add_scattering(p, tg, x0, false, mass2, c);
+        transport_cyl(J, c);
+    }
+    return true;
 }
 
 // chi2 of a hit (cos phi_h, sin phi_h, z_h) against a predicted state: the

@@ -1122,13 +1122,11 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     //    the layer keeps its state and stops.
     bool predicted = false;
     if (active) {
-        float np[6], F[6][6], sn, cn;
-        const bool ok = kDisk ? propagate_plane(S.p, S.tg, lp.zplane, P.w_per_qpt, np, F, sn, cn)
-                              : propagate(S.p, S.tg, lp.r, P.w_per_qpt, np, F, sn, cn);
+        float np[6], sn, cn;
+        const bool ok = predict<kDisk>(S.p, S.tg, kDisk ? lp.zplane : lp.r, P.w_per_qpt, P.layer[L - 1].x0, P.mass2,
+                                       np, sn, cn, S.c);
         if (kStats) cnt.prop++;
         if (ok) {
-            add_scattering(S.p, S.tg, P.layer[L - 1].x0, kDisk, P.mass2, S.c);
-            transport<kDisk>(F, S.c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) S.p[i] = np[i];
             S.tg.sph = sn;
@@ -1439,16 +1437,14 @@ __device__ __forceinline__ void fit_track(const Params &P, CEvent &E, float (&p)
             const bool more = L + 1 < P.n_layers;
             h_next = more ? hit_of(L + 1) : -1;
             if (L > 0) {
-                float np[6], F[6][6], sn, cn;
-                if (!(kDisk ? propagate_plane(p, tg, P.layer[L].zplane, P.w_per_qpt, np, F, sn, cn)
-                            : propagate(p, tg, P.layer[L].r, P.w_per_qpt, np, F, sn, cn))) {
+                float np[6], sn, cn;
+                if (!predict<kDisk>(p, tg, kDisk ? P.layer[L].zplane : P.layer[L].r, P.w_per_qpt,
+                                    P.layer[L - 1].x0, P.mass2, np, sn, cn, c)) {
                     status = 2;
                     return false;
                 }
-                add_scattering(p, tg, P.layer[L - 1].x0, kDisk, P.mass2, c);
                 tg.sph = sn;
                 tg.cph = cn;
-                transport<kDisk>(F, c);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) p[i] = np[i];
             }
@@ -1491,16 +1487,13 @@ __device__ __forceinline__ void fit_track(const Params &P, CEvent &E, float (&p)
             }
         }
         if (L > 0) {
-            float np[6], F[6][6], sn, cn;
-            if (!(kDisk ? propagate_plane(p, tg, where, P.w_per_qpt, np, F, sn, cn)
-                        : propagate(p, tg, where, P.w_per_qpt, np, F, sn, cn))) {
+            float np[6], sn, cn;
+            if (!predict<kDisk>(p, tg, where, P.w_per_qpt, P.layer[L - 1].x0, P.mass2, np, sn, cn, c)) {
                 status = 2;
                 break;
             }
-            add_scattering(p, tg, P.layer[L - 1].x0, kDisk, P.mass2, c);
             tg.sph = sn;
             tg.cph = cn;
-            transport<kDisk>(F, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) p[i] = np[i];
         }
