@@ -29,15 +29,15 @@ sys.path.insert(0, ROOT)
 # source (fma = 2; add, sub, mul, rcp, sqrt, rsq, sin, cos, log, atan = 1;
 # compares, selects and integer work not counted).
 FLOP_SCATTER = 40             # Highland angle and the 4 noise terms
-FLOP_PROPAGATE = 160          # path root, helix step and the Jacobian
-FLOP_TRANSPORT = 272          # F C F^T against the Jacobian's sparsity
+FLOP_PROPAGATE = 136          # path root, helix step and the Jacobian's factors P, v, d
+FLOP_TRANSPORT = 212          # F C F^T with F = P + v d^T (cylinders)
 FLOP_WINDOW = 37              # search window and bin range
-FLOP_PER_CAND_LAYER = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT + FLOP_WINDOW   # 509
+FLOP_PER_CAND_LAYER = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT + FLOP_WINDOW   # 425
 FLOP_PER_CHI2 = 39            # window tests, tangent-plane residual, 2x2 innovation, chi2
 FLOP_PER_UPDATE = 187         # gain, state and covariance update
 FLOP_PER_UPDATE_JOSEPH = 445  # fit update in Joseph form (the first JOSEPH_UPDATES of a fit)
 JOSEPH_UPDATES = 3
-FLOP_PER_FIT_STEP = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT   # 472, layers 1..9 of a fit
+FLOP_PER_FIT_STEP = FLOP_SCATTER + FLOP_PROPAGATE + FLOP_TRANSPORT   # 388, layers 1..9 of a fit
 BYTES_PER_FIT_TRACK = 108 + 40 + 10 * 16 + 232   # prior (f32), hit ids, hits (float4), fit result (f64)
 BYTES_PER_SEED_IO = 120 + 276     # seed in (f32 state, cov, hit ids) + track out (f64)
 BYTES_PER_HIT = 16                # binned hit read once
