@@ -100,8 +100,10 @@ __device__ __forceinline__ CEvent &event_desc(const DevEvent *events, int e) { r
 
 // atan2 to 3.8e-7 rad: octant reduction and an odd degree-15 polynomial
 // (least-squares fit to atan on [0, 1], max error 1.1e-7 in FP32; the
-// rounding of results near pi dominates the total).  Used only for the
-// search-window centre, whose azimuth range is padded by 1e-5 rad.
+// rounding of results near pi dominates the total).  Used for the
+// search-window centre, whose azimuth range is padded by 1e-5 rad, and for
+// the azimuth bin of every hit (so a hit within that error of a bin edge may
+// take either bin, and the padded window still covers it).
 __device__ __forceinline__ float fast_atan2(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);

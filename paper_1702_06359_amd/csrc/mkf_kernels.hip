@@ -111,14 +111,10 @@ constexpr bool geo_xyz(int geo) { return (geo & 2) != 0; }
 // propagation step needs.  bin = row * bins_phi + (phi bin).
 __device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const float4 v)
 {
-    float phi, g2;
-    if (geo_xyz(P.geo)) {
-        phi = atan2f(v.y, v.x);
-        g2 = lp.kind ? sqrtf(fmaf(v.x, v.x, v.y * v.y)) : v.z;
-    } else {
-        phi = atan2f(v.y, v.x);
-        g2 = v.z;
-    }
+    // the azimuth to 3.8e-7 rad: far inside the 1e-5 rad the search window
+    // adds to its own azimuth range, which uses the same function
+    const float phi = fast_atan2(v.y, v.x);
+    const float g2 = geo_xyz(P.geo) ? (lp.kind ? sqrtf(fmaf(v.x, v.x, v.y * v.y)) : v.z) : v.z;
     int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
     int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
     ip = min(max(ip, 0), P.bins_phi - 1);
@@ -161,7 +157,7 @@ __device__ __forceinline__ int lds_bump(unsigned *s_cnt, int bin)
 
 // In-place exclusive scan of the nr counters in s_cnt, starting from
 // `carry`; each offset plus `gbase` is also written to gout[0, nr) as it is
-// formed (gout 16-byte aligned).  Each thread owns kPer (a multiple of 8)
+// formed when gout is not null (16-byte aligned).  Each thread owns kPer (a multiple of 8)
 // consecutive bins per step: one step for up to 1024 kPer bins in a block of
 // 1024.  Every thread of the block calls it; it ends on a barrier.
 template <bool kShort, int kPer>
@@ -223,7 +219,8 @@ __device__ __forceinline__ void lds_scan_counts(unsigned *s_cnt, int nr, int car
             }
             run += v[j];
         }
-        if (b0 + kPer <= nr) {
+        if (gout == nullptr) {
+        } else if (b0 + kPer <= nr) {
 #pragma unroll
             for (int j = 0; j < kPer; j += 4)
                 store_global(reinterpret_cast<int4 *>(gout + b0 + j),
@@ -397,8 +394,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         lds_bump<kShort>(s_cnt, b);
     }
     __syncthreads();
-    lds_scan_counts<kShort, 32>(s_cnt, nb, 0, s_wave, off, h0);   // ends on a barrier
+    lds_scan_counts<kShort, 32>(s_cnt, nb, 0, s_wave, nullptr, 0);   // ends on a barrier
+    // the offsets written out four consecutive bins per lane, so that each
+    // store instruction covers one contiguous kilobyte
+    for (int i = 4 * (int)threadIdx.x; i < nb; i += 4 * (int)blockDim.x) {
+        if (i + 4 <= nb) {
+            store_global(reinterpret_cast<int4 *>(off + i),
+                         make_int4(h0 + lds_count<kShort>(s_cnt, i), h0 + lds_count<kShort>(s_cnt, i + 1),
+                                   h0 + lds_count<kShort>(s_cnt, i + 2), h0 + lds_count<kShort>(s_cnt, i + 3)));
+        } else {
+            for (int j = i; j < nb; ++j) store_global(off + j, h0 + lds_count<kShort>(s_cnt, j));
+        }
+    }
     if (threadIdx.x == 0) off[nb] = h0 + n;
+    __syncthreads();   // every offset read before the placement moves them
     for (int i = threadIdx.x; i < n_full; i += step) {
         int b[kU];
         float4 v[kU];

@@ -38,11 +38,12 @@ def host_bins(hits, L, geometry, bins_phi, bins_z):
 
 
 # FP32 rounding of a hit's bin coordinate on the device, in bins: the azimuth
-# carries the rounding of the packed (cos, sin) (< 1e-7 rad), atan2f (taken
-# as 4 ulp of pi, < 1e-6 rad), the sum with the FP32 pi (< 2.5e-7 rad, plus
-# the 9e-8 rad by which FP32 pi differs from pi): 1.5e-6 rad in all, times
-# bins_phi / 2 pi; the scaling by bins / extent and the product's own
-# rounding add less than 3 x 2^-24 of the bin count.
+# carries the rounding of the packed (cos, sin) (< 1e-7 rad), the device's
+# atan2 (3.8e-7 rad, pinned in test_atan_approximation.py), the sum with the
+# FP32 pi (< 2.5e-7 rad, plus the 9e-8 rad by which FP32 pi differs from
+# pi): under 1e-6 rad, taken as 1.5e-6, times bins_phi / 2 pi; the scaling
+# by bins / extent and the product's own rounding add less than 3 x 2^-24
+# of the bin count.
 PHI_ERR_RAD = 1.5e-6
 
 
