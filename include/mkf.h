@@ -321,6 +321,15 @@ mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t 
                            int32_t *order);
 
 /* Work counters of the last build of an event. */
+/* The bin grid of a loaded event's hit index (Section 3.2.1): the context's
+ * grid (mkf_tuning bins_phi x bins_z), coarsened for a small event by
+ * halving both axes while its fullest layer keeps at least three bins per hit,
+ * both counts stay divisible and at least 64 azimuth bins and 2 rows remain,
+ * so that a small event's index and windows suit its hit density.  Writes
+ * the event's bins_phi and bins_z.  Errors: MKF_E_INVALID (NULL pointer),
+ * MKF_E_NOTFOUND, MKF_E_STATE (no index for the current grid yet). */
+mkf_status mkf_index_grid(mkf_ctx *ctx, int32_t handle, int32_t *bins_phi, int32_t *bins_z);
+
 mkf_status mkf_get_stats(mkf_ctx *ctx, int32_t handle, mkf_build_stats *out);
 
 /* KF fit with known hits (Section 2: once the hit set is fixed the filter

@@ -117,6 +117,7 @@ _PROTOS = {
     "mkf_ctx_broken": (C.c_int32, [_ctx_p]),
     "mkf_get_stats": (C.c_int, [_ctx_p, C.c_int32, _P(BuildStats)]),
     "mkf_fetch_index": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
+    "mkf_index_grid": (C.c_int, [_ctx_p, C.c_int32, _P(C.c_int32), _P(C.c_int32)]),
     "mkf_fit": (C.c_int, [_ctx_p, C.c_int32, C.c_int32, _P(C.c_double), _P(C.c_double), _P(C.c_int32),
                           _P(Tracks)]),
     "mkf_fit_batch": (C.c_int, [_ctx_p, _P(C.c_int32), C.c_int32, _P(Tracks)]),
@@ -432,10 +433,16 @@ class Context:
         check(lib().mkf_fetch_beam(self.h, int(handle), C.byref(out.tracks)))
         return {name: v.reshape((n_seeds, k) + v.shape[1:]) for name, v in out.as_dict().items()}
 
+    def index_grid(self, handle: int):
+        """(bins_phi, bins_z) of the event's own index grid."""
+        bp, bz = C.c_int32(), C.c_int32()
+        check(lib().mkf_index_grid(self.h, int(handle), C.byref(bp), C.byref(bz)))
+        return bp.value, bz.value
+
     def fetch_index(self, handle: int, layer: int, n_hits: int):
         """(bin_off, bin_of, order) of one layer's device hit index."""
-        t = self.get_tuning()
-        off = np.zeros(t.bins_phi * t.bins_z + 1, dtype=np.int32)
+        bp, bz = self.index_grid(handle)
+        off = np.zeros(bp * bz + 1, dtype=np.int32)
         bin_of = np.zeros(n_hits, dtype=np.int32)
         order = np.zeros(n_hits, dtype=np.int32)
         check(lib().mkf_fetch_index(self.h, int(handle), int(layer), _ip(off), _ip(bin_of), _ip(order)))

@@ -110,7 +110,7 @@ struct DevEvent {
     int *st_meta;                        // [slots]
     int *st_hist;                        // [n_layers][slots] parent rank << 24 | hit (0xFFFFFF: hole)
     int st_slots;
-    int pad;
+    int grid_k;                          // the event's bin grid: (bins_phi >> grid_k) x (bins_z >> grid_k)
 };
 
 // A batch: events plus the flattened work decomposition over them.
@@ -128,11 +128,31 @@ struct BatchArgs {
     int total_seeds;
     int seeds_per_item;
     int max_layer_hits;          // largest layer of any event (index launch shape)
+    int max_bins;                // largest bin grid of any event (index launch shape)
 };
 
 // Ints per layer in the bin-offset array: its n_bins + 1 offsets, padded to
 // a multiple of four so that every layer's row starts 16-byte aligned.
 __host__ __device__ constexpr int bin_off_stride(int n_bins) { return (n_bins + 4) & ~3; }
+
+// The bin grid of one event: the context's grid (bins_phi x bins_z, set for
+// the fullest events) coarsened by halving both axes while the event's
+// fullest layer keeps at least three bins per hit (the headline's 20,000-
+// track events have three), both counts stay divisible, and at least 64
+// azimuth bins and 2 rows remain.  Small events so get an index and windows
+// sized for their hit density instead of an index as large as the largest.
+inline int event_grid_shift(int max_layer_hits, int bins_phi, int bins_z)
+{
+    int k = 0;
+    for (;;) {
+        const int k1 = k + 1;
+        if ((bins_phi >> k1) << k1 != bins_phi || (bins_z >> k1) << k1 != bins_z) break;
+        if ((bins_phi >> k1) < 64 || (bins_z >> k1) < 2) break;
+        if ((long long)(bins_phi >> k1) * (bins_z >> k1) < 3LL * max_layer_hits) break;
+        k = k1;
+    }
+    return k;
+}
 
 // Batch descriptors of the no-allocation builder: a fixed device array per
 // GPU (mkf_kernels.hip), as laid out for up to kNoAllocMaxEvents events.
@@ -146,7 +166,7 @@ void *noalloc_scratch(int device);              // its device address (null befo
 // Launch helpers implemented in mkf_kernels.hip.
 size_t build_lds_bytes(int geo, int n_layers, int waves_per_block);   // dynamic LDS of a batched build block
 hipError_t launch_fill_i32(int *ptr, int value, int n, hipStream_t s);
-hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s);
+hipError_t launch_batch_zero(const BatchArgs &b, hipStream_t s);   // work counters of a batch
 hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s);
 hipError_t launch_build_batch(const Params &p, const BatchArgs &b, int lanes_per_seed, int waves_per_block,
                               int persistent, int n_blocks, bool stats, hipStream_t s);

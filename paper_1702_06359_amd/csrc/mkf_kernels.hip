@@ -80,16 +80,12 @@ __global__ void __launch_bounds__(256) k_calib_fma(float *__restrict__ out, int 
     store_global(out + t, sum);
 }
 
-// Clears the per-event work counters and/or hit-index bin counts of a batch
-// (a kernel rather than a memset so that it can sit in a captured graph).
-__global__ void k_batch_zero(const BatchArgs B, int n_bins_per_event, int do_stats, int do_bins)
+// Clears the per-event work counters of a batch (a kernel rather than a
+// memset so that it can sit in a captured graph).
+__global__ void k_batch_zero(const BatchArgs B)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (do_stats && g < B.n_events * 5) B.events[g / 5].stats[g % 5] = 0ull;
-    if (do_bins && g < B.n_events * n_bins_per_event) {
-        const int e = g / n_bins_per_event;
-        B.events[e].bin_count[g - e * n_bins_per_event] = 0;
-    }
+    if (g < B.n_events * 5) B.events[g / 5].stats[g % 5] = 0ull;
 }
 
 // Geometries the kernels are specialised for: bit 0 disks (else cylinders);
@@ -105,21 +101,35 @@ constexpr bool geo_xyz(int geo) { return (geo & 2) != 0; }
 // or (r, phi): bin = iz * bins_phi + iphi.  A counting sort over all events
 // of a batch at once.
 
+// An event's bin grid (event_grid_shift): bins_phi x bins_z, and the factor
+// 2^-k that turns the context grid's per-layer scales into the event's
+// (exact, so the scaled products round as the unscaled ones would).
+struct EvGrid {
+    int bp, bz;
+    float sc;
+};
+
+__device__ __forceinline__ EvGrid ev_grid(const Params &P, CEvent &E)
+{
+    const int k = E.grid_k;
+    return EvGrid{P.bins_phi >> k, P.bins_z >> k, __builtin_ldexpf(1.f, -k)};
+}
+
 // The bin of a hit as the host packed it: (cos phi_h, sin phi_h, g2, -) with
 // g2 = z on a cylinder and r on a disk, or, on layers of finite thickness and
 // for the 3x3 measurement, (x, y, z, 0), whose own surface the second
 // propagation step needs.  bin = row * bins_phi + (phi bin).
-__device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const float4 v)
+__device__ __forceinline__ int bin_hit(const Params &P, const LayerParam &lp, const EvGrid &g, const float4 v)
 {
     // the azimuth to 3.8e-7 rad: far inside the 1e-5 rad the search window
     // adds to its own azimuth range, which uses the same function
     const float phi = fast_atan2(v.y, v.x);
     const float g2 = geo_xyz(P.geo) ? (lp.kind ? sqrtf(fmaf(v.x, v.x, v.y * v.y)) : v.z) : v.z;
-    int ip = (int)floorf((phi + kPi) * lp.inv_dphi);
-    int iz = (int)floorf((g2 - lp.grid_lo) * lp.inv_dz);
-    ip = min(max(ip, 0), P.bins_phi - 1);
-    iz = min(max(iz, 0), P.bins_z - 1);
-    return iz * P.bins_phi + ip;
+    int ip = (int)floorf((phi + kPi) * (lp.inv_dphi * g.sc));
+    int iz = (int)floorf((g2 - lp.grid_lo) * (lp.inv_dz * g.sc));
+    ip = min(max(ip, 0), g.bp - 1);
+    iz = min(max(iz, 0), g.bz - 1);
+    return iz * g.bp + ip;
 }
 
 // Binning of every hit of a batch, no atomics: grid (chunks, event x
@@ -131,8 +141,9 @@ __global__ void __launch_bounds__(256) k_index_bin(const Params P, const BatchAr
     CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const LayerParam lp = P.layer[L];
+    const EvGrid g = ev_grid(P, E);
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x)
-        store_global(E.bin_of + h, bin_hit(P, lp, load_global(E.hits + h)));
+        store_global(E.bin_of + h, bin_hit(P, lp, g, load_global(E.hits + h)));
 }
 
 // Bin counters in LDS: one 32-bit counter per bin, or two 16-bit counters per
@@ -269,7 +280,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int L = el - e * P.n_layers;
     CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], n = E.layer_off[L + 1] - h0;
-    const int nb = P.bins_phi * P.bins_z;
+    const EvGrid g = ev_grid(P, E);
+    const int nb = g.bp * g.bz;
     int *off = E.bin_off + L * bin_off_stride(nb);
     const int *bin_of = E.bin_of + h0;
     const float4 *hits = E.hits + h0;
@@ -366,7 +378,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], n = E.layer_off[L + 1] - h0;
     const LayerParam lp = P.layer[L];
-    const int nb = P.bins_phi * P.bins_z;
+    const EvGrid g = ev_grid(P, E);
+    const int nb = g.bp * g.bz;
     int *off = E.bin_off + L * bin_off_stride(nb);
     const float4 *hits = E.hits + h0;
     int *bin_of = E.bin_of + h0;
@@ -383,13 +396,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         for (int u = 0; u < kU; ++u) v[u] = load_global(hits + i + u * stride);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int b = bin_hit(P, lp, v[u]);
+            const int b = bin_hit(P, lp, g, v[u]);
             store_global(bin_of + i + u * stride, b);
             lds_bump<kShort>(s_cnt, b);
         }
     }
     for (int i = n_full + threadIdx.x; i < n; i += stride) {
-        const int b = bin_hit(P, lp, load_global(hits + i));
+        const int b = bin_hit(P, lp, g, load_global(hits + i));
         store_global(bin_of + i, b);
         lds_bump<kShort>(s_cnt, b);
     }
@@ -439,9 +452,10 @@ __global__ void __launch_bounds__(256) k_index_prep(const Params P, const BatchA
     CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
     const LayerParam lp = P.layer[L];
-    int *cnt = E.bin_count + L * P.bins_phi * P.bins_z;
+    const EvGrid g = ev_grid(P, E);
+    int *cnt = E.bin_count + L * g.bp * g.bz;
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
-        const int bin = bin_hit(P, lp, load_global(E.hits + h));
+        const int bin = bin_hit(P, lp, g, load_global(E.hits + h));
         E.bin_of[h] = bin;
         E.bin_rank[h] = atomicAdd(&cnt[bin], 1);
     }
@@ -458,7 +472,8 @@ __global__ void __launch_bounds__(1024) k_index_scan(const Params P, const Batch
     const int e = blockIdx.x / P.n_layers;
     const int L = blockIdx.x - e * P.n_layers;
     CEvent &E = event_desc(B.events, e);
-    const int nb = P.bins_phi * P.bins_z;
+    const EvGrid g = ev_grid(P, E);
+    const int nb = g.bp * g.bz;
     int *cnt = E.bin_count + L * nb;
     int *off = E.bin_off + L * bin_off_stride(nb);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
@@ -532,7 +547,8 @@ __global__ void __launch_bounds__(256) k_index_scatter(const Params P, const Bat
     const int L = blockIdx.y - e * P.n_layers;
     CEvent &E = event_desc(B.events, e);
     const int h0 = E.layer_off[L], h1 = E.layer_off[L + 1];
-    const int nb = P.bins_phi * P.bins_z;
+    const EvGrid g = ev_grid(P, E);
+    const int nb = g.bp * g.bz;
     const int *off = E.bin_off + L * bin_off_stride(nb);
     for (int h = h0 + blockIdx.x * blockDim.x + threadIdx.x; h < h1; h += gridDim.x * blockDim.x) {
         const int pos = load_global(off + load_global(E.bin_of + h)) + load_global(E.bin_rank + h);
@@ -975,6 +991,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
 {
     SearchLds<kGeo> &W = ws.W;
     constexpr bool kDisk = geo_disk(kGeo), kXyz = geo_xyz(kGeo);
+    const EvGrid gr = ev_grid(P, E);
     int n_rows = 0, izlo = 0, n_seg = 1, s0lo = 0, s0hi = -1, s1lo = 0, s1hi = -1;
     float du = 0.f, dz = 0.f, g2 = pp[2];
     if (predicted) {
@@ -1024,14 +1041,15 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
                 g2hi = 1e30f;
             }
         }
-        const int nphi = P.bins_phi;
+        const int nphi = gr.bp;
         if (finite && isfinite(lo) && isfinite(hi) && !isnan(g2lo) && !isnan(g2hi)) {
-            const int ilo = (int)floorf((phipos + lo + kPi) * lp.inv_dphi);
-            const int ihi = (int)floorf((phipos + hi + kPi) * lp.inv_dphi);
-            const float zlo = fmaxf((g2lo - 1e-4f - lp.grid_lo) * lp.inv_dz, -1.f);
-            const float zhi = fminf((g2hi + 1e-4f - lp.grid_lo) * lp.inv_dz, (float)P.bins_z);
-            izlo = min(max((int)floorf(zlo), 0), P.bins_z - 1);
-            const int izhi = min(max((int)floorf(zhi), 0), P.bins_z - 1);
+            const float idphi = lp.inv_dphi * gr.sc, idz = lp.inv_dz * gr.sc;
+            const int ilo = (int)floorf((phipos + lo + kPi) * idphi);
+            const int ihi = (int)floorf((phipos + hi + kPi) * idphi);
+            const float zlo = fmaxf((g2lo - 1e-4f - lp.grid_lo) * idz, -1.f);
+            const float zhi = fminf((g2hi + 1e-4f - lp.grid_lo) * idz, (float)gr.bz);
+            izlo = min(max((int)floorf(zlo), 0), gr.bz - 1);
+            const int izhi = min(max((int)floorf(zhi), 0), gr.bz - 1);
             n_rows = izhi - izlo + 1;
             if (ihi - ilo + 1 >= nphi) {
                 s0lo = 0;
@@ -1070,11 +1088,11 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     W.best[lane] = ~0ull;
 
     const int n_runs = n_rows * n_seg;
-    const int *off = E.bin_off + L * bin_off_stride(P.bins_phi * P.bins_z);
+    const int *off = E.bin_off + L * bin_off_stride(gr.bp * gr.bz);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
     auto run_bounds = [&](int q, int &b, int &e) {
         const int sg = n_seg == 2 ? (q & 1) : 0;
-        const int row = (izlo + (n_seg == 2 ? q >> 1 : q)) * P.bins_phi;
+        const int row = (izlo + (n_seg == 2 ? q >> 1 : q)) * gr.bp;
         b = load_global(off + row + (sg ? s1lo : s0lo));
         e = load_global(off + row + (sg ? s1hi : s0hi) + 1);
     };
@@ -1796,12 +1814,10 @@ hipError_t launch_calib_fma(float *dst, int n_blocks, int iters, hipStream_t s)
 
 int calib_fma_chains() { return kFmaChains; }
 
-hipError_t launch_batch_zero(const Params &p, const BatchArgs &b, bool stats, bool bins, hipStream_t s)
+hipError_t launch_batch_zero(const BatchArgs &b, hipStream_t s)
 {
-    const int nb = p.n_layers * p.bins_phi * p.bins_z;
-    const long long n = std::max<long long>(stats ? 5LL * b.n_events : 0, bins ? (long long)nb * b.n_events : 0);
-    if (n <= 0) return hipSuccess;
-    k_batch_zero<<<blocks_for(n, 256), 256, 0, s>>>(b, nb, stats ? 1 : 0, bins ? 1 : 0);
+    if (b.n_events <= 0) return hipSuccess;
+    k_batch_zero<<<blocks_for(5 * b.n_events, 256), 256, 0, s>>>(b);
     return hipGetLastError();
 }
 
@@ -1845,7 +1861,7 @@ static void lds_refused()
 hipError_t launch_index(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_hits <= 0) return hipSuccess;
-    const size_t nb = (size_t)p.bins_phi * p.bins_z;
+    const size_t nb = (size_t)b.max_bins;   // the batch's largest event grid
     const size_t lds = lds_per_block();
     const unsigned blocks = (unsigned)(b.n_events * p.n_layers);
     const int n_cu = compute_units();

@@ -792,21 +792,38 @@ mkf_status ensure_index(mkf_ctx *ctx, EventRec *rec, bool *rebuilt, hipStream_t 
     return ensure_index_grid(ctx, rec, ctx->tuning.bins_phi, ctx->tuning.bins_z, rebuilt, s);
 }
 
+int max_layer_hits(const EventShape &s)
+{
+    int m = 0;
+    for (int L = 0; L < s.n_layers; ++L) m = std::max(m, s.layer_off[L + 1] - s.layer_off[L]);
+    return m;
+}
+
+int event_bins(const EventShape &s, int bins_phi, int bins_z)
+{
+    const int k = event_grid_shift(max_layer_hits(s), bins_phi, bins_z);
+    return (bins_phi >> k) * (bins_z >> k);
+}
+
 mkf_status ensure_index_grid(mkf_ctx *ctx, EventRec *rec, int bp, int bz, bool *rebuilt, hipStream_t s)
 {
     *rebuilt = false;
     if (rec->index && rec->index_bins_phi == bp && rec->index_bins_z == bz) return MKF_OK;
     if (rec->index) MKF_HIP(hipStreamSynchronize(ctx->stream));   // queued builds may still read it
     rec->heap->release(rec->index);
-    const size_t bytes = event_index_bytes(rec->shape, bp * bz);
+    // the event's own grid: the context's, coarsened for a small event
+    const int k = event_grid_shift(max_layer_hits(rec->shape), bp, bz);
+    const int nb = (bp >> k) * (bz >> k);
+    const size_t bytes = event_index_bytes(rec->shape, nb);
     rec->index = rec->heap->alloc(bytes);
     if (!rec->index) {
         rec->index_bins_phi = rec->index_bins_z = 0;
         return fail(MKF_E_NOMEM, "hit index: %zu bytes", bytes);
     }
-    carve_index(rec->shape, bp * bz, rec->index, &rec->view);
+    carve_index(rec->shape, nb, rec->index, &rec->view);
+    rec->view.grid_k = k;
     // the index build expects zero bin counts (and leaves them at zero)
-    MKF_HIP(launch_fill_i32(rec->view.bin_count, 0, rec->shape.n_layers * bp * bz, s));
+    MKF_HIP(launch_fill_i32(rec->view.bin_count, 0, rec->shape.n_layers * nb, s));
     rec->index_bins_phi = bp;
     rec->index_bins_z = bz;
     drop_plain_graph(rec);
@@ -840,10 +857,12 @@ mkf_status compose_batch(EventRec *const *recs, int n, int spi, bool beam, char 
     int *tp = reinterpret_cast<int *>(h + o_trk);
     int *sp = reinterpret_cast<int *>(h + o_seed);
     long long items = 0, hits = 0, trks = 0, seeds = 0;
-    int max_layer = 0;
+    int max_layer = 0, max_bins = 0;
     for (int i = 0; i < n; ++i) {
         const EventShape &sh = recs[i]->shape;
         for (int L = 0; L < sh.n_layers; ++L) max_layer = std::max(max_layer, sh.layer_off[L + 1] - sh.layer_off[L]);
+        const int k = recs[i]->view.grid_k;
+        max_bins = std::max(max_bins, (recs[i]->index_bins_phi >> k) * (recs[i]->index_bins_z >> k));
         ev[i] = recs[i]->view;
         if (beam) {   // this launch also writes every rank of the final beam
             const DevEvent &b = recs[i]->beam_view;
@@ -883,6 +902,7 @@ mkf_status compose_batch(EventRec *const *recs, int n, int spi, bool beam, char 
     args->total_seeds = (int)seeds;
     args->seeds_per_item = spi;
     args->max_layer_hits = max_layer;
+    args->max_bins = max_bins;
     return MKF_OK;
 }
 
@@ -928,7 +948,7 @@ mkf_status run_pipeline_with(mkf_ctx *ctx, const Params &P, const mkf_tuning &t,
     const bool stats = flags & MKF_BATCH_STATS, reindex = flags & MKF_BATCH_REINDEX;
     // bin counts are left at zero by every index build; fresh tables are
     // cleared when they are allocated
-    if (stats) MKF_HIP(launch_batch_zero(P, args, true, false, s));
+    if (stats) MKF_HIP(launch_batch_zero(args, s));
     if (reindex) {
         if (timed) timer_begin(ctx, 1, s);
         MKF_HIP(launch_index(P, args, s));
@@ -1153,7 +1173,7 @@ mkf_status mkf_load_events(mkf_ctx *ctx, const mkf_event *evs, int32_t n, int32_
     if ((st = stage_batch(ctx, raw, ctx->batch_dev, ctx->batch_host, seeds_per_item(ctx->tuning.lanes_per_seed),
                           &args, s)) != MKF_OK)
         return undo(st);
-    hipError_t e = launch_batch_zero(ctx->params, args, true, false, s);
+    hipError_t e = launch_batch_zero(args, s);
     if (e == hipSuccess) e = launch_index(ctx->params, args, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -1483,6 +1503,18 @@ mkf_status mkf_fetch_beam(mkf_ctx *ctx, int32_t handle, mkf_tracks *out)
     return MKF_OK;
 }
 
+mkf_status mkf_index_grid(mkf_ctx *ctx, int32_t handle, int32_t *bins_phi, int32_t *bins_z)
+{
+    if (!ctx || !bins_phi || !bins_z) return fail(MKF_E_INVALID, "NULL argument");
+    EventRec *rec = find_event(ctx, handle);
+    if (!rec) return fail(MKF_E_NOTFOUND, "unknown event handle %d", handle);
+    if (!rec->index || rec->index_bins_phi != ctx->tuning.bins_phi || rec->index_bins_z != ctx->tuning.bins_z)
+        return fail(MKF_E_STATE, "the index was built for another bin grid");
+    *bins_phi = rec->index_bins_phi >> rec->view.grid_k;
+    *bins_z = rec->index_bins_z >> rec->view.grid_k;
+    return MKF_OK;
+}
+
 mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t *bin_off, int32_t *bin_of,
                            int32_t *order)
 {
@@ -1492,7 +1524,8 @@ mkf_status mkf_fetch_index(mkf_ctx *ctx, int32_t handle, int32_t layer, int32_t 
     if (layer < 0 || layer >= rec->shape.n_layers) return fail(MKF_E_INVALID, "layer %d out of range", layer);
     if (!rec->index || rec->index_bins_phi != ctx->tuning.bins_phi || rec->index_bins_z != ctx->tuning.bins_z)
         return fail(MKF_E_STATE, "the index was built for another bin grid");
-    const int nb = ctx->tuning.bins_phi * ctx->tuning.bins_z;
+    const int k = rec->view.grid_k;
+    const int nb = (ctx->tuning.bins_phi >> k) * (ctx->tuning.bins_z >> k);
     const int h0 = rec->shape.layer_off[layer], n = rec->shape.layer_off[layer + 1] - h0;
     const DevEvent &v = rec->view;
     std::vector<int32_t> off(bin_off ? nb + 1 : 0);

@@ -75,6 +75,8 @@ struct EventShape {
 size_t event_data_bytes(const EventShape &s);
 size_t event_input_bytes(const EventShape &s);   // the packed inputs at the start of the data block
 size_t event_index_bytes(const EventShape &s, int n_bins);
+int max_layer_hits(const EventShape &s);
+int event_bins(const EventShape &s, int bins_phi, int bins_z);   // bins per layer of the event's grid
 
 // One loaded event.
 struct EventRec {

@@ -143,7 +143,7 @@ struct Server {
     // rounds them
     size_t footprint(const EventShape &s) const
     {
-        return round256(event_data_bytes(s)) + round256(event_index_bytes(s, tuning.bins_phi * tuning.bins_z));
+        return round256(event_data_bytes(s)) + round256(event_index_bytes(s, event_bins(s, tuning.bins_phi, tuning.bins_z)));
     }
 
     void release_ticket_resources(Ticket *t)

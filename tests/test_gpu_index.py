@@ -70,9 +70,10 @@ def check_layer(off, bin_of, order, ref_bins, edge, tol):
 
 # Cases by the index form the launch takes: one event (bin ranges split over
 # many blocks, 16-bit counters), batches of seven uneven and of sixty small
-# events (one block per layer, binning included), many events on a grid too
-# fine for one block's LDS (device-wide counting atomics), a layer of more
-# than 65,535 hits (32-bit counters), a disk geometry, and a coarse ragged grid.
+# events (one block per layer, binning included; small events on coarsened
+# grids of their own), many events one of which keeps a grid too fine for one
+# block's LDS (device-wide counting atomics), a layer of more than 65,535 hits
+# (32-bit counters), a disk geometry, and a coarse ragged grid (not halved).
 CASES = ["barrel_one_event", "barrel_batch", "many_events", "many_events_fine_grid", "big_layer", "endcap",
          "coarse"]
 
@@ -85,8 +86,10 @@ def test_index_is_the_counting_sort_of_the_bins(gpu_required, case):
                                                                                        40, 12000, 500))]
     elif case.startswith("many_events"):
         rng = np.random.default_rng(232)
-        evs = [synth.make_event(int(n), cfg=232, event=i, noise=0.3)
-               for i, n in enumerate(rng.integers(50, 1500, size=60))]
+        sizes = rng.integers(50, 1500, size=60)
+        if case == "many_events_fine_grid":
+            sizes[7] = 10000   # an event whose own grid stays the full, too fine one
+        evs = [synth.make_event(int(n), cfg=232, event=i, noise=0.3) for i, n in enumerate(sizes)]
     elif case == "big_layer":
         evs = [synth.make_event(60000, cfg=233, event=0, noise=0.1)]
     else:
@@ -104,11 +107,20 @@ def test_index_is_the_counting_sort_of_the_bins(gpu_required, case):
         t = c.get_tuning()
         n_edge = n_hits = 0
         for e, h in zip(evs, hs):
+            bp, bz = c.index_grid(h)
+            # the event's grid: the context's, halved on both axes while the
+            # fullest layer keeps three bins per hit
+            k = 0
+            while (t.bins_phi % (2 << k) == 0 and t.bins_z % (2 << k) == 0 and t.bins_phi >> (k + 1) >= 64
+                   and t.bins_z >> (k + 1) >= 2
+                   and (t.bins_phi >> (k + 1)) * (t.bins_z >> (k + 1)) >= 3 * max(len(x) for x in e.hits)):
+                k += 1
+            assert (bp, bz) == (t.bins_phi >> k, t.bins_z >> k)
             for L in range(g.n_layers):
                 print(f"case index {case}: layer {L}", flush=True)
                 off, bin_of, order = c.fetch_index(h, L, len(e.hits[L]))
-                ref, edge = host_bins(e.hits[L], L, g, t.bins_phi, t.bins_z)
-                n_edge += check_layer(off, bin_of, order, ref, edge, edge_tolerance(t.bins_phi, t.bins_z))
+                ref, edge = host_bins(e.hits[L], L, g, bp, bz)
+                n_edge += check_layer(off, bin_of, order, ref, edge, edge_tolerance(bp, bz))
                 n_hits += len(bin_of)
     finally:
         c.close()

@@ -121,9 +121,9 @@ def test_admission_takes_a_slot_and_budget_at_submit(ctx):
     second = _wait(ctx, [t2])[t2]
     assert first[0] == abi.OK and second[0] == abi.OK
     # a budget that holds one 4,000-track event at a time (its hits, seeds,
-    # outputs and a 65,536-bin index per layer take about 11.5 MB)
+    # outputs and an index on its own 1024 x 16 grid take about 6 MB)
     ev = synth.make_event(4000, cfg=221, event=2, noise=0.3)
-    ctx.serve_config(16 << 20, max_in_flight=8)
+    ctx.serve_config(10 << 20, max_in_flight=8)
     print("case serve admission: tight budget", flush=True)
     ta, _ = ctx.serve_submit(ev)
     assert ta is not None
