@@ -1356,8 +1356,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
         if (item >= B.total_items) break;
         const int e = uniform(upper_bound_i32(B.item_prefix, B.n_events + 1, item) - 1);
         CEvent &E = event_desc(B.events, e);
-        const int seed = (item - B.item_prefix[e]) * B.seeds_per_item + lane / G;
-        const bool valid = lane < (kWave / G) * G && seed < E.n_seeds;
+        // the item's seeds, taken in azimuth order
+        const int k = (item - B.item_prefix[e]) * B.seeds_per_item + lane / G;
+        const bool valid = lane < (kWave / G) * G && k < E.n_seeds;
+        const int seed = valid ? load_global(E.seed_order + k) : E.n_seeds;
         Lane S;
         init_lane(S, E, P, valid ? seed : 0, valid && lane % G == 0);
         Count cnt;
@@ -1760,7 +1762,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
         const int e = uniform(e_lane);
         if (e_lane != e) continue;
         CEvent &E = event_desc(B.events, e);
-        refit_built<kGeo>(P, E, (size_t)(g - load_global(B.seed_prefix + e)));
+        refit_built<kGeo>(P, E, (size_t)load_global(E.seed_order + (g - load_global(B.seed_prefix + e))));
         break;
     }
 }

@@ -133,6 +133,7 @@ size_t carve_data(const EventShape &s, void *base, DevEvent *v, DevEvent **dev_v
     v->seed_par = c.take<float>(6 * ns);
     v->seed_cov = c.take<float>(21 * ns);
     v->seed_hits = c.take<int>((size_t)s.n_seed_layers * ns);
+    v->seed_order = c.take<int>(ns);
     v->track_par = c.take<float>(6 * nt);
     v->track_cov = c.take<float>(21 * nt);
     v->track_hits = c.take<int>(nl * nt);
@@ -646,6 +647,28 @@ static bool pack_state(const double *par, const double *cov, float *fpar, float 
 // thickness or the 3x3 measurement), computed in FP64; seeds and tracks
 // FP32 states and covariances, finite, theta in (0, pi), hit indices in
 // range.  The layers and the seeds are packed in parallel for large events.
+// The seeds in order of the azimuth of their direction: a counting sort over
+// 1024 sectors that keeps the caller's order within a sector.  The batched
+// builder takes the seeds of one wavefront, and of the wavefronts that run
+// together, from neighbouring sectors, so the hits and bins their windows read
+// are shared in cache instead of each wavefront reading a different part of
+// every layer.  The outputs stay in the caller's order.
+static void order_seeds(const double *seed_par, int ns, int *order)
+{
+    constexpr int kSectors = 1024;
+    std::vector<int> start(kSectors + 1, 0);
+    std::vector<uint16_t> sector(ns);
+    for (int i = 0; i < ns; ++i) {
+        double f = seed_par[6 * (size_t)i + 4] * (0.5 / M_PI);
+        f -= std::floor(f);   // [0, 1); not finite: rejected by the seed checks, sector 0 here
+        const int k = std::isfinite(f) ? std::min(kSectors - 1, std::max(0, (int)(f * kSectors))) : 0;
+        sector[i] = (uint16_t)k;
+        ++start[k + 1];
+    }
+    for (int k = 0; k < kSectors; ++k) start[k + 1] += start[k];
+    for (int i = 0; i < ns; ++i) order[start[sector[i]]++] = i;
+}
+
 mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *image, int threads, std::string *why)
 {
     DevEvent v{};
@@ -653,10 +676,15 @@ mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *
     const int nl = sh.n_layers, nsl = sh.n_seed_layers;
     const int chunk = 4096;
     const int seed_tasks = (sh.n_seeds + chunk - 1) / chunk, track_tasks = (sh.n_tracks + chunk - 1) / chunk;
-    const int n_tasks = nl + seed_tasks + track_tasks;
+    const int order_task = nl + seed_tasks + track_tasks;   // the seed order, beside the packing
+    const int n_tasks = order_task + (sh.n_seeds > 0 ? 1 : 0);
     // first failure of each task: (index, kind), index -1 for none
     std::vector<int> bad(n_tasks, -1), kind(n_tasks, 0);
     run_tasks(n_tasks, threads, [&](int t) {
+        if (t == order_task) {
+            order_seeds(ev->seed_par, sh.n_seeds, const_cast<int *>(v.seed_order));
+            return;
+        }
         if (t < nl) {
             // a hit as the kernels read it: its direction and second grid
             // coordinate computed here in FP64 and rounded once

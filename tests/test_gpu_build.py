@@ -262,6 +262,29 @@ def test_repeat_and_batch_composition_are_deterministic(ctx6):
         _equal(a, d)
 
 
+def test_seed_order_does_not_change_results(ctx6):
+    """The batched builder and the final fit take the seeds in azimuth order
+    (a sort made when the event is loaded); every seed's track and fit must
+    not depend on where the caller put it."""
+    ev = synth.make_event(3000, cfg=214, event=0, noise=0.2)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(ev.n_seeds)
+    shuffled = abi.EventArrays(ev.hits, ev.seed_par[perm], ev.seed_cov[perm], ev.seed_hits[perm])
+    hs = [ctx6.load_event(abi.EventArrays.from_synth(ev)), ctx6.load_event(shuffled)]
+    try:
+        print("case seed order 3000 tracks", flush=True)
+        base, mixed = ctx6.build_batch(hs, [ev.n_seeds] * 2, flags=abi.BATCH_FIT)
+        fits = [ctx6.fetch_fit(h, ev.n_seeds) for h in hs]
+        alone = ctx6.build(hs[1], ev.n_seeds)   # the per-layer builder keeps the caller's order
+    finally:
+        for h in hs:
+            ctx6.unload_event(h)
+    for k in FIELDS:
+        assert np.array_equal(mixed[k], base[k][perm]), k
+        assert np.array_equal(fits[1][k], fits[0][k][perm]), k
+    _equal(mixed, alone)
+
+
 @pytest.mark.parametrize("case", ["barrel", "endcap", "thick", "dense", "coarse", "one_bin", "large", "wide",
                                   "edges"])
 def test_one_block_per_layer_index(gpu_required, case):
