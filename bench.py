@@ -109,7 +109,28 @@ def make_ctx(k, tuning=None, geometry=None):
     return ctx
 
 
-def time_steps(fn, steps, warmup, sync):
+PRIME_S = 0.15
+
+
+def prime(fn, sync, seconds=PRIME_S):
+    """Run the step until `seconds` of wall time have passed: after a load or
+    an idle gap the GPU's clocks ramp up over the first ~40 launches (20 ms of
+    work), each launch a little faster than the last (measured on MI355X: the
+    build kernel takes 0.40 ms, then settles at 0.365 ms), so a few warm-up
+    steps leave the timed steps on the ramp.  Untimed; returns the steps run."""
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        sync()
+        n += 8
+    return n
+
+
+def time_steps(fn, steps, warmup, sync, primed=False):
+    if not primed:
+        prime(fn, sync)
     for _ in range(warmup):
         fn()
     sync()
@@ -289,10 +310,9 @@ def batched_leg(args, steps=10):
         torch.cuda.synchronize()
     tracks = int(sum(e.n_seeds for e in evs))
     step = lambda: ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC)
-    step()
-    sync()
+    prime(step, sync)
     ctx.timer_reset()
-    t_batch = time_steps(step, steps, 0, sync)
+    t_batch = time_steps(step, steps, 0, sync, primed=True)
     build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
     index_ms, index_n = ctx.timer_read(abi.TIMER_INDEX)
     n_plain = max(1, steps // 5)
@@ -329,12 +349,13 @@ def workload_ckf(args):
     def sync():
         ctx.sync()
         torch.cuda.synchronize()
-    log("warmup + timed steps")
+    log("priming, warmup + timed steps")
+    n_prime = prime(step, sync)
     for _ in range(args.warmup):
         step()
     sync()
     ctx.timer_reset()
-    elapsed = time_steps(step, args.steps, 0, sync)
+    elapsed = time_steps(step, args.steps, 0, sync, primed=True)
     build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
     index_ms, index_n = ctx.timer_read(abi.TIMER_INDEX)
     tracks = n_events * n_tracks
@@ -359,11 +380,10 @@ def workload_ckf(args):
     def step_fit():
         ctx.build_batch(handles, None, flags=abi.BATCH_REINDEX | abi.BATCH_ASYNC | abi.BATCH_FIT)
 
-    step_fit()
-    sync()
+    prime(step_fit, sync)
     ctx.timer_reset()
     fit_steps = max(1, args.steps // 2)
-    fit_elapsed = time_steps(step_fit, fit_steps, 0, sync)
+    fit_elapsed = time_steps(step_fit, fit_steps, 0, sync, primed=True)
     refit_ms, refit_n = ctx.timer_read(abi.TIMER_FIT)
     fit_vs_build = fitted_vs_built(ctx, evs[0], handles[0])
     plain_rate = None
@@ -380,7 +400,9 @@ def workload_ckf(args):
         "config": {"workload": "combinatorial KF building, 10 events x 20,000 tracks, 10% noise hits, "
                                "k=6 candidates/seed, chi2<30, 1 hole, 10-layer barrel, 3.8 T",
                    "events": n_events, "tracks_per_event": n_tracks, "noise": noise, "max_cands": k,
-                   "step": "hit index + batched build of all events, steps queued back to back", "tuning": tuning},
+                   "step": "hit index + batched build of all events, steps queued back to back", "tuning": tuning,
+                   "priming": f"{n_prime} untimed steps ({PRIME_S} s) before the warmup, so that the timed steps run "
+                              "at the GPU's sustained clock"},
         "roofline": roofline,
         "index_build_ms_per_step": round(index_ms / max(index_n, 1), 4),
         "build_and_fit": {"tracks_per_s": round(tracks * fit_steps / fit_elapsed, 1),
@@ -529,10 +551,9 @@ def geometry_leg(args, evs, geometry, workload, steps=None):
         ctx.sync()
         torch.cuda.synchronize()
     n = steps or args.steps
-    step()
-    sync()
+    prime(step, sync)
     ctx.timer_reset()
-    elapsed = time_steps(step, n, 0, sync)
+    elapsed = time_steps(step, n, 0, sync, primed=True)
     build_ms, build_n = ctx.timer_read(abi.TIMER_BUILD)
     ctx.close()
     tracks = sum(e.n_seeds for e in evs)
@@ -577,11 +598,12 @@ def workload_fit(args):
     ctx = make_ctx(6)
     handles = [ctx.load_event(abi.EventArrays.from_synth(e, with_seeds=False, with_tracks=True)) for e in evs]
     sync = torch.cuda.synchronize
+    prime(lambda: ctx.fit_batch(handles), sync)
     for _ in range(args.warmup):
         ctx.fit_batch(handles)
     sync()
     ctx.timer_reset()
-    elapsed = time_steps(lambda: ctx.fit_batch(handles), args.steps, 0, sync)
+    elapsed = time_steps(lambda: ctx.fit_batch(handles), args.steps, 0, sync, primed=True)
     fit_ms, fit_n = ctx.timer_read(abi.TIMER_FIT)
     n = int(sizes.sum())
     per_track = np.concatenate([(e.truth_hit >= 0).sum(1) for e in evs])

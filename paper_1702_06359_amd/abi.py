@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 import re
 from typing import Dict, List, Optional, Sequence
 
@@ -297,8 +298,14 @@ def _torch_hooks():
         except Exception:
             return None
 
+    delete, finalizing = torch.cuda.caching_allocator_delete, sys.is_finalizing
+
     def _free(ptr, stream_ptr, user):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        # a context left open until the interpreter exits is destroyed after
+        # torch's allocator may be gone; the process's memory goes with it
+        if finalizing():
+            return
+        delete(int(ptr))
 
     keep = (ALLOC_FN(_alloc), FREE_FN(_free))
     a = Allocator()

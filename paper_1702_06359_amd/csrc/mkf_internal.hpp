@@ -72,7 +72,7 @@ struct DevEvent {
     const float *seed_cov;               // [n_seeds][21]
     const int *seed_hits;                // [n_seeds][n_seed_layers]
     const int *seed_order;               // [n_seeds] the seeds by azimuth of their direction: the batched
-                                         // builder and the final fit take them in this order
+                                         // builder takes them in this order
     const float *track_par;              // [n_tracks][6]
     const float *track_cov;              // [n_tracks][21]
     const int *track_hits;               // [n_tracks][n_layers]

@@ -1762,7 +1762,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xy
         const int e = uniform(e_lane);
         if (e_lane != e) continue;
         CEvent &E = event_desc(B.events, e);
-        refit_built<kGeo>(P, E, (size_t)load_global(E.seed_order + (g - load_global(B.seed_prefix + e))));
+        refit_built<kGeo>(P, E, (size_t)(g - load_global(B.seed_prefix + e)));
         break;
     }
 }
