@@ -654,6 +654,21 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Issue priority of a wavefront through the phases of a layer step.  The
+// prediction and the Kalman update are long runs of VALU work; the hit search
+// and above all the beam selection spend most of their time waiting on LDS
+// round trips and hit loads.  Raising the priority of the waiting phases lets
+// a wavefront that comes out of a wait issue ahead of the wavefronts in their
+// VALU runs (the SIMD picks the highest-priority ready wavefront), so its
+// chain of waits ends sooner while the VALU runs fill the gaps.  The levels
+// were chosen by timing the headline build; they change no result.
+enum : int { kPrioVector = 0, kPrioWindow = 1, kPrioListing = 2, kPrioPairs = 1, kPrioSelect = 3 };
+template <int kLevel>
+__device__ __forceinline__ void wave_priority()
+{
+    __builtin_amdgcn_s_setprio(kLevel);
+}
+
 __device__ __forceinline__ int lanes_below(unsigned long long m)
 {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -1087,6 +1102,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
     W.tally[lane] = (n_hits + 1) << 16;
     W.best[lane] = ~0ull;
 
+    wave_priority<kPrioListing>();
     const int n_runs = n_rows * n_seg;
     const int *off = E.bin_off + L * bin_off_stride(gr.bp * gr.bz);
     // bin offsets of run q: [off[row + lo], off[row + hi + 1])
@@ -1104,6 +1120,7 @@ __device__ __forceinline__ int search_layer(const float (&pp)[6], const float (&
         if (q + 1 < n_runs) run_bounds(q + 1, nb, ne);
         ws.add_run(beg, len);
     }
+    wave_priority<kPrioPairs>();
     ws.evaluate();
     wave_lds_sync();
     return W.tally[lane] & 0xFFFF;
@@ -1147,6 +1164,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     // 1. scattering of the layer being left, propagation, transport.  The
     //    prediction replaces the state in place; a lane whose helix misses
     //    the layer keeps its state and stops.
+    wave_priority<kPrioVector>();
     bool predicted = false;
     if (active) {
         float np[6], sn, cn;
@@ -1168,6 +1186,7 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     const float (&pc)[21] = S.c;
 
     // 2. windowed hit search: every accepted hit child into the search's list
+    wave_priority<kPrioWindow>();
     WaveSearch<G, kStats, kGeo> ws{W, E.binned, P, lane, cnt};
     const int nacc = search_layer<G, kStats, kGeo>(pp, pc, S.tg, S.chi2, S.n_hits, predicted, L, lp, P, E, lane, ws);
     if (kStats) cnt.acc += nacc;
@@ -1184,11 +1203,13 @@ __device__ __forceinline__ void layer_step(Lane &S, const int L, const Params &P
     // 4. keep the max_cands best children of the seed (accepted hits, and
     //    each candidate's hole or stop entry): the lane of rank r takes the
     //    r-th best key of its group
+    wave_priority<kPrioSelect>();
     unsigned long long mine = ws.select(tail ? child_key(S.n_hits, __float_as_uint(S.chi2), slot, kHoleId) : ~0ull);
     if (slot >= P.max_cands || lane >= (kWave / G) * G) mine = ~0ull;
 
     // 5. each kept entry moves to the lane of its rank: fetch the parent's
     //    state and apply the Kalman update with the entry's hit
+    wave_priority<kPrioVector>();
     const bool alive = mine != ~0ull;
     const int parent = alive ? key_parent(mine) : slot;
     const int src = alive ? gbase + parent : lane;
