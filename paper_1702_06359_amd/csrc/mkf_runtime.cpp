@@ -653,20 +653,20 @@ static bool pack_state(const double *par, const double *cov, float *fpar, float 
 // together, from neighbouring sectors, so the hits and bins their windows read
 // are shared in cache instead of each wavefront reading a different part of
 // every layer.  The outputs stay in the caller's order.
-static void order_seeds(const double *seed_par, int ns, int *order)
+constexpr int kSeedSectors = 1024;
+
+static inline uint16_t seed_sector(double phi)
 {
-    constexpr int kSectors = 1024;
-    std::vector<int> start(kSectors + 1, 0);
-    std::vector<uint16_t> sector(ns);
-    for (int i = 0; i < ns; ++i) {
-        double f = seed_par[6 * (size_t)i + 4] * (0.5 / M_PI);
-        f -= std::floor(f);   // [0, 1); not finite: rejected by the seed checks, sector 0 here
-        const int k = std::isfinite(f) ? std::min(kSectors - 1, std::max(0, (int)(f * kSectors))) : 0;
-        sector[i] = (uint16_t)k;
-        ++start[k + 1];
-    }
-    for (int k = 0; k < kSectors; ++k) start[k + 1] += start[k];
-    for (int i = 0; i < ns; ++i) order[start[sector[i]]++] = i;
+    const double x = (phi + M_PI) * (kSeedSectors / (2 * M_PI));
+    return (uint16_t)(x >= 0.0 ? (x < kSeedSectors ? (int)x : kSeedSectors - 1) : 0);   // NaN: sector 0
+}
+
+static void order_seeds(const std::vector<uint16_t> &sector, int *order)
+{
+    int start[kSeedSectors + 1] = {0};
+    for (uint16_t k : sector) ++start[k + 1];
+    for (int k = 0; k < kSeedSectors; ++k) start[k + 1] += start[k];
+    for (int i = 0; i < (int)sector.size(); ++i) order[start[sector[i]]++] = i;
 }
 
 mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *image, int threads, std::string *why)
@@ -676,15 +676,11 @@ mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *
     const int nl = sh.n_layers, nsl = sh.n_seed_layers;
     const int chunk = 4096;
     const int seed_tasks = (sh.n_seeds + chunk - 1) / chunk, track_tasks = (sh.n_tracks + chunk - 1) / chunk;
-    const int order_task = nl + seed_tasks + track_tasks;   // the seed order, beside the packing
-    const int n_tasks = order_task + (sh.n_seeds > 0 ? 1 : 0);
+    const int n_tasks = nl + seed_tasks + track_tasks;
     // first failure of each task: (index, kind), index -1 for none
     std::vector<int> bad(n_tasks, -1), kind(n_tasks, 0);
+    std::vector<uint16_t> sector(sh.n_seeds);   // azimuth sector of each seed, taken while it is packed
     run_tasks(n_tasks, threads, [&](int t) {
-        if (t == order_task) {
-            order_seeds(ev->seed_par, sh.n_seeds, const_cast<int *>(v.seed_order));
-            return;
-        }
         if (t < nl) {
             // a hit as the kernels read it: its direction and second grid
             // coordinate computed here in FP64 and rounded once
@@ -730,6 +726,7 @@ mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *
                 kind[t] = bad_hit;
                 return;
             }
+            if (seeds) sector[i] = seed_sector(ev->seed_par[6 * (size_t)i + 4]);
         }
     });
     for (int t = 0; t < n_tasks; ++t) {
@@ -746,6 +743,7 @@ mkf_status pack_event(const mkf_event *ev, const EventShape &sh, int geo, void *
         *why = msg;
         return MKF_E_INVALID;
     }
+    order_seeds(sector, const_cast<int *>(v.seed_order));
     return MKF_OK;
 }
 
