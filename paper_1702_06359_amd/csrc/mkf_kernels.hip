@@ -692,6 +692,21 @@ __device__ __forceinline__ int wave_exclusive_sum(int x, int lane)
     return v - x;
 }
 
+// Inclusive prefix maximum over the wavefront of non-negative values, with
+// DPP moves: within each row of 16 lanes by shifts of 1, 2, 4 and 8 lanes,
+// then across rows by broadcasting lane 15 into rows 1 and 3 and lane 31
+// into rows 2 and 3.  Lanes a move does not reach take 0, the identity.
+__device__ __forceinline__ int wave_inclusive_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true));   // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true));   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 template <int G, bool kStats, int kGeo>
 struct WaveSearch {
     static constexpr bool kDisk = geo_disk(kGeo);
@@ -723,36 +738,46 @@ struct WaveSearch {
     // group in a lane only the smaller enters the round (the slots hold runs
     // of one candidate's pairs, so this halves the lanes that meet at one
     // address).  Program order suffices between the reads and writes of one
-    // round: a wavefront's LDS instructions execute in order.
+    // round: a wavefront's LDS instructions execute in order.  Which items are
+    // live and which enter a round are kept as wavefront masks in scalar
+    // registers, so that a round's bookkeeping is scalar work beside the
+    // vector work of the other wavefronts.
     __device__ __forceinline__ void rounds(const unsigned long long (&key)[3], const int (&grp)[3], bool (&live)[3],
                                            bool (&taken)[3], unsigned long long &mine)
     {
         const int my_grp = lane / G, my_rank = lane - my_grp * G;
         mine = ~0ull;
+        const unsigned long long L0i = __ballot(live[0]), L1i = __ballot(live[1]), L2i = __ballot(live[2]);
+        unsigned long long L0 = L0i, L1 = L1i, L2 = L2i;
+        // of slots 0 and 1 in one group, the larger waits while the smaller is live
+        const bool same = grp[0] == grp[1];
+        const unsigned long long Y0 = __ballot(same & (key[1] < key[0])), Y1 = __ballot(same & (key[0] < key[1]));
         for (int r = 0; r < P.max_cands; ++r) {
-            if (__ballot(live[0] | live[1] | live[2]) == 0) break;
-            // of slots 0 and 1 in one group, the larger waits
-            const bool both = live[0] & live[1] & (grp[0] == grp[1]);
-            const bool in0 = live[0] & !(both & (key[1] < key[0]));
-            const bool in1 = live[1] & !(both & (key[0] < key[1]));
-            const int a0 = in0 ? grp[0] : kWave, a1 = in1 ? grp[1] : kWave, a2 = live[2] ? grp[2] : kWave;
+            if ((L0 | L1 | L2) == 0) break;
+            const unsigned long long I0 = L0 & ~(Y0 & L1), I1 = L1 & ~(Y1 & L0), I2 = L2;
+            const bool in0 = __builtin_amdgcn_inverse_ballot_w64(I0);
+            const bool in1 = __builtin_amdgcn_inverse_ballot_w64(I1);
+            const bool in2 = __builtin_amdgcn_inverse_ballot_w64(I2);
+            const int a0 = in0 ? grp[0] : kWave, a1 = in1 ? grp[1] : kWave, a2 = in2 ? grp[2] : kWave;
             if (in0) atomicMin(&W.best[a0], key[0]);
             if (in1) atomicMin(&W.best[a1], key[1]);
-            if (live[2]) atomicMin(&W.best[a2], key[2]);
+            if (in2) atomicMin(&W.best[a2], key[2]);
             wave_lds_sync();
             const unsigned long long b0 = W.best[a0], b1 = W.best[a1], b2 = W.best[a2], bm = W.best[my_grp];
-            const bool w0 = in0 & (b0 == key[0]), w1 = in1 & (b1 == key[1]), w2 = live[2] & (b2 == key[2]);
-            taken[0] |= w0;
-            taken[1] |= w1;
-            taken[2] |= w2;
-            live[0] &= !w0;
-            live[1] &= !w1;
-            live[2] &= !w2;
+            L0 &= ~(__ballot(b0 == key[0]) & I0);
+            L1 &= ~(__ballot(b1 == key[1]) & I1);
+            L2 &= ~(__ballot(b2 == key[2]) & I2);
             mine = my_rank == r ? bm : mine;
             wave_lds_sync();
             if (my_rank == r) W.best[my_grp] = ~0ull;
             wave_lds_sync();
         }
+        taken[0] |= __builtin_amdgcn_inverse_ballot_w64(L0i & ~L0);
+        taken[1] |= __builtin_amdgcn_inverse_ballot_w64(L1i & ~L1);
+        taken[2] |= __builtin_amdgcn_inverse_ballot_w64(L2i & ~L2);
+        live[0] = __builtin_amdgcn_inverse_ballot_w64(L0);
+        live[1] = __builtin_amdgcn_inverse_ballot_w64(L1);
+        live[2] = __builtin_amdgcn_inverse_ballot_w64(L2);
     }
 
     // The accepted list is full: keep only its entries that are among the
@@ -815,11 +840,10 @@ struct WaveSearch {
         const int prev = first - 1;
         first += __popcll(__ballot(starts));
         wave_lds_sync();
-        const int mk = W.mark[lane];
-        const unsigned long long below = __ballot(mk >= 0) & (~0ull >> (63 - lane));
-        const int from = below ? 63 - __clzll((long long)below) : 0;
-        const int mk_from = __shfl(mk, from);
-        const int rr = below ? mk_from : prev;
+        // the last run starting at or before this slot: the marks rise with
+        // the slot, so it is their prefix maximum
+        const int last = wave_inclusive_max(W.mark[lane] + 1) - 1;
+        const int rr = last >= 0 ? last : prev;
         const int pair = t0 + lane;
         const bool valid = pair < n_pairs;
         // every lane loads (a slot past the last pair, the first binned hit),
