@@ -1795,11 +1795,57 @@ __device__ __forceinline__ void refit_built(const Params &P, CEvent &E, const si
 }
 
 // Final fit of every built track of a batch (after the build): one lane per
-// seed.
+// seed.  A wavefront whose 64 seeds lie in one event moves their hit lists in
+// and their results out through LDS (as the fit does), so that each transfer
+// is one contiguous run instead of 64 rows 40 to 168 bytes apart.
 template <int kGeo>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geo_xyz(kGeo) ? 3 : 4))) k_refit(const Params P, const BatchArgs B)
 {
-    const int g = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    extern __shared__ int s_dyn[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g0 = uniform(xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + (threadIdx.x & ~(kWave - 1)));
+    if (g0 >= B.total_seeds) return;
+    const int g = g0 + lane;
+    const int e0 = uniform(upper_bound_i32(B.seed_prefix, B.n_events + 1, g0) - 1);
+    if (g0 + kWave <= load_global(B.seed_prefix + e0 + 1)) {
+        CEvent &E = event_desc(B.events, e0);
+        const size_t t0 = (size_t)(g0 - load_global(B.seed_prefix + e0));
+        const int nl = P.n_layers;
+        float *sp = reinterpret_cast<float *>(s_dyn + (threadIdx.x >> 6) * fit_lds_words(nl));   // [64][6]
+        float *sc = sp + 6 * kWave;                                                            // [64][21]
+        int *sh = reinterpret_cast<int *>(sc + 21 * kWave);                                    // [64][nl]
+        const int *gh = E.out_hits + t0 * nl;
+        for (int k = 0; k < nl; ++k) sh[k * kWave + lane] = load_global(gh + k * kWave + lane);
+        wave_lds_sync();
+        const int *hits = sh + nl * lane;
+        int h3[3];
+#pragma unroll
+        for (int L = 0; L < 3; ++L) h3[L] = hits[L];
+        float p[6], c[21], op[6], oc[21], chi2 = 0.f;
+        int nupd = 0, status = 3;
+        if (final_fit_prior<geo_disk(kGeo)>(E, P, h3, p, c))
+            fit_track<kGeo>(P, E, p, c, [&](int L) { return hits[L]; }, op, oc, chi2, nupd, status);
+        else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) op[i] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 21; ++i) oc[i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sp[6 * lane + i] = op[i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) sc[21 * lane + i] = oc[i];
+        wave_lds_sync();
+        double *fp = E.rf_par + 6 * t0, *fc = E.rf_cov + 21 * t0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) store_global(fp + k * kWave + lane, (double)sp[k * kWave + lane]);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) store_global(fc + k * kWave + lane, (double)sc[k * kWave + lane]);
+        store_global(E.rf_chi2 + t0 + lane, (double)chi2);
+        store_global(E.rf_nupd + t0 + lane, nupd);
+        store_global(E.rf_status + t0 + lane, status);
+        return;
+    }
     if (g >= B.total_seeds) return;
     const int e_lane = upper_bound_i32(B.seed_prefix, B.n_events + 1, g) - 1;
     // one pass per event the wave's lanes cover, as in k_fit
@@ -2037,13 +2083,14 @@ hipError_t launch_refit(const Params &p, const BatchArgs &b, hipStream_t s)
 {
     if (b.total_seeds <= 0) return hipSuccess;
     const unsigned grid = blocks_for(b.total_seeds, 256);
+    const size_t lds = 4 * sizeof(int) * (size_t)fit_lds_words(p.n_layers);
     switch (p.geo | (p.update3d ? 4 : 0)) {
-    case 0: k_refit<0><<<grid, 256, 0, s>>>(p, b); break;
-    case 1: k_refit<1><<<grid, 256, 0, s>>>(p, b); break;
-    case 2: k_refit<2><<<grid, 256, 0, s>>>(p, b); break;
-    case 3: k_refit<3><<<grid, 256, 0, s>>>(p, b); break;
-    case 6: k_refit<6><<<grid, 256, 0, s>>>(p, b); break;
-    case 7: k_refit<7><<<grid, 256, 0, s>>>(p, b); break;
+    case 0: k_refit<0><<<grid, 256, lds, s>>>(p, b); break;
+    case 1: k_refit<1><<<grid, 256, lds, s>>>(p, b); break;
+    case 2: k_refit<2><<<grid, 256, lds, s>>>(p, b); break;
+    case 3: k_refit<3><<<grid, 256, lds, s>>>(p, b); break;
+    case 6: k_refit<6><<<grid, 256, lds, s>>>(p, b); break;
+    case 7: k_refit<7><<<grid, 256, lds, s>>>(p, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
