@@ -18,7 +18,7 @@ from paper_1702_06359_amd import abi, synth
 
 n_ev = int(sys.argv[1]) if len(sys.argv) > 1 else 3
 n_sample = int(sys.argv[2]) if len(sys.argv) > 2 else 2000
-out_path = sys.argv[3] if len(sys.argv) > 3 else "gpurun_out/chi2err.npz"
+out_path = sys.argv[3] if len(sys.argv) > 3 else "chi2err.npz"
 g = synth.Geometry()
 rows_c2, rows_d, rows_tot, rows_dtot, rows_L = [], [], [], [], []
 gaps_g, gaps_o = [], []
