@@ -412,6 +412,8 @@ def workload_ckf(args):
         "plain_builder_tracks_per_s": None if plain_rate is None else round(plain_rate, 1),
     }
     if not args.quick:
+        log("two batch slots in flight")
+        result["two_slots"] = two_slots_leg(args, ctx, handles, evs, sync)
         log("host-inclusive step")
         result["host_inclusive"] = host_inclusive(ctx, evs)
         log("endcap workload")
@@ -489,6 +491,37 @@ def fitted_vs_built(ctx, ev, h):
         dd = wrap(fitted["par"][good, i] - built["par"][good, i], i) / sig
         out["diff_over_built_sigma_rms"][k] = round(float(np.sqrt(np.mean(dd ** 2))), 4)
     return out
+
+
+def two_slots_leg(args, ctx, handles, evs, sync, steps=200):
+    """The headline step with two batches in flight: a second context on a
+    stream of its own holds another copy of the ten events, and the steps
+    alternate between the two, so that one batch's index and build overlap
+    the other's (as a serving pipeline runs consecutive batches).  Reported
+    beside `value`, which keeps one stream."""
+    import torch
+    from paper_1702_06359_amd import abi
+    s2 = torch.cuda.Stream()
+    with torch.cuda.stream(s2):
+        ctx2 = make_ctx(6, args.tuning)
+        handles2 = [ctx2.load_event(e) for e in evs]
+    flags = abi.BATCH_REINDEX | abi.BATCH_ASYNC
+    slots = [(ctx, handles), (ctx2, handles2)]
+    k = [0]
+
+    def step():
+        c, h = slots[k[0] & 1]
+        k[0] += 1
+        c.build_batch(h, None, flags=flags)
+
+    def sync2():
+        ctx2.sync()
+        sync()
+    elapsed = time_steps(step, steps, 0, sync2)
+    ctx2.close()
+    tracks = sum(e.n_seeds for e in evs)
+    return {"step": "index + batched build of ten events, two batches (two contexts, two streams) in flight",
+            "tracks_per_s": round(tracks * steps / elapsed, 1), "ms_per_step": round(elapsed / steps * 1e3, 4)}
 
 
 def host_inclusive(ctx, evs, reps=3):
