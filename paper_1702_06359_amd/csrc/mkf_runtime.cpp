@@ -1161,18 +1161,6 @@ mkf_status mkf_load_events(mkf_ctx *ctx, const mkf_event *evs, int32_t n, int32_
         ctx->load_pin_bytes = off[n];
     }
     char *pin = static_cast<char *>(ctx->load_pin);
-    std::vector<mkf_status> sts(n, MKF_OK);
-    std::vector<std::string> why(n);
-    const int threads = pack_threads(values);
-    if (n == 1) {
-        sts[0] = pack_event(&evs[0], shapes[0], ctx->params.geo, pin, threads, &why[0]);
-    } else {
-        run_tasks(n, threads,
-                  [&](int i) { sts[i] = pack_event(&evs[i], shapes[i], ctx->params.geo, pin + off[i], 1, &why[i]); });
-    }
-    for (int i = 0; i < n; ++i)
-        if (sts[i] != MKF_OK) return n == 1 ? fail(sts[i], "%s", why[i].c_str())
-                                            : fail(sts[i], "event %d: %s", i, why[i].c_str());
     std::vector<std::unique_ptr<EventRec>> recs(n);
     auto undo = [&](mkf_status st) {
         (void)hipStreamSynchronize(ctx->stream);
@@ -1182,12 +1170,35 @@ mkf_status mkf_load_events(mkf_ctx *ctx, const mkf_event *evs, int32_t n, int32_
     };
     hipStream_t s = ctx->stream;
     mkf_status st;
+    // device memory first (the allocator may call back into the caller, so
+    // on this thread); then every event is packed and its copy queued as soon
+    // as its packing ends, so that the copies overlap the packing of the
+    // others
+    for (int i = 0; i < n; ++i)
+        if ((st = create_event(ctx, shapes[i], &ctx->heap, &recs[i])) != MKF_OK) return undo(st);
+    std::vector<mkf_status> sts(n, MKF_OK);
+    std::vector<std::string> why(n);
+    std::vector<hipError_t> copied(n, hipSuccess);
+    auto pack_send = [&](int i, int th) {
+        sts[i] = pack_event(&evs[i], shapes[i], ctx->params.geo, pin + off[i], th, &why[i]);
+        const size_t bytes = event_input_bytes(shapes[i]);
+        if (sts[i] == MKF_OK && bytes)
+            copied[i] = hipMemcpyAsync(recs[i]->data, pin + off[i], bytes, hipMemcpyHostToDevice, s);
+    };
+    const int threads = pack_threads(values);
+    if (n == 1) pack_send(0, threads);
+    else run_tasks(n, threads, [&](int i) { pack_send(i, 1); });
+    for (int i = 0; i < n; ++i)
+        if (sts[i] != MKF_OK) return undo(n == 1 ? fail(sts[i], "%s", why[i].c_str())
+                                                 : fail(sts[i], "event %d: %s", i, why[i].c_str()));
+    for (int i = 0; i < n; ++i)
+        if (copied[i] != hipSuccess) {
+            note_device_error(copied[i]);
+            return undo(fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(copied[i])));
+        }
     for (int i = 0; i < n; ++i) {
         bool rebuilt = false;
-        if ((st = create_event(ctx, shapes[i], &ctx->heap, &recs[i])) != MKF_OK ||
-            (st = upload_packed(recs[i].get(), pin + off[i], s)) != MKF_OK ||
-            (st = ensure_index(ctx, recs[i].get(), &rebuilt, s)) != MKF_OK)
-            return undo(st);
+        if ((st = ensure_index(ctx, recs[i].get(), &rebuilt, s)) != MKF_OK) return undo(st);
         const hipError_t e = hipMemcpyAsync(recs[i]->dev_view, &recs[i]->view, sizeof(DevEvent),
                                             hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return undo(fail(MKF_E_DEVICE, "load: %s", hipGetErrorString(e)));
